@@ -1,0 +1,257 @@
+/*
+ * st.h -- C ABI of the synchronized blobtree tracer for MI355X (gfx950).
+ *
+ * The library ray-casts a blobtree (a binary tree whose leaves are primitives
+ * and whose inner nodes are CSG operators) and writes a G-buffer of hit depth
+ * and unit normal per pixel: for each pixel ray r(t) it finds the first t with
+ * f(r(t)) = 0 (the iso-surface problem statement of "Implicit volume
+ * visualization", Section 2.2 of Zanni 2023, "Synchronized-tracing of implicit
+ * surfaces"), with deferred shading left to the caller (Section "GPU runtime
+ * statistics").  The pipeline is the paper's: a per-screen-tile A-buffer of
+ * primitive volumes of interest (Section 6), then per-tile synchronized sphere
+ * tracing of subfrustums with a bottom-up pruned tree (Sections 7 and 8,
+ * Algorithms 2 and 3).
+ *
+ * Conventions for every call:
+ *  - All functions return st_status; no C++ exception crosses the ABI.  On
+ *    failure, st_last_error() returns a thread-local message.
+ *  - "device" pointers are HIP device allocations on the current device;
+ *    "host" pointers are ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it; calls are asynchronous unless stated otherwise.
+ *  - Handles are not thread safe: one thread at a time per st_scene.
+ */
+#ifndef ST_H
+#define ST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ST_OK = 0,
+    ST_E_INVALID = 1,   /* bad argument: NULL, NaN/inf parameter, bad camera or tuning */
+    ST_E_TREE = 2,      /* malformed blobtree */
+    ST_E_CAPACITY = 3,  /* a fixed capacity of the library was exceeded */
+    ST_E_NOMEM = 4,     /* device or host allocation failed */
+    ST_E_DEVICE = 5,    /* a HIP call failed; st_last_error() has HIP's message */
+    ST_E_STALE = 6      /* the A-buffer was built for another camera/scene version */
+} st_status;
+
+/* Node kinds.  Primitives are exact signed distances (Lipschitz 1), as the
+ * paper requires of primitives that get volumes of interest (Section 6.1).
+ * Operators: sharp CSG min / max / max(f0,-f1) (Section 2.1) and the compact
+ * smooth operators of Section 5 (the piecewise operator G_op built on the
+ * polynomial blends g, with the blend radius interpolated by b_r). */
+enum {
+    ST_SPHERE = 0,   /* p[0..2] centre, p[3] radius > 0 */
+    ST_BOX = 1,      /* p[0..2] centre, p[3..5] half extents > 0,
+                        p[6..9] rotation quaternion (w,x,y,z), non-zero; the
+                        box axes are the columns of its rotation matrix */
+    ST_CAPSULE = 2,  /* p[0..2] a, p[3..5] b, p[6] radius > 0 */
+    ST_UNION = 16,   /* sharp union, no parameters */
+    ST_INTER = 17,   /* sharp intersection */
+    ST_DIFF = 18,    /* sharp difference left \ right */
+    ST_SUNION = 19,  /* compact smooth union: p[0] blend radius k > 0,
+                        p[1] operator range d_o (<= 0: d_o = 7k/6) */
+    ST_SINTER = 20,  /* compact smooth intersection, same parameters */
+    ST_SDIFF = 21    /* compact smooth difference, same parameters */
+};
+
+/* One blobtree node as the caller describes it (any node order). */
+typedef struct {
+    uint32_t kind;
+    int32_t left, right;   /* child indices into the caller's array; -1 for primitives */
+    float p[16];           /* parameters, layout per kind above */
+} st_node;
+
+/* Pinhole camera.  Pixel (i, j) -- column i, row j, row 0 at the top -- has
+ * the ray through its centre: x = (2(i+1/2)/W - 1) tan(fov/2) W/H,
+ * y = (1 - 2(j+1/2)/H) tan(fov/2), dir = normalize(x right + y up + fwd),
+ * fwd = normalize(target - eye), right = normalize(fwd x up_hint),
+ * up = right x fwd.  t is the distance along the unit direction. */
+typedef struct {
+    float eye[3], target[3], up[3];
+    float vfov_deg;        /* in (0, 180) */
+    int32_t width, height; /* > 0 */
+} st_camera;
+
+enum { ST_STEP_PLAIN = 0, ST_STEP_OVERRELAX = 1, ST_STEP_LEARNED = 2 };
+
+/* Tuning of the A-buffer build and the tracer.  st_default_tuning() fills the
+ * paper's defaults where it gives one (Section 10, Implementation details). */
+typedef struct {
+    int32_t tile;          /* A-buffer tile edge in pixels: 8, 16 or 32 */
+    int32_t max_active;    /* per-wave capacity of active primitives held on
+                              chip (the paper's M_overlap, 96); tiles whose
+                              volumes of interest overlap more at some depth
+                              run on a wider-capacity path, never fail */
+    float sub_depth;       /* fetch-ahead depth d as a fraction of the scene's
+                              view-depth span (paper: 1/20) */
+    int32_t max_new;       /* new primitives fetched per subfrustum (paper: 6) */
+    float eps;             /* minimum step and probing step, scene units */
+    int32_t max_steps;     /* field evaluations per ray for stepping */
+    int32_t refine_iters;  /* bracket refinement iterations after a crossing */
+    int32_t step_mode;     /* ST_STEP_* */
+    float omega;           /* over-relaxation factor for ST_STEP_OVERRELAX (paper: 1.7) */
+    float lipschitz;       /* 0: proven bound of each pruned view; > 0: this
+                              fixed global bound (paper: 1.45, not proven) */
+    int32_t reserved[6];
+} st_tuning;
+
+/* Counters of one st_trace call (all 64-bit). */
+typedef struct {
+    uint64_t rays, hits, unconverged;
+    uint64_t field_evals;     /* evaluations of the pruned field at one point:
+                                 steps, probes, refinements, learned-step
+                                 checks; a value+gradient evaluation counts 1 */
+    uint64_t grad_evals;      /* value+gradient evaluations (normals) */
+    uint64_t node_evals[4];   /* by node class: sphere, box, capsule, operator */
+    uint64_t grad_node_evals[4];
+    uint64_t steps;           /* stepping evaluations (no refinement/gradient) */
+    uint64_t subfrustums;     /* (wave, subfrustum) pairs processed */
+    uint64_t empty_views;     /* subfrustums whose pruned root is unused (no surface) */
+    uint64_t view_nodes;      /* sum of pruned-view sizes over subfrustums */
+    uint64_t abuffer_entries; /* A-buffer entries of the scene */
+    uint64_t max_list;        /* longest tile list */
+    uint64_t max_overlap;     /* largest depth overlap of volumes of interest in a tile */
+    uint64_t max_active;      /* largest active set used by the tracer */
+    uint64_t wide_tiles;      /* tiles traced on the wide-capacity path */
+    uint64_t learned_accepted, learned_rejected;
+    uint64_t reserved[8];
+} st_stats;
+
+/* Device memory allocator used for the scene's buffers (e.g. a framework's
+ * caching allocator).  NULL allocator = hipMalloc / hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} st_allocator;
+
+typedef struct st_scene st_scene;
+
+/* Summary of a flattened scene (host struct). */
+typedef struct {
+    int32_t n_nodes, n_prims, depth;
+    float extent;          /* largest edge of the primitives' bounding box */
+    float lipschitz;       /* proven Lipschitz bound of the whole tree */
+    float voi_lo[3], voi_hi[3];  /* bounding box of all volumes of interest */
+    uint64_t device_bytes; /* device memory held by the scene (without A-buffer) */
+    uint64_t abuffer_bytes;
+} st_scene_info;
+
+const char *st_status_str(st_status s);
+const char *st_last_error(void);
+
+/* Fill *t with the default tuning. */
+st_status st_default_tuning(st_tuning *t);
+
+/*
+ * st_flatten_blobtree -- preprocessing of a blobtree (Section 4 storage and
+ * Section 5 range-of-interest propagation; the paper runs it on the CPU only
+ * when the tree structure changes).
+ *   nodes[n] (host): the tree, root index `root`; n = 2P-1 for P primitives.
+ *   alloc: allocator for the scene's device buffers (NULL: hipMalloc).
+ *   stream: stream for the upload and the volume-of-interest kernel.
+ *   *out: new scene handle, owned by the caller, freed by st_scene_destroy.
+ * Work: validation, post-order relabelling, node bitfields, ranges of
+ * interest (root (-inf,0]; a compact operator gives its children
+ * max(d_o, d_parent), a sharp one d_parent), per-node Lipschitz factors,
+ * pruning tables, then one host-to-device copy and a device pass computing
+ * every primitive's volume of interest.
+ * Errors: ST_E_TREE (not a binary tree over all n nodes, cycles, unknown
+ * kind, depth > 31), ST_E_INVALID (NULL pointers, NaN/inf, radius/extent/k
+ * <= 0, zero quaternion, 6 d_o - k <= 0), ST_E_NOMEM, ST_E_DEVICE.
+ */
+st_status st_flatten_blobtree(const st_node *nodes, int32_t n, int32_t root,
+                              const st_allocator *alloc, void *stream, st_scene **out);
+
+void st_scene_destroy(st_scene *s);
+
+st_status st_scene_get_info(const st_scene *s, st_scene_info *info);
+
+/*
+ * st_build_abuffer -- per-tile A-buffer of volumes of interest (Section 6.2):
+ * for every screen tile, the list of primitives whose volume of interest meets
+ * a pixel-centre ray of the tile, with the tile's entry/exit view depth
+ * (minimum entry, maximum exit over its rays), sorted by entry depth (ties by
+ * primitive).  Built on the device by project -> count -> scan -> scatter ->
+ * per-tile sort; synchronizes `stream` once to size the A-buffer.
+ *   cam (host), t (host, NULL = defaults).  The A-buffer is kept in the scene
+ *   and tagged with the camera and tuning; st_trace refuses a different one.
+ * Errors: ST_E_INVALID (camera size <= 0, fov outside (0,180), degenerate
+ * basis, tile not 8/16/32), ST_E_NOMEM, ST_E_DEVICE.
+ */
+st_status st_build_abuffer(st_scene *s, const st_camera *cam, const st_tuning *t, void *stream);
+
+/*
+ * st_trace -- synchronized tracing (Algorithm 2): one wavefront per 8x8 pixel
+ * block walks its tile's A-buffer list, segments the frustum into subfrustums
+ * with a fixed active primitive set, builds the pruned tree of that set, and
+ * sphere-traces every ray's span in it (Algorithm 3 evaluation).
+ *   out_depth (device, float[H*W], row-major, row 0 top): t of the first
+ *     surface crossing along the unit ray, +INFINITY on a miss;
+ *   out_normal (device, float[H*W*3]): unit outward grad f/|grad f| at the
+ *     hit, 0 on a miss;
+ *   out_stats (host, may be NULL): counters; non-NULL makes the call
+ *     synchronize `stream`.
+ * Errors: ST_E_STALE (no A-buffer, or built for another camera), ST_E_INVALID,
+ * ST_E_DEVICE.  Overlaps beyond max_active never fail (wide path).
+ */
+st_status st_trace(st_scene *s, const st_camera *cam, float *out_depth, float *out_normal,
+                   st_stats *out_stats, void *stream);
+
+/*
+ * st_debug_eval_field -- test hook: evaluates the pruned field f_A of a given
+ * active primitive set at points (pruning semantics of Sections 7-9).  The
+ * view is built by the same device code the tracer uses.
+ *   active (host, caller's node indices of primitives, any order, no
+ *     duplicates) or NULL for all primitives; n_active entries.
+ *   pts (device, float[n_pts*3]); out_f (device, float[n_pts]);
+ *   out_grad (device, float[n_pts*3], may be NULL).
+ *   *out_root_used (host, may be NULL): 0 when the pruned root is unused
+ *     (f_A is then +INFINITY everywhere: no surface in the volume).
+ *   out_view (host, int32[view_cap], may be NULL): the device-built view as
+ *     caller node indices in evaluation order; *out_view_len its length.
+ * Synchronous.  Errors: ST_E_INVALID (bad index, duplicate, non-primitive),
+ * ST_E_CAPACITY (active set beyond the library's largest view, 1024, or
+ * view_cap too small), ST_E_DEVICE.
+ */
+st_status st_debug_eval_field(const st_scene *s, const int32_t *active, int32_t n_active,
+                              const float *pts, int32_t n_pts, float *out_f, float *out_grad,
+                              int32_t *out_root_used, int32_t *out_view, int32_t view_cap,
+                              int32_t *out_view_len, void *stream);
+
+/*
+ * st_debug_prune_tree -- test hook, host only (no device needed): flattens
+ * nodes[n] (same rules as st_flatten_blobtree) and builds the pruned tree view
+ * of the active primitives with the same code the device runs after its LCA
+ * step.  Writes the view in evaluation (post) order as caller node indices to
+ * out_nodes[cap] and its length to *out_len (0 when the root is unused);
+ * *out_lip gets the view's Lipschitz bound (may be NULL).
+ * Errors: those of st_flatten_blobtree, ST_E_INVALID (bad active index),
+ * ST_E_CAPACITY (cap too small).
+ */
+st_status st_debug_prune_tree(const st_node *nodes, int32_t n, int32_t root, const int32_t *active,
+                              int32_t n_active, int32_t *out_nodes, int32_t cap, int32_t *out_len,
+                              float *out_lip);
+
+/*
+ * st_debug_abuffer -- test hook: copies the current A-buffer to host memory.
+ *   tile_off (host, uint32[n_tiles+1]), entries (host, 3 x uint32 per entry:
+ *   caller node index of the primitive, z_in bits, z_out bits), capacities in
+ *   elements; *n_tiles and *n_entries receive the sizes.  Pass NULL arrays to
+ *   query sizes.  Synchronous.
+ */
+st_status st_debug_abuffer(const st_scene *s, uint32_t *tile_off, size_t tile_cap,
+                           uint32_t *entries, size_t entry_cap, int32_t *n_tiles,
+                           int64_t *n_entries, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ST_H */

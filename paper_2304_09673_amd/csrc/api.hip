@@ -1,0 +1,434 @@
+// C ABI entry points (include/st.h): argument checking, device memory,
+// camera set-up, and the calls into the host preprocessing, the A-buffer
+// build and the tracer.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "st_internal.h"
+
+namespace st {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+st_status device_error(hipError_t e, const char* where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return ST_E_DEVICE;
+}
+
+void* dev_alloc(st_scene* s, size_t bytes, hipStream_t stream) {
+    if (bytes == 0) bytes = 256;
+    if (s->has_alloc) return s->alloc.alloc(bytes, (void*)stream, s->alloc.ctx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(st_scene* s, void* p, hipStream_t stream) {
+    if (!p) return;
+    if (s->has_alloc) { s->alloc.free(p, (void*)stream, s->alloc.ctx); return; }
+    (void)hipFree(p);
+}
+
+static void free_abuffer(st_scene* s, hipStream_t stream) {
+    dev_free(s, s->d_tile_off, stream); s->d_tile_off = nullptr;
+    dev_free(s, s->d_tile_ovl, stream); s->d_tile_ovl = nullptr;
+    dev_free(s, s->d_e_node, stream); s->d_e_node = nullptr;
+    dev_free(s, s->d_e_zin, stream); s->d_e_zin = nullptr;
+    dev_free(s, s->d_e_zout, stream); s->d_e_zout = nullptr;
+    dev_free(s, s->d_wide, stream); s->d_wide = nullptr;
+    dev_free(s, s->d_scratch, stream); s->d_scratch = nullptr;
+    s->scratch_bytes = 0;
+    s->ab_cap = 0;
+    s->n_tiles = 0;
+    s->ab_valid = false;
+}
+
+static bool make_devcam(const st_camera& c, DevCam& d) {
+    double fwd[3], up[3], right[3];
+    for (int j = 0; j < 3; j++) {
+        if (!std::isfinite(c.eye[j]) || !std::isfinite(c.target[j]) || !std::isfinite(c.up[j])) return false;
+        fwd[j] = double(c.target[j]) - c.eye[j];
+    }
+    double fn = std::sqrt(fwd[0] * fwd[0] + fwd[1] * fwd[1] + fwd[2] * fwd[2]);
+    if (!(fn > 0)) return false;
+    for (int j = 0; j < 3; j++) fwd[j] /= fn;
+    right[0] = fwd[1] * c.up[2] - fwd[2] * c.up[1];
+    right[1] = fwd[2] * c.up[0] - fwd[0] * c.up[2];
+    right[2] = fwd[0] * c.up[1] - fwd[1] * c.up[0];
+    double rn = std::sqrt(right[0] * right[0] + right[1] * right[1] + right[2] * right[2]);
+    if (!(rn > 1e-12)) return false;
+    for (int j = 0; j < 3; j++) right[j] /= rn;
+    up[0] = right[1] * fwd[2] - right[2] * fwd[1];
+    up[1] = right[2] * fwd[0] - right[0] * fwd[2];
+    up[2] = right[0] * fwd[1] - right[1] * fwd[0];
+    double th = std::tan(0.5 * double(c.vfov_deg) * M_PI / 180.0);
+    for (int j = 0; j < 3; j++) {
+        d.eye[j] = c.eye[j];
+        d.fwd[j] = float(fwd[j]);
+        d.right[j] = float(right[j]);
+        d.up[j] = float(up[j]);
+    }
+    d.tx = float(th * double(c.width) / double(c.height));
+    d.ty = float(th);
+    d.inv_w2 = float(2.0 / c.width);
+    d.inv_h2 = float(2.0 / c.height);
+    d.w = c.width;
+    d.h = c.height;
+    return true;
+}
+
+static st_status check_tuning(const st_tuning& t) {
+    if (t.tile != 8 && t.tile != 16 && t.tile != 32) { set_error("tuning: tile must be 8, 16 or 32"); return ST_E_INVALID; }
+    if (t.max_active < 2) { set_error("tuning: max_active < 2"); return ST_E_INVALID; }
+    if (!(t.sub_depth > 0.f) || !std::isfinite(t.sub_depth)) { set_error("tuning: sub_depth must be > 0"); return ST_E_INVALID; }
+    if (t.max_new < 1) { set_error("tuning: max_new < 1"); return ST_E_INVALID; }
+    if (!(t.eps > 0.f) || !std::isfinite(t.eps)) { set_error("tuning: eps must be > 0"); return ST_E_INVALID; }
+    if (t.max_steps < 1 || t.refine_iters < 0 || t.refine_iters > 64) { set_error("tuning: step limits"); return ST_E_INVALID; }
+    if (t.step_mode < ST_STEP_PLAIN || t.step_mode > ST_STEP_LEARNED) { set_error("tuning: step_mode"); return ST_E_INVALID; }
+    if (!(t.omega >= 1.f) || !(t.omega <= 4.f)) { set_error("tuning: omega outside [1, 4]"); return ST_E_INVALID; }
+    if (!(t.lipschitz >= 0.f) || !std::isfinite(t.lipschitz)) { set_error("tuning: lipschitz < 0"); return ST_E_INVALID; }
+    return ST_OK;
+}
+
+}  // namespace st
+
+using namespace st;
+
+extern "C" {
+
+const char* st_status_str(st_status s) {
+    switch (s) {
+    case ST_OK: return "ok";
+    case ST_E_INVALID: return "invalid argument";
+    case ST_E_TREE: return "malformed blobtree";
+    case ST_E_CAPACITY: return "capacity exceeded";
+    case ST_E_NOMEM: return "out of memory";
+    case ST_E_DEVICE: return "device error";
+    case ST_E_STALE: return "stale A-buffer";
+    }
+    return "unknown status";
+}
+
+const char* st_last_error(void) { return g_err.c_str(); }
+
+st_status st_default_tuning(st_tuning* t) {
+    if (!t) { set_error("NULL tuning"); return ST_E_INVALID; }
+    std::memset(t, 0, sizeof(*t));
+    t->tile = 16;
+    t->max_active = 128;
+    t->sub_depth = 1.0f / 20.0f;
+    t->max_new = 6;
+    t->eps = 1e-4f;
+    t->max_steps = 128;
+    t->refine_iters = 8;
+    t->step_mode = ST_STEP_PLAIN;
+    t->omega = 1.7f;
+    t->lipschitz = 0.f;
+    return ST_OK;
+}
+
+st_status st_flatten_blobtree(const st_node* nodes, int32_t n, int32_t root, const st_allocator* alloc,
+                              void* stream_v, st_scene** out) {
+    if (!out) { set_error("flatten: NULL out"); return ST_E_INVALID; }
+    *out = nullptr;
+    hipStream_t stream = (hipStream_t)stream_v;
+    st_scene* s = new (std::nothrow) st_scene();
+    if (!s) { set_error("flatten: host allocation failed"); return ST_E_NOMEM; }
+    if (alloc) {
+        if (!alloc->alloc || !alloc->free) { delete s; set_error("flatten: allocator without alloc/free"); return ST_E_INVALID; }
+        s->alloc = *alloc;
+        s->has_alloc = true;
+    }
+    st_status r;
+    try {
+        r = flatten_host(nodes, n, root, s);
+    } catch (const std::bad_alloc&) {
+        r = ST_E_NOMEM;
+        set_error("flatten: host allocation failed");
+    }
+    if (r != ST_OK) { delete s; return r; }
+    size_t N = size_t(s->n_nodes), P = size_t(s->n_prims);
+    struct { void** p; size_t bytes; const void* src; } bufs[] = {
+        {(void**)&s->d_blob, N * 4, s->h_blob.data()},
+        {(void**)&s->d_kill, N * 4, s->h_kill.data()},
+        {(void**)&s->d_rmq, s->h_rmq.size() * 4, s->h_rmq.data()},
+        {(void**)&s->d_prims, P * 4, s->h_prims.data()},
+        {(void**)&s->d_par, N * sizeof(NodePar), s->h_par.data()},
+        {(void**)&s->d_roi, N * 4, s->h_roi.data()},
+        {(void**)&s->d_voi, P * sizeof(Voi), nullptr},
+        {(void**)&s->d_stats, kStatCount * 8, nullptr},
+        {(void**)&s->d_misc, 64 * 4, nullptr},
+    };
+    for (auto& b : bufs) {
+        *b.p = dev_alloc(s, b.bytes, stream);
+        if (!*b.p) { st_scene_destroy(s); set_error("flatten: device allocation failed"); return ST_E_NOMEM; }
+        s->device_bytes += b.bytes;
+        if (b.src) {
+            hipError_t e = hipMemcpyAsync(*b.p, b.src, b.bytes, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) { st_scene_destroy(s); return device_error(e, "flatten upload"); }
+        }
+    }
+    r = launch_voi(s, stream);
+    if (r != ST_OK) { st_scene_destroy(s); return r; }
+    hipError_t e = hipStreamSynchronize(stream);   // host arrays stay owned by the scene; keep the copy simple
+    if (e != hipSuccess) { st_scene_destroy(s); return device_error(e, "flatten sync"); }
+    *out = s;
+    return ST_OK;
+}
+
+void st_scene_destroy(st_scene* s) {
+    if (!s) return;
+    hipStream_t stream = nullptr;
+    free_abuffer(s, stream);
+    dev_free(s, s->d_blob, stream);
+    dev_free(s, s->d_kill, stream);
+    dev_free(s, s->d_rmq, stream);
+    dev_free(s, s->d_prims, stream);
+    dev_free(s, s->d_par, stream);
+    dev_free(s, s->d_roi, stream);
+    dev_free(s, s->d_voi, stream);
+    dev_free(s, s->d_stats, stream);
+    dev_free(s, s->d_misc, stream);
+    dev_free(s, s->d_mlp, stream);
+    delete s;
+}
+
+st_status st_scene_get_info(const st_scene* s, st_scene_info* info) {
+    if (!s || !info) { set_error("info: NULL argument"); return ST_E_INVALID; }
+    info->n_nodes = s->n_nodes;
+    info->n_prims = s->n_prims;
+    info->depth = s->depth;
+    info->extent = s->extent;
+    info->lipschitz = s->lipschitz;
+    for (int j = 0; j < 3; j++) { info->voi_lo[j] = s->voi_lo[j]; info->voi_hi[j] = s->voi_hi[j]; }
+    info->device_bytes = s->device_bytes;
+    info->abuffer_bytes = uint64_t(s->ab_cap) * 12 + uint64_t(s->n_tiles + 1) * 8;
+    return ST_OK;
+}
+
+st_status st_build_abuffer(st_scene* s, const st_camera* cam, const st_tuning* tin, void* stream_v) {
+    if (!s || !cam) { set_error("build: NULL argument"); return ST_E_INVALID; }
+    hipStream_t stream = (hipStream_t)stream_v;
+    st_tuning t;
+    if (tin) t = *tin; else st_default_tuning(&t);
+    st_status r = check_tuning(t);
+    if (r != ST_OK) return r;
+    if (cam->width <= 0 || cam->height <= 0 || !(cam->vfov_deg > 0.f) || !(cam->vfov_deg < 180.f)) {
+        set_error("build: camera size <= 0 or field of view outside (0, 180)");
+        return ST_E_INVALID;
+    }
+    if (int64_t(cam->width) * cam->height > (int64_t(1) << 30)) { set_error("build: image too large"); return ST_E_CAPACITY; }
+    DevCam dc;
+    if (!make_devcam(*cam, dc)) { set_error("build: degenerate camera basis"); return ST_E_INVALID; }
+    int tx = (cam->width + t.tile - 1) / t.tile, ty = (cam->height + t.tile - 1) / t.tile;
+    int T = tx * ty;
+    if (T != s->n_tiles || !s->d_tile_off) {
+        dev_free(s, s->d_tile_off, stream);
+        dev_free(s, s->d_tile_ovl, stream);
+        s->d_tile_off = (uint32_t*)dev_alloc(s, size_t(T + 1) * 4, stream);
+        s->d_tile_ovl = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
+        if (!s->d_wide) s->d_wide = nullptr;
+        if (!s->d_tile_off || !s->d_tile_ovl) { set_error("build: tile arrays allocation failed"); return ST_E_NOMEM; }
+    }
+    dev_free(s, s->d_wide, stream);
+    s->d_wide = (uint32_t*)dev_alloc(s, size_t(T + 1) * 4, stream);
+    if (!s->d_wide) { set_error("build: wide list allocation failed"); return ST_E_NOMEM; }
+    s->dcam = dc;
+    s->tiles_x = tx;
+    s->tiles_y = ty;
+    s->n_tiles = T;
+    // view-depth span of the box of all volumes of interest
+    double zmin = INFINITY, zmax = -INFINITY;
+    for (int c = 0; c < 8; c++) {
+        double p[3] = {(c & 1) ? s->voi_hi[0] : s->voi_lo[0], (c & 2) ? s->voi_hi[1] : s->voi_lo[1],
+                       (c & 4) ? s->voi_hi[2] : s->voi_lo[2]};
+        double z = 0;
+        for (int j = 0; j < 3; j++) z += (p[j] - cam->eye[j]) * dc.fwd[j];
+        zmin = std::min(zmin, z);
+        zmax = std::max(zmax, z);
+    }
+    s->z_min = float(std::max(zmin, 0.0));
+    s->z_max = float(std::max(zmax, 0.0));
+    s->ab_ma_fast = std::min(t.max_active, 128);
+    s->ab_ma_wide = 1024;
+    s->ab_valid = false;
+    r = build_abuffer_device(s, t, stream);
+    if (r != ST_OK) return r;
+    s->ab_cam = *cam;
+    s->ab_tune = t;
+    s->ab_valid = true;
+    return ST_OK;
+}
+
+st_status st_trace(st_scene* s, const st_camera* cam, float* out_depth, float* out_normal, st_stats* out_stats,
+                   void* stream_v) {
+    if (!s || !cam || !out_depth || !out_normal) { set_error("trace: NULL argument"); return ST_E_INVALID; }
+    hipStream_t stream = (hipStream_t)stream_v;
+    if (!s->ab_valid || std::memcmp(cam, &s->ab_cam, sizeof(st_camera)) != 0) {
+        set_error("trace: the A-buffer was not built for this camera");
+        return ST_E_STALE;
+    }
+    st_status r = trace_device(s, s->ab_tune, out_depth, out_normal, stream);
+    if (r != ST_OK) return r;
+    if (out_stats) {
+        unsigned long long h[kStatCount];
+        hipError_t e = hipMemcpyAsync(h, s->d_stats, sizeof(h), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return device_error(e, "trace stats");
+        std::memset(out_stats, 0, sizeof(*out_stats));
+        out_stats->rays = h[0];
+        out_stats->hits = h[1];
+        out_stats->unconverged = h[2];
+        out_stats->field_evals = h[3];
+        out_stats->grad_evals = h[4];
+        for (int q = 0; q < 4; q++) {
+            out_stats->node_evals[q] = h[5 + q];
+            out_stats->grad_node_evals[q] = h[9 + q];
+        }
+        out_stats->steps = h[13];
+        out_stats->subfrustums = h[14];
+        out_stats->empty_views = h[15];
+        out_stats->view_nodes = h[16];
+        out_stats->max_active = h[17];
+        out_stats->wide_tiles = h[18];
+        out_stats->learned_accepted = h[19];
+        out_stats->learned_rejected = h[20];
+        out_stats->reserved[0] = h[21];   // stalled blocks (must be 0)
+        out_stats->reserved[1] = h[22];   // compact operators evaluated on their smooth branch
+        out_stats->abuffer_entries = uint64_t(s->n_entries);
+        out_stats->max_list = s->max_list;
+        out_stats->max_overlap = s->max_overlap;
+    }
+    return ST_OK;
+}
+
+static st_status active_to_post(const st_scene* s, const int32_t* active, int32_t n_active,
+                                std::vector<uint32_t>& post) {
+    post.clear();
+    if (!active) {
+        post.assign(s->h_prims.begin(), s->h_prims.end());
+        return ST_OK;
+    }
+    if (n_active < 0) { set_error("n_active < 0"); return ST_E_INVALID; }
+    for (int i = 0; i < n_active; i++) {
+        int32_t c = active[i];
+        if (c < 0 || c >= s->n_nodes) { set_error("active index out of range"); return ST_E_INVALID; }
+        int32_t p = s->post_of_caller[size_t(c)];
+        if (!blob_prim(s->h_blob[size_t(p)])) { set_error("active node is not a primitive"); return ST_E_INVALID; }
+        post.push_back(uint32_t(p));
+    }
+    std::sort(post.begin(), post.end());
+    if (std::adjacent_find(post.begin(), post.end()) != post.end()) { set_error("duplicate active primitive"); return ST_E_INVALID; }
+    return ST_OK;
+}
+
+st_status st_debug_prune_tree(const st_node* nodes, int32_t n, int32_t root, const int32_t* active,
+                              int32_t n_active, int32_t* out_nodes, int32_t cap, int32_t* out_len, float* out_lip) {
+    if (!out_len) { set_error("prune: NULL out_len"); return ST_E_INVALID; }
+    st_scene s;
+    st_status r;
+    try {
+        r = flatten_host(nodes, n, root, &s);
+        if (r != ST_OK) return r;
+        std::vector<uint32_t> post, view;
+        r = active_to_post(&s, active, n_active, post);
+        if (r != ST_OK) return r;
+        PruneResult pr = host_prune(&s, post, view);
+        *out_len = pr.len;
+        if (out_lip) *out_lip = pr.lip;
+        if (pr.len > 0) {
+            if (!out_nodes || cap < pr.len) { set_error("prune: output capacity too small"); return ST_E_CAPACITY; }
+            for (int i = 0; i < pr.len; i++) out_nodes[i] = s.caller_of_post[ventry_node(view[size_t(i)])];
+        }
+    } catch (const std::bad_alloc&) {
+        set_error("prune: host allocation failed");
+        return ST_E_NOMEM;
+    }
+    return ST_OK;
+}
+
+st_status st_debug_eval_field(const st_scene* s, const int32_t* active, int32_t n_active, const float* pts,
+                              int32_t n_pts, float* out_f, float* out_grad, int32_t* out_root_used,
+                              int32_t* out_view, int32_t view_cap, int32_t* out_view_len, void* stream_v) {
+    if (!s || (n_pts > 0 && (!pts || !out_f)) || n_pts < 0) { set_error("eval: NULL argument"); return ST_E_INVALID; }
+    hipStream_t stream = (hipStream_t)stream_v;
+    std::vector<uint32_t> post;
+    st_status r = active_to_post(s, active, n_active, post);
+    if (r != ST_OK) return r;
+    int n = int(post.size());
+    if (n > 1024) { set_error("eval: active set larger than the largest view"); return ST_E_CAPACITY; }
+    // device buffer: sorted active list + [used, len, lip, pad] + view copy
+    size_t bytes = size_t(n) * 4 + 256 + 16 + 2048 * 4 + 256;
+    st_scene* sm = const_cast<st_scene*>(s);
+    char* buf = (char*)dev_alloc(sm, bytes, stream);
+    if (!buf) { set_error("eval: allocation failed"); return ST_E_NOMEM; }
+    uint32_t* d_act = (uint32_t*)buf;
+    int* d_ru = (int*)(buf + ((size_t(n) * 4 + 255) & ~size_t(255)));
+    hipError_t e = hipSuccess;
+    if (n > 0) e = hipMemcpyAsync(d_act, post.data(), size_t(n) * 4, hipMemcpyHostToDevice, stream);
+    int hdr[4] = {0, 0, 0, 0};
+    std::vector<uint32_t> hview(2048, 0u);
+    if (e == hipSuccess && n > 0) {
+        r = debug_eval_device(s, d_act, n, pts, n_pts, out_f, out_grad, d_ru, stream);
+        if (r != ST_OK) { dev_free(sm, buf, stream); return r; }
+        e = hipMemcpyAsync(hdr, d_ru, 16, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(hview.data(), d_ru + 4, 2048 * 4, hipMemcpyDeviceToHost, stream);
+    } else if (e == hipSuccess && n_pts > 0) {
+        // empty active set: the pruned root is unused, f_A = +inf
+        std::vector<float> inf(size_t(n_pts), INFINITY);
+        e = hipMemcpyAsync(out_f, inf.data(), size_t(n_pts) * 4, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && out_grad) e = hipMemsetAsync(out_grad, 0, size_t(n_pts) * 12, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    dev_free(sm, buf, stream);
+    if (e != hipSuccess) return device_error(e, "eval");
+    if (out_root_used) *out_root_used = hdr[0];
+    int vlen = hdr[0] ? hdr[1] : 0;
+    if (out_view_len) *out_view_len = vlen;
+    if (out_view) {
+        if (view_cap < vlen) { set_error("eval: view capacity too small"); return ST_E_CAPACITY; }
+        for (int i = 0; i < vlen; i++) out_view[i] = s->caller_of_post[ventry_node(hview[size_t(i)])];
+    }
+    return ST_OK;
+}
+
+st_status st_debug_abuffer(const st_scene* s, uint32_t* tile_off, size_t tile_cap, uint32_t* entries,
+                           size_t entry_cap, int32_t* n_tiles, int64_t* n_entries, void* stream_v) {
+    if (!s) { set_error("abuffer: NULL scene"); return ST_E_INVALID; }
+    if (!s->ab_valid) { set_error("abuffer: not built"); return ST_E_STALE; }
+    hipStream_t stream = (hipStream_t)stream_v;
+    if (n_tiles) *n_tiles = s->n_tiles;
+    if (n_entries) *n_entries = s->n_entries;
+    hipError_t e = hipSuccess;
+    if (tile_off) {
+        if (tile_cap < size_t(s->n_tiles + 1)) { set_error("abuffer: tile capacity"); return ST_E_CAPACITY; }
+        e = hipMemcpyAsync(tile_off, s->d_tile_off, size_t(s->n_tiles + 1) * 4, hipMemcpyDeviceToHost, stream);
+    }
+    if (entries && e == hipSuccess) {
+        size_t E = size_t(s->n_entries);
+        if (entry_cap < 3 * E) { set_error("abuffer: entry capacity"); return ST_E_CAPACITY; }
+        std::vector<uint32_t> a(E), b(E), c(E);
+        if (E) {
+            e = hipMemcpyAsync(a.data(), s->d_e_node, E * 4, hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(b.data(), s->d_e_zin, E * 4, hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(c.data(), s->d_e_zout, E * 4, hipMemcpyDeviceToHost, stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        for (size_t i = 0; i < E && e == hipSuccess; i++) {
+            entries[3 * i] = uint32_t(s->caller_of_post[a[i]]);
+            entries[3 * i + 1] = b[i];
+            entries[3 * i + 2] = c[i];
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error(e, "abuffer copy");
+    return ST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,617 @@
+// Tile A-buffer of volumes of interest (Section 6 of Zanni 2023).
+//
+// The paper rasterises every volume of interest at tile resolution: a
+// geometry shader emits an impostor, its fragment shader intersects the
+// tile's 8x8 rays with the volume, keeps the minimum entry and maximum exit
+// depth, and inserts {primitive, z_in, z_out} into the tile's linked list kept
+// sorted by entry depth (Section 6.2).  Here the same per-tile lists are built
+// with data-parallel kernels and no list atomics:
+//   voi      : per primitive, the volume of interest (bound offset by the
+//              range of interest) and a bounding sphere;
+//   rect     : per primitive, the conservative screen rectangle of tiles its
+//              bounding sphere can touch (exact tangent planes of a sphere);
+//   scan     : candidate (primitive, tile) pairs are numbered by prefix sum;
+//   test     : per candidate, the tile's pixel-centre rays are intersected
+//              with the volume; min entry / max exit view depth are kept and
+//              the tile's count incremented when some ray hits;
+//   scan     : tile offsets (CSR);
+//   scatter  : entries written to their tile's segment;
+//   sort     : per tile, entries sorted by (z_in, primitive) in LDS (bitonic),
+//              and the tile's largest depth overlap of intervals computed.
+#include <algorithm>
+
+#include "st_internal.h"
+
+namespace st {
+
+// ---------------------------------------------------------------------------
+// volumes of interest
+__global__ void voi_kernel(const uint32_t* __restrict__ prims, int P, const NodePar* __restrict__ par,
+                           const float* __restrict__ roi, const uint32_t* __restrict__ blob,
+                           Voi* __restrict__ out) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    uint32_t node = prims[p];
+    const float* q = par[node].v;
+    float d = roi[node];
+    uint32_t kind = blob_op(blob[node]);
+    Voi v;
+    for (int j = 0; j < 24; j++) v.v[j] = 0.f;
+    if (kind == ST_SPHERE) {
+        float R = q[3] + d;
+        v.v[0] = q[0]; v.v[1] = q[1]; v.v[2] = q[2]; v.v[3] = R;
+        v.v[4] = q[0]; v.v[5] = q[1]; v.v[6] = q[2]; v.v[7] = R;
+    } else if (kind == ST_BOX) {
+        float e0 = q[7] + d, e1 = q[11] + d, e2 = q[15] + d;
+        v.v[0] = q[0]; v.v[1] = q[1]; v.v[2] = q[2];
+        v.v[3] = sqrtf(e0 * e0 + e1 * e1 + e2 * e2) * 1.0001f;
+        v.v[4] = q[0]; v.v[5] = q[1]; v.v[6] = q[2];
+        for (int a = 0; a < 3; a++) {
+            for (int c = 0; c < 3; c++) v.v[8 + 4 * a + c] = q[4 + 4 * a + c];
+        }
+        v.v[11] = e0; v.v[15] = e1; v.v[19] = e2;
+    } else {
+        float R = q[3] + d;
+        float bx = q[0] + q[4], by = q[1] + q[5], bz = q[2] + q[6];
+        float hl = 0.5f * sqrtf(q[4] * q[4] + q[5] * q[5] + q[6] * q[6]);
+        v.v[0] = 0.5f * (q[0] + bx); v.v[1] = 0.5f * (q[1] + by); v.v[2] = 0.5f * (q[2] + bz);
+        v.v[3] = (hl + R) * 1.0001f;
+        v.v[4] = q[0]; v.v[5] = q[1]; v.v[6] = q[2]; v.v[7] = R;
+        v.v[8] = bx; v.v[9] = by; v.v[10] = bz;
+    }
+    v.v[20] = float(kind);
+    v.v[21] = __uint_as_float(node);
+    out[p] = v;
+}
+
+// ---------------------------------------------------------------------------
+// ray / volume-of-interest interval along the unit ray (t), false on a miss
+__device__ __forceinline__ bool ray_sphere(const float o[3], const float d[3], float cx, float cy, float cz,
+                                           float R, float& t0, float& t1) {
+    float ox = o[0] - cx, oy = o[1] - cy, oz = o[2] - cz;
+    float b = ox * d[0] + oy * d[1] + oz * d[2];
+    // distance of the centre to the ray, computed without cancellation
+    float qx = ox - b * d[0], qy = oy - b * d[1], qz = oz - b * d[2];
+    float disc = R * R - (qx * qx + qy * qy + qz * qz);
+    if (disc < 0.f) return false;
+    float s = sqrtf(disc);
+    t0 = -b - s;
+    t1 = -b + s;
+    return true;
+}
+
+__device__ __forceinline__ bool ray_voi(const Voi& v, const float o[3], const float d[3], float& t0, float& t1) {
+    int kind = int(v.v[20]);
+    if (kind == ST_SPHERE) return ray_sphere(o, d, v.v[4], v.v[5], v.v[6], v.v[7], t0, t1);
+    if (kind == ST_BOX) {
+        float rx = o[0] - v.v[4], ry = o[1] - v.v[5], rz = o[2] - v.v[6];
+        float lo = -__builtin_inff(), hi = __builtin_inff();
+        for (int a = 0; a < 3; a++) {
+            const float* ax = v.v + 8 + 4 * a;
+            float ol = ax[0] * rx + ax[1] * ry + ax[2] * rz;
+            float dl = ax[0] * d[0] + ax[1] * d[1] + ax[2] * d[2];
+            float e = ax[3];
+            if (fabsf(dl) < 1e-20f) {
+                if (fabsf(ol) > e) return false;
+                continue;
+            }
+            float inv = 1.0f / dl;
+            float u = (-e - ol) * inv, w = (e - ol) * inv;
+            lo = fmaxf(lo, fminf(u, w));
+            hi = fminf(hi, fmaxf(u, w));
+        }
+        if (lo > hi) return false;
+        t0 = lo; t1 = hi;
+        return true;
+    }
+    // capsule: end spheres and the cylinder between the end planes
+    float R = v.v[7];
+    float ax = v.v[4], ay = v.v[5], az = v.v[6], bx = v.v[8], by = v.v[9], bz = v.v[10];
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+    float u, w;
+    if (ray_sphere(o, d, ax, ay, az, R, u, w)) { lo = fminf(lo, u); hi = fmaxf(hi, w); }
+    if (ray_sphere(o, d, bx, by, bz, R, u, w)) { lo = fminf(lo, u); hi = fmaxf(hi, w); }
+    float ex = bx - ax, ey = by - ay, ez = bz - az;
+    float len = sqrtf(ex * ex + ey * ey + ez * ez);
+    if (len > 0.f) {
+        float il = 1.0f / len;
+        ex *= il; ey *= il; ez *= il;
+        float oax = o[0] - ax, oay = o[1] - ay, oaz = o[2] - az;
+        float de = d[0] * ex + d[1] * ey + d[2] * ez;
+        float oe = oax * ex + oay * ey + oaz * ez;
+        float dpx = d[0] - de * ex, dpy = d[1] - de * ey, dpz = d[2] - de * ez;
+        float opx = oax - oe * ex, opy = oay - oe * ey, opz = oaz - oe * ez;
+        float qa = dpx * dpx + dpy * dpy + dpz * dpz;
+        float qb = opx * dpx + opy * dpy + opz * dpz;
+        float qc = opx * opx + opy * opy + opz * opz - R * R;
+        if (qa > 1e-20f) {
+            // distance of closest approach to the axis line, cancellation free
+            float tc = -qb / qa;
+            float cx = opx + tc * dpx, cy = opy + tc * dpy, cz = opz + tc * dpz;
+            float disc = (R * R - (cx * cx + cy * cy + cz * cz)) / qa;
+            if (disc >= 0.f) {
+                float sq = sqrtf(disc);
+                float c0 = tc - sq, c1 = tc + sq;
+                float s0, s1;
+                if (fabsf(de) > 1e-20f) {
+                    float ide = 1.0f / de;
+                    s0 = -oe * ide; s1 = (len - oe) * ide;
+                    if (s0 > s1) { float tmp = s0; s0 = s1; s1 = tmp; }
+                } else {
+                    if (oe < 0.f || oe > len) { s0 = 1.f; s1 = 0.f; } else { s0 = -__builtin_inff(); s1 = __builtin_inff(); }
+                }
+                float x0 = fmaxf(c0, s0), x1 = fminf(c1, s1);
+                if (x0 <= x1) { lo = fminf(lo, x0); hi = fmaxf(hi, x1); }
+            }
+        } else if (qc <= 0.f) {
+            float s0, s1;
+            if (fabsf(de) > 1e-20f) {
+                float ide = 1.0f / de;
+                s0 = -oe * ide; s1 = (len - oe) * ide;
+                if (s0 > s1) { float tmp = s0; s0 = s1; s1 = tmp; }
+                lo = fminf(lo, s0); hi = fmaxf(hi, s1);
+            }
+        }
+    }
+    if (!(lo <= hi)) return false;
+    t0 = lo; t1 = hi;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// screen rectangle of tiles touched by a bounding sphere
+__device__ __forceinline__ void slope_range(float c, float z, float r, float& lo, float& hi) {
+    // tangent lines through the eye to the circle (c, z) of radius r: slope c/z
+    float den = z * z - r * r;
+    float sq = r * sqrtf(fmaxf(c * c + den, 0.f));
+    lo = (c * z - sq) / den;
+    hi = (c * z + sq) / den;
+}
+
+__global__ void rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int ts, int tiles_x, int tiles_y,
+                            int4* __restrict__ rect, uint32_t* __restrict__ count) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const Voi& v = voi[p];
+    float rx = v.v[0] - cam.eye[0], ry = v.v[1] - cam.eye[1], rz = v.v[2] - cam.eye[2];
+    float cx = rx * cam.right[0] + ry * cam.right[1] + rz * cam.right[2];
+    float cy = rx * cam.up[0] + ry * cam.up[1] + rz * cam.up[2];
+    float cz = rx * cam.fwd[0] + ry * cam.fwd[1] + rz * cam.fwd[2];
+    float r = v.v[3] * 1.001f + 1e-5f;
+    int i0 = 0, i1 = cam.w - 1, j0 = 0, j1 = cam.h - 1;
+    if (cz + r <= 0.f) {  // entirely behind the eye
+        rect[p] = make_int4(0, 0, -1, -1);
+        count[p] = 0;
+        return;
+    }
+    if (cz > r * 1.01f + 1e-4f) {
+        float xl, xh, yl, yh;
+        slope_range(cx, cz, r, xl, xh);
+        slope_range(cy, cz, r, yl, yh);
+        // pixel centre coordinate u = i + 1/2 = (x/tx + 1) W/2;  v = j + 1/2 = (1 - y/ty) H/2
+        float ul = (xl / cam.tx + 1.f) * 0.5f * cam.w, uh = (xh / cam.tx + 1.f) * 0.5f * cam.w;
+        float vl = (1.f - yh / cam.ty) * 0.5f * cam.h, vh = (1.f - yl / cam.ty) * 0.5f * cam.h;
+        i0 = max(i0, int(floorf(ul - 0.5f)) - 1);
+        i1 = min(i1, int(ceilf(uh - 0.5f)) + 1);
+        j0 = max(j0, int(floorf(vl - 0.5f)) - 1);
+        j1 = min(j1, int(ceilf(vh - 0.5f)) + 1);
+    }
+    if (i0 > i1 || j0 > j1) {
+        rect[p] = make_int4(0, 0, -1, -1);
+        count[p] = 0;
+        return;
+    }
+    int tx0 = i0 / ts, tx1 = i1 / ts, ty0 = j0 / ts, ty1 = j1 / ts;
+    rect[p] = make_int4(tx0, ty0, tx1, ty1);
+    count[p] = uint32_t((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+}
+
+// ---------------------------------------------------------------------------
+// exclusive prefix sum of u32 (three passes, 1024-element blocks)
+constexpr int kScanBlock = 1024;
+
+__global__ void scan_block_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int n,
+                                  uint32_t* __restrict__ block_sums) {
+    __shared__ uint32_t sh[kScanBlock];
+    int base = blockIdx.x * kScanBlock;
+    int i = base + threadIdx.x;
+    uint32_t x = i < n ? in[i] : 0u;
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        uint32_t y = threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sh[threadIdx.x] += y;
+        __syncthreads();
+    }
+    if (i < n) out[i] = sh[threadIdx.x] - x;
+    if (threadIdx.x == kScanBlock - 1) block_sums[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ void scan_sums_kernel(uint32_t* __restrict__ sums, int nb, uint32_t* __restrict__ total) {
+    // single block, sequential chunks of 1024
+    __shared__ uint32_t sh[kScanBlock];
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kScanBlock) {
+        int i = base + threadIdx.x;
+        uint32_t x = i < nb ? sums[i] : 0u;
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int off = 1; off < kScanBlock; off <<= 1) {
+            uint32_t y = threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < nb) sums[i] = carry + sh[threadIdx.x] - x;
+        uint32_t blk = sh[kScanBlock - 1];
+        __syncthreads();
+        carry += blk;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void scan_add_kernel(uint32_t* __restrict__ out, int n, const uint32_t* __restrict__ sums,
+                                const uint32_t* __restrict__ total, uint32_t* __restrict__ out_total_slot) {
+    int i = blockIdx.x * kScanBlock + threadIdx.x;
+    if (i < n) out[i] += sums[blockIdx.x];
+    if (i == 0 && out_total_slot) *out_total_slot = *total;
+}
+
+// out[0..n) = exclusive scan of in, *total = sum; if out_total_slot, also
+// writes the total there (CSR end offset).  scratch: >= ceil(n/1024)+1 u32.
+static void exclusive_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* scratch, uint32_t* total,
+                           uint32_t* out_total_slot, hipStream_t stream) {
+    int nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(kScanBlock), 0, stream, in, out, n, scratch);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, stream, scratch, nb, total);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(kScanBlock), 0, stream, out, n, scratch, total,
+                       out_total_slot);
+}
+
+// ---------------------------------------------------------------------------
+// candidate (primitive, tile) test against the tile's pixel-centre rays
+__global__ void test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
+                            const uint32_t* __restrict__ cand_off, int P, uint32_t n_cand, DevCam cam, int ts,
+                            int tiles_x, float2* __restrict__ cz, uint32_t* __restrict__ ctile,
+                            uint32_t* __restrict__ tile_count) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cand) return;
+    // primitive owning candidate c: last p with cand_off[p] <= c
+    int lo = 0, hi = P - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cand_off[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    int p = lo;
+    int4 rc = rect[p];
+    uint32_t l = c - cand_off[p];
+    int w = rc.z - rc.x + 1;
+    int tx = rc.x + int(l % uint32_t(w)), ty = rc.y + int(l / uint32_t(w));
+    const Voi v = voi[p];
+    float zmin = __builtin_inff(), zmax = -__builtin_inff();
+    int i0 = tx * ts, j0 = ty * ts;
+    int i1 = min(i0 + ts, cam.w), j1 = min(j0 + ts, cam.h);
+    for (int j = j0; j < j1; j++) {
+        for (int i = i0; i < i1; i++) {
+            Ray r = pixel_ray(cam, i, j);
+            float t0, t1;
+            if (ray_voi(v, r.o, r.d, t0, t1) && t1 >= 0.f) {
+                t0 = fmaxf(t0, 0.f);
+                zmin = fminf(zmin, t0 * r.cosv);
+                zmax = fmaxf(zmax, t1 * r.cosv);
+            }
+        }
+    }
+    uint32_t tile = uint32_t(ty * tiles_x + tx);
+    if (zmin <= zmax) {
+        // conservative padding for FP32 rounding of the intervals
+        float pad = 2e-5f * fmaxf(fabsf(zmax), 1.0f);
+        cz[c] = make_float2(fmaxf(zmin - pad, 0.f), zmax + pad);
+        ctile[c] = tile;
+        atomicAdd(tile_count + tile, 1u);
+    } else {
+        ctile[c] = 0xFFFFFFFFu;
+    }
+}
+
+__global__ void scatter_kernel(const Voi* __restrict__ voi, const uint32_t* __restrict__ cand_off, int P,
+                               uint32_t n_cand, const float2* __restrict__ cz, const uint32_t* __restrict__ ctile,
+                               const uint32_t* __restrict__ tile_off, uint32_t* __restrict__ cursor,
+                               uint32_t* __restrict__ e_node, float* __restrict__ e_zin,
+                               float* __restrict__ e_zout) {
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cand) return;
+    uint32_t tile = ctile[c];
+    if (tile == 0xFFFFFFFFu) return;
+    int lo = 0, hi = P - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cand_off[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    uint32_t pos = tile_off[tile] + atomicAdd(cursor + tile, 1u);
+    float2 z = cz[c];
+    e_node[pos] = __float_as_uint(voi[lo].v[21]);
+    e_zin[pos] = z.x;
+    e_zout[pos] = z.y;
+}
+
+// ---------------------------------------------------------------------------
+// per-tile sort by (z_in, node) and largest depth overlap
+__device__ __forceinline__ uint32_t f2key(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+constexpr int kSortThreads = 512;
+
+// Bitonic sort of keys[0..np2) (u64) with a u32 payload, in place, by the
+// whole workgroup.  Works on LDS or on global memory (the latter with the
+// workgroup-scope fences that the barrier carries).
+template <class K, class V>
+__device__ void bitonic_wg(K* keys, V* vals, int np2) {
+    for (int k = 2; k <= np2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    bool up = (i & k) == 0;
+                    K a = keys[i], b = keys[ixj];
+                    if ((a > b) == up) {
+                        keys[i] = b; keys[ixj] = a;
+                        if (vals) { V t = vals[i]; vals[i] = vals[ixj]; vals[ixj] = t; }
+                    }
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+}
+
+template <class K>
+__device__ int upper_bound_keys(const K* a, int n, K x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (a[m] <= x) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+// Sorts one tile's segment [e0, e1) given staging arrays (LDS or global),
+// then computes the largest number of closed intervals sharing a point.
+__device__ void sort_segment(uint64_t* keys, uint32_t* vals, uint32_t* zo_keys, uint32_t e0, uint32_t e1,
+                             uint32_t* e_node, float* e_zin, float* e_zout, uint32_t* ovl_out) {
+    int n = int(e1 - e0);
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+        if (i < n) {
+            keys[i] = (uint64_t(f2key(e_zin[e0 + i])) << 32) | e_node[e0 + i];
+            vals[i] = __float_as_uint(e_zout[e0 + i]);
+        } else {
+            keys[i] = ~0ull;
+            vals[i] = 0u;
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    bitonic_wg(keys, vals, np2);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        uint64_t k = keys[i];
+        e_node[e0 + i] = uint32_t(k & 0xFFFFFFFFu);
+        uint32_t zb = uint32_t(k >> 32);
+        e_zin[e0 + i] = __uint_as_float((zb & 0x80000000u) ? (zb & 0x7FFFFFFFu) : ~zb);
+        e_zout[e0 + i] = __uint_as_float(vals[i]);
+    }
+    __threadfence_block();
+    __syncthreads();
+    // exit depths sorted separately: overlap at z_in(i) = #(z_in <= z_in(i)) - #(z_out < z_in(i))
+    for (int i = threadIdx.x; i < np2; i += blockDim.x) zo_keys[i] = i < n ? f2key(e_zout[e0 + i]) : 0xFFFFFFFFu;
+    __threadfence_block();
+    __syncthreads();
+    bitonic_wg(zo_keys, (uint32_t*)nullptr, np2);
+    uint32_t best = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        uint32_t zb = f2key(e_zin[e0 + i]);
+        // #(z_in <= zb): keys sorted by z_in first
+        uint64_t probe = (uint64_t(zb) << 32) | 0xFFFFFFFFull;
+        int a = upper_bound_keys(keys, n, probe);
+        // #(z_out < zb)
+        int lo = 0, hi = n;
+        while (lo < hi) {
+            int m = (lo + hi) >> 1;
+            if (zo_keys[m] < zb) lo = m + 1; else hi = m;
+        }
+        uint32_t ov = uint32_t(a - lo);
+        best = best > ov ? best : ov;
+    }
+    // workgroup max
+    __shared__ uint32_t red;
+    if (threadIdx.x == 0) red = 0;
+    __syncthreads();
+    atomicMax(&red, best);
+    __syncthreads();
+    if (threadIdx.x == 0) *ovl_out = red;
+}
+
+constexpr int kSortLdsCap = 4096;
+
+__global__ void __launch_bounds__(kSortThreads) tile_sort_kernel(
+        const uint32_t* __restrict__ tile_off, int n_tiles, uint32_t* e_node, float* e_zin, float* e_zout,
+        uint32_t* __restrict__ tile_ovl, uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
+        uint32_t ma_fast, uint32_t* __restrict__ wide) {
+    __shared__ uint64_t keys[kSortLdsCap];
+    __shared__ uint32_t vals[kSortLdsCap];
+    __shared__ uint32_t zo[kSortLdsCap];
+    int tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    uint32_t e0 = tile_off[tile], e1 = tile_off[tile + 1];
+    uint32_t n = e1 - e0;
+    if (n > kSortLdsCap) {
+        if (threadIdx.x == 0) long_list[atomicAdd(misc + 0, 1u)] = uint32_t(tile);
+        return;
+    }
+    if (n == 0) {
+        if (threadIdx.x == 0) tile_ovl[tile] = 0;
+        return;
+    }
+    __shared__ uint32_t ov;
+    sort_segment(keys, vals, zo, e0, e1, e_node, e_zin, e_zout, &ov);
+    if (threadIdx.x == 0) {
+        tile_ovl[tile] = ov;
+        atomicMax(misc + 1, ov);
+        atomicMax(misc + 2, n);
+        if (ov > ma_fast) wide[1 + atomicAdd(wide, 1u)] = uint32_t(tile);
+    }
+}
+
+// long lists: bitonic sort in global scratch (one workgroup per long tile)
+__global__ void __launch_bounds__(kSortThreads) tile_sort_long_kernel(
+        const uint32_t* __restrict__ tile_off, uint32_t* e_node, float* e_zin, float* e_zout,
+        uint32_t* __restrict__ tile_ovl, const uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
+        uint64_t* scratch_keys, uint32_t* scratch_vals, uint32_t* scratch_zo, uint32_t ma_fast,
+        uint32_t* __restrict__ wide) {
+    uint32_t n_long = misc[0];
+    __shared__ uint32_t ov;
+    for (uint32_t idx = blockIdx.x; idx < n_long; idx += gridDim.x) {
+        uint32_t tile = long_list[idx];
+        uint32_t e0 = tile_off[tile], e1 = tile_off[tile + 1];
+        // scratch segment: entries of this tile padded to a power of two fit
+        // in [2*e0, 2*e0 + 2n) since np2 < 2n
+        uint64_t* k = scratch_keys + 2 * size_t(e0);
+        uint32_t* v = scratch_vals + 2 * size_t(e0);
+        uint32_t* z = scratch_zo + 2 * size_t(e0);
+        sort_segment(k, v, z, e0, e1, e_node, e_zin, e_zout, &ov);
+        if (threadIdx.x == 0) {
+            tile_ovl[tile] = ov;
+            atomicMax(misc + 1, ov);
+            atomicMax(misc + 2, e1 - e0);
+            if (ov > ma_fast) wide[1 + atomicAdd(wide, 1u)] = tile;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+st_status launch_voi(st_scene* s, hipStream_t stream) {
+    int P = s->n_prims;
+    hipLaunchKernelGGL(voi_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_prims, P, s->d_par,
+                       s->d_roi, s->d_blob, s->d_voi);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ST_OK : device_error(e, "voi_kernel");
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stream) {
+    const int P = s->n_prims;
+    const int T = s->n_tiles;
+    const int ts = t.tile;
+    // scratch layout (bytes): rect P*16, count P*4, cand_off (P+1)*4, scan sums, tile_count T*4,
+    // cursor T*4, long list T*4, misc 16*4
+    size_t nb_p = size_t(P + kScanBlock) / kScanBlock + 2, nb_t = size_t(T + kScanBlock) / kScanBlock + 2;
+    size_t off_rect = 0;
+    size_t off_count = align_up(off_rect + size_t(P) * 16);
+    size_t off_coff = align_up(off_count + size_t(P) * 4);
+    size_t off_sums = align_up(off_coff + size_t(P + 1) * 4);
+    size_t off_tcnt = align_up(off_sums + std::max(nb_p, nb_t) * 4 + 16);
+    size_t off_cur = align_up(off_tcnt + size_t(T + 1) * 4);
+    size_t off_long = align_up(off_cur + size_t(T) * 4);
+    size_t off_misc = align_up(off_long + size_t(T) * 4);
+    size_t need = align_up(off_misc + 64 * 4);
+    if (need > s->scratch_bytes) {
+        if (s->d_scratch) dev_free(s, s->d_scratch, stream);
+        s->d_scratch = dev_alloc(s, need, stream);
+        if (!s->d_scratch) { s->scratch_bytes = 0; set_error("build: scratch allocation failed"); return ST_E_NOMEM; }
+        s->scratch_bytes = need;
+    }
+    char* base = (char*)s->d_scratch;
+    int4* rect = (int4*)(base + off_rect);
+    uint32_t* count = (uint32_t*)(base + off_count);
+    uint32_t* coff = (uint32_t*)(base + off_coff);
+    uint32_t* sums = (uint32_t*)(base + off_sums);
+    uint32_t* tcnt = (uint32_t*)(base + off_tcnt);
+    uint32_t* cur = (uint32_t*)(base + off_cur);
+    uint32_t* longl = (uint32_t*)(base + off_long);
+    uint32_t* misc = (uint32_t*)(base + off_misc);
+    hipError_t e;
+#define ST_CHECK(x, what) do { e = (x); if (e != hipSuccess) return device_error(e, what); } while (0)
+
+    hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
+                       s->tiles_x, s->tiles_y, rect, count);
+    exclusive_scan(count, coff, P, sums, misc + 8, coff + P, stream);
+    uint32_t n_cand = 0;
+    ST_CHECK(hipMemcpyAsync(&n_cand, misc + 8, 4, hipMemcpyDeviceToHost, stream), "copy candidate count");
+    ST_CHECK(hipStreamSynchronize(stream), "sync (candidates)");
+
+    // candidate results: z pair + tile id
+    size_t cand_bytes = align_up(size_t(n_cand) * 8) + align_up(size_t(n_cand) * 4) + 256;
+    char* cbuf = (char*)dev_alloc(s, cand_bytes, stream);
+    if (!cbuf && cand_bytes) { set_error("build: candidate buffer allocation failed"); return ST_E_NOMEM; }
+    float2* cz = (float2*)cbuf;
+    uint32_t* ctile = (uint32_t*)(cbuf + align_up(size_t(n_cand) * 8));
+
+    ST_CHECK(hipMemsetAsync(tcnt, 0, size_t(T + 1) * 4, stream), "memset tile counts");
+    ST_CHECK(hipMemsetAsync(misc, 0, 64 * 4, stream), "memset misc");
+    if (n_cand)
+        hipLaunchKernelGGL(test_kernel, dim3((n_cand + 255) / 256), dim3(256), 0, stream, s->d_voi, rect, coff, P,
+                           n_cand, s->dcam, ts, s->tiles_x, cz, ctile, tcnt);
+    exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
+    uint32_t n_ent = 0;
+    ST_CHECK(hipMemcpyAsync(&n_ent, misc + 9, 4, hipMemcpyDeviceToHost, stream), "copy entry count");
+    ST_CHECK(hipStreamSynchronize(stream), "sync (entries)");
+    s->n_entries = n_ent;
+
+    // entry arrays (grown on demand) + long-sort scratch
+    if (int64_t(n_ent) > s->ab_cap) {
+        dev_free(s, s->d_e_node, stream);
+        dev_free(s, s->d_e_zin, stream);
+        dev_free(s, s->d_e_zout, stream);
+        int64_t cap = std::max<int64_t>(int64_t(n_ent) + int64_t(n_ent) / 4, 1024);
+        s->d_e_node = (uint32_t*)dev_alloc(s, size_t(cap) * 4, stream);
+        s->d_e_zin = (float*)dev_alloc(s, size_t(cap) * 4, stream);
+        s->d_e_zout = (float*)dev_alloc(s, size_t(cap) * 4, stream);
+        if (!s->d_e_node || !s->d_e_zin || !s->d_e_zout) {
+            dev_free(s, cbuf, stream);
+            set_error("build: A-buffer allocation failed");
+            s->ab_cap = 0;
+            return ST_E_NOMEM;
+        }
+        s->ab_cap = cap;
+    }
+    ST_CHECK(hipMemsetAsync(cur, 0, size_t(T) * 4, stream), "memset cursors");
+    if (n_cand)
+        hipLaunchKernelGGL(scatter_kernel, dim3((n_cand + 255) / 256), dim3(256), 0, stream, s->d_voi, coff, P,
+                           n_cand, cz, ctile, s->d_tile_off, cur, s->d_e_node, s->d_e_zin, s->d_e_zout);
+    ST_CHECK(hipMemsetAsync(s->d_wide, 0, 4, stream), "memset wide list");
+    hipLaunchKernelGGL(tile_sort_kernel, dim3(T), dim3(kSortThreads), 0, stream, s->d_tile_off, T, s->d_e_node,
+                       s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, uint32_t(s->ab_ma_fast), s->d_wide);
+    // long tiles, if any (the kernel reads their count on the device)
+    size_t long_bytes = size_t(2) * n_ent * (8 + 4 + 4) + 64;
+    char* lbuf = (char*)dev_alloc(s, long_bytes, stream);
+    if (!lbuf) { dev_free(s, cbuf, stream); set_error("build: sort scratch allocation failed"); return ST_E_NOMEM; }
+    uint64_t* sk = (uint64_t*)lbuf;
+    uint32_t* sv = (uint32_t*)(lbuf + size_t(2) * n_ent * 8);
+    uint32_t* sz = (uint32_t*)(lbuf + size_t(2) * n_ent * 12);
+    hipLaunchKernelGGL(tile_sort_long_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream,
+                       s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, sk, sv, sz,
+                       uint32_t(s->ab_ma_fast), s->d_wide);
+    uint32_t h_misc[4] = {0, 0, 0, 0}, h_wide = 0;
+    ST_CHECK(hipMemcpyAsync(h_misc, misc, 16, hipMemcpyDeviceToHost, stream), "copy build stats");
+    ST_CHECK(hipMemcpyAsync(&h_wide, s->d_wide, 4, hipMemcpyDeviceToHost, stream), "copy wide count");
+    e = hipGetLastError();
+    if (e != hipSuccess) { dev_free(s, cbuf, stream); dev_free(s, lbuf, stream); return device_error(e, "binning kernels"); }
+    ST_CHECK(hipStreamSynchronize(stream), "sync (build)");
+    dev_free(s, cbuf, stream);
+    dev_free(s, lbuf, stream);
+    s->max_overlap = h_misc[1];
+    s->max_list = h_misc[2];
+    s->n_wide = h_wide;
+#undef ST_CHECK
+    return ST_OK;
+}
+
+}  // namespace st

@@ -1,0 +1,328 @@
+// Host preprocessing of a blobtree (the paper's CPU step, run only when the
+// tree structure changes; Sections 4, 5 and 7-9):
+//  - validation and post-order relabelling (the linearised storage of
+//    Section 4 keeps nodes in post-order, so a subtree is a contiguous index
+//    range ending at its root);
+//  - node bitfields with ignoreMod (Section 9) and parent pointers;
+//  - per-node parameter blocks in the device layout;
+//  - ranges of interest propagated from the root (Section 5: the root has
+//    (-inf, 0]; a compact operator hands its children max(d_o, d_parent), a
+//    sharp operator hands them d_parent);
+//  - pruning tables: the nearest "killing" ancestor of every node (an
+//    intersection, or a difference reached from its right operand: the nodes
+//    where the paper cuts fast ancestor pointers) and a sparse table of
+//    (depth, parent) over post-order positions for O(1) LCA queries;
+//  - the tree's proven Lipschitz bound and bounding boxes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "st_internal.h"
+
+namespace st {
+
+namespace {
+
+bool finite_params(const st_node& nd, int count) {
+    for (int i = 0; i < count; i++)
+        if (!std::isfinite(nd.p[i])) return false;
+    return true;
+}
+
+void quat_axes(const float q_in[4], double axes[3][3]) {
+    double w = q_in[0], x = q_in[1], y = q_in[2], z = q_in[3];
+    double n = std::sqrt(w * w + x * x + y * y + z * z);
+    w /= n; x /= n; y /= n; z /= n;
+    // rotation matrix R (row-major); the box axes are its columns
+    double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                      {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                      {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++) axes[a][c] = R[c][a];
+}
+
+}  // namespace
+
+st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* s) {
+    if (!nodes || n <= 0 || root < 0 || root >= n) {
+        set_error("flatten: NULL nodes, n <= 0 or root out of range");
+        return ST_E_INVALID;
+    }
+    if (uint32_t(n) >= kMaxNodes) {
+        set_error("flatten: too many nodes");
+        return ST_E_CAPACITY;
+    }
+    // validate kinds and parameters
+    for (int i = 0; i < n; i++) {
+        const st_node& nd = nodes[i];
+        uint32_t k = nd.kind;
+        if (is_prim_kind(k)) {
+            if (nd.left != -1 || nd.right != -1) {
+                set_error("flatten: primitive " + std::to_string(i) + " has children");
+                return ST_E_TREE;
+            }
+            int cnt = k == ST_SPHERE ? 4 : k == ST_BOX ? 10 : 7;
+            if (!finite_params(nd, cnt)) { set_error("flatten: non-finite primitive parameter"); return ST_E_INVALID; }
+            if (k == ST_SPHERE && !(nd.p[3] > 0)) { set_error("flatten: sphere radius <= 0"); return ST_E_INVALID; }
+            if (k == ST_BOX) {
+                if (!(nd.p[3] > 0 && nd.p[4] > 0 && nd.p[5] > 0)) { set_error("flatten: box extent <= 0"); return ST_E_INVALID; }
+                double qn = 0;
+                for (int j = 6; j < 10; j++) qn += double(nd.p[j]) * nd.p[j];
+                if (!(qn > 1e-20)) { set_error("flatten: zero quaternion"); return ST_E_INVALID; }
+            }
+            if (k == ST_CAPSULE && !(nd.p[6] > 0)) { set_error("flatten: capsule radius <= 0"); return ST_E_INVALID; }
+        } else if (is_op_kind(k)) {
+            if (nd.left < 0 || nd.left >= n || nd.right < 0 || nd.right >= n || nd.left == nd.right) {
+                set_error("flatten: operator " + std::to_string(i) + " has invalid children");
+                return ST_E_TREE;
+            }
+            if (is_compact_kind(k)) {
+                if (!finite_params(nd, 2)) { set_error("flatten: non-finite blend parameter"); return ST_E_INVALID; }
+                double kk = nd.p[0], d = nd.p[1] > 0 ? nd.p[1] : 7.0 * kk / 6.0;
+                if (!(kk > 0)) { set_error("flatten: blend radius k <= 0"); return ST_E_INVALID; }
+                if (!(6.0 * d - kk > 0)) { set_error("flatten: 6 d_o - k <= 0"); return ST_E_INVALID; }
+            }
+        } else {
+            set_error("flatten: unknown node kind " + std::to_string(k));
+            return ST_E_TREE;
+        }
+    }
+
+    // post-order walk from the root; every node must be reached exactly once
+    std::vector<int32_t> order;
+    order.reserve(n);
+    std::vector<int32_t> parent(n, -1), depth(n, 0);
+    std::vector<char> seen(n, 0);
+    std::vector<std::pair<int32_t, int>> stk;
+    stk.reserve(64);
+    stk.push_back({root, 0});
+    seen[root] = 1;
+    int maxd = 0;
+    while (!stk.empty()) {
+        auto& top = stk.back();
+        int32_t v = top.first;
+        const st_node& nd = nodes[v];
+        if (is_prim_kind(nd.kind) || top.second == 2) {
+            order.push_back(v);
+            stk.pop_back();
+            continue;
+        }
+        int32_t c = top.second == 0 ? nd.left : nd.right;
+        top.second++;
+        if (seen[c]) { set_error("flatten: node reached twice (cycle or shared child)"); return ST_E_TREE; }
+        seen[c] = 1;
+        parent[c] = v;
+        depth[c] = depth[v] + 1;
+        maxd = std::max(maxd, depth[c]);
+        if (maxd > kMaxDepth) { set_error("flatten: tree deeper than 31 levels"); return ST_E_TREE; }
+        stk.push_back({c, 0});
+    }
+    if (int32_t(order.size()) != n) { set_error("flatten: not every node is reachable from the root"); return ST_E_TREE; }
+
+    s->n_nodes = n;
+    s->depth = maxd;
+    s->post_of_caller.assign(n, -1);
+    s->caller_of_post.assign(n, -1);
+    for (int p = 0; p < n; p++) {
+        s->caller_of_post[p] = order[p];
+        s->post_of_caller[order[p]] = p;
+    }
+    s->h_blob.assign(n, 0);
+    s->h_kill.assign(n, kNoKill);
+    s->h_par.assign(n, NodePar{});
+    s->h_roi.assign(n, 0.f);
+    s->h_prims.clear();
+
+    std::vector<double> roi(n, 0.0), lip(n, 1.0);
+    // top-down: roi, Lipschitz products, kill pointers (parents come later in post-order)
+    for (int p = n - 1; p >= 0; p--) {
+        int32_t c = order[p];
+        const st_node& nd = nodes[c];
+        int32_t pc = parent[c];
+        uint32_t pp = pc >= 0 ? uint32_t(s->post_of_caller[pc]) : kNoNode;
+        bool is_left = pc >= 0 && nodes[pc].left == c;
+        s->h_blob[p] = blob_pack(is_prim_kind(nd.kind), nd.kind, is_op_kind(nd.kind) ? ignore_of(nd.kind) : 0u,
+                                 is_left, pp);
+        if (pc < 0) {
+            roi[p] = 0.0;
+            lip[p] = 1.0;
+            s->h_kill[p] = kNoKill;
+        } else {
+            const st_node& pn = nodes[pc];
+            double dp = roi[pp], lf = 1.0;
+            if (is_compact_kind(pn.kind)) {
+                double kk = pn.p[0], d = pn.p[1] > 0 ? pn.p[1] : 7.0 * kk / 6.0;
+                dp = std::max(dp, d);
+                lf = 1.0 + kk / (6.0 * d - kk);
+            }
+            roi[p] = dp;
+            lip[p] = lip[pp] * lf;
+            uint32_t im = ignore_of(pn.kind);
+            bool kills = is_left ? (im & 1u) != 0 : (im & 2u) != 0;
+            s->h_kill[p] = kills ? pp : s->h_kill[pp];
+        }
+        s->h_roi[p] = float(roi[p]);
+    }
+
+    // parameters, bounds
+    double ext_lo[3] = {INFINITY, INFINITY, INFINITY}, ext_hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double voi_lo[3] = {INFINITY, INFINITY, INFINITY}, voi_hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double Lmax = 1.0;
+    int nprim = 0;
+    for (int p = 0; p < n; p++) {
+        const st_node& nd = nodes[order[p]];
+        float* q = s->h_par[p].v;
+        double d = roi[p];
+        auto grow = [&](const double lo[3], const double hi[3], double off) {
+            for (int j = 0; j < 3; j++) {
+                ext_lo[j] = std::min(ext_lo[j], lo[j]); ext_hi[j] = std::max(ext_hi[j], hi[j]);
+                voi_lo[j] = std::min(voi_lo[j], lo[j] - off); voi_hi[j] = std::max(voi_hi[j], hi[j] + off);
+            }
+        };
+        switch (nd.kind) {
+        case ST_SPHERE: {
+            for (int j = 0; j < 4; j++) q[j] = nd.p[j];
+            double lo[3], hi[3];
+            for (int j = 0; j < 3; j++) { lo[j] = double(nd.p[j]) - nd.p[3]; hi[j] = double(nd.p[j]) + nd.p[3]; }
+            grow(lo, hi, d);
+            break;
+        }
+        case ST_BOX: {
+            double ax[3][3];
+            quat_axes(nd.p + 6, ax);
+            for (int j = 0; j < 3; j++) q[j] = nd.p[j];
+            for (int a = 0; a < 3; a++) {
+                for (int c = 0; c < 3; c++) q[4 + 4 * a + c] = float(ax[a][c]);
+                q[7 + 4 * a] = nd.p[3 + a];
+            }
+            double lo[3], hi[3];
+            for (int j = 0; j < 3; j++) {
+                double e = 0;
+                for (int a = 0; a < 3; a++) e += std::fabs(ax[a][j]) * nd.p[3 + a];
+                lo[j] = nd.p[j] - e; hi[j] = nd.p[j] + e;
+            }
+            grow(lo, hi, 0.0);
+            // VOI box: offset along the box axes
+            double lo2[3], hi2[3];
+            for (int j = 0; j < 3; j++) {
+                double e = 0;
+                for (int a = 0; a < 3; a++) e += std::fabs(ax[a][j]) * (nd.p[3 + a] + d);
+                lo2[j] = nd.p[j] - e; hi2[j] = nd.p[j] + e;
+                voi_lo[j] = std::min(voi_lo[j], lo2[j]); voi_hi[j] = std::max(voi_hi[j], hi2[j]);
+            }
+            break;
+        }
+        case ST_CAPSULE: {
+            double ba[3], bb = 0;
+            for (int j = 0; j < 3; j++) { q[j] = nd.p[j]; ba[j] = double(nd.p[3 + j]) - nd.p[j]; q[4 + j] = float(ba[j]); bb += ba[j] * ba[j]; }
+            q[3] = nd.p[6];
+            q[7] = bb > 0 ? float(1.0 / bb) : 0.f;
+            double lo[3], hi[3];
+            for (int j = 0; j < 3; j++) {
+                lo[j] = std::min<double>(nd.p[j], nd.p[3 + j]) - nd.p[6];
+                hi[j] = std::max<double>(nd.p[j], nd.p[3 + j]) + nd.p[6];
+            }
+            grow(lo, hi, d);
+            break;
+        }
+        default: {
+            if (is_compact_kind(nd.kind)) {
+                double kk = nd.p[0], dd = nd.p[1] > 0 ? nd.p[1] : 7.0 * kk / 6.0;
+                q[0] = float(kk);
+                q[1] = float(1.0 / kk);
+                q[2] = float(6.0 * kk / (6.0 * dd - kk));
+                q[3] = float(dd);
+                q[4] = float(1.0 + kk / (6.0 * dd - kk));
+                q[5] = float(kk / 6.0);
+            } else {
+                q[4] = 1.f;
+            }
+        }
+        }
+        if (is_prim_kind(nd.kind)) {
+            s->h_prims.push_back(uint32_t(p));
+            nprim++;
+            Lmax = std::max(Lmax, lip[p]);
+        }
+    }
+    s->n_prims = nprim;
+    s->lipschitz = float(Lmax);
+    double e = 0;
+    for (int j = 0; j < 3; j++) {
+        e = std::max(e, ext_hi[j] - ext_lo[j]);
+        s->voi_lo[j] = float(voi_lo[j]);
+        s->voi_hi[j] = float(voi_hi[j]);
+    }
+    s->extent = float(e);
+
+    // sparse table over post-order positions of (depth << 24 | parent)
+    int levels = 1;
+    while ((1 << levels) <= n) levels++;
+    s->rmq_levels = levels;
+    s->h_rmq.assign(size_t(levels) * n, 0xFFFFFFFFu);
+    for (int p = 0; p < n; p++) {
+        int32_t c = order[p];
+        int32_t pc = parent[c];
+        s->h_rmq[p] = pc < 0 ? 0xFFFFFFFFu
+                             : (uint32_t(depth[c]) << 24) | uint32_t(s->post_of_caller[pc]);
+    }
+    for (int k = 1; k < levels; k++) {
+        int half = 1 << (k - 1);
+        for (int x = 0; x + (1 << k) <= n; x++) {
+            uint32_t a = s->h_rmq[size_t(k - 1) * n + x], b = s->h_rmq[size_t(k - 1) * n + x + half];
+            s->h_rmq[size_t(k) * n + x] = std::min(a, b);
+        }
+    }
+    return ST_OK;
+}
+
+namespace {
+
+struct HostCtx {
+    const st_scene* s;
+    const std::vector<uint32_t>* vs;
+    std::vector<uint32_t>* out;
+    uint32_t st_nu[kStack + 2], st_start[kStack + 2], st_kill[kStack + 2];
+    float st_L[kStack + 2];
+    uint32_t node(int j) const { return (*vs)[j]; }
+    uint32_t blob(int j) const { return s->h_blob[(*vs)[j]]; }
+    uint32_t kill(int j) const { return s->h_kill[(*vs)[j]]; }
+    float lipf(int j) const { return s->h_par[(*vs)[j]].v[4]; }
+    void spush(int sp, uint32_t nu, uint32_t start, float L, uint32_t k) {
+        st_nu[sp] = nu; st_start[sp] = start; st_L[sp] = L; st_kill[sp] = k;
+    }
+    void sget(int sp, uint32_t& nu, uint32_t& start, float& L, uint32_t& k) const {
+        nu = st_nu[sp]; start = st_start[sp]; L = st_L[sp]; k = st_kill[sp];
+    }
+    void emit(int pos, uint32_t e) { (*out)[pos] = e; }
+    void move(int dst, int src, int len) {
+        for (int i = 0; i < len; i++) (*out)[dst + i] = (*out)[src + i];
+    }
+};
+
+}  // namespace
+
+// Host version of the tracer's view build: same LCA query, same merge, same
+// bottom-up pass.  active_post: post-order indices of active primitives.
+PruneResult host_prune(const st_scene* s, std::vector<uint32_t> act, std::vector<uint32_t>& view) {
+    PruneResult r{0, 0, 0.f};
+    view.clear();
+    if (act.empty()) return r;
+    std::sort(act.begin(), act.end());
+    std::vector<uint32_t> lcas;
+    for (size_t i = 0; i + 1 < act.size(); i++)
+        lcas.push_back(lca_query(s->h_rmq.data(), uint32_t(s->n_nodes), act[i], act[i + 1]));
+    std::sort(lcas.begin(), lcas.end());
+    std::vector<uint32_t> vs;
+    std::merge(act.begin(), act.end(), lcas.begin(), lcas.end(), std::back_inserter(vs));
+    view.assign(vs.size(), 0u);
+    HostCtx c;
+    c.s = s;
+    c.vs = &vs;
+    c.out = &view;
+    r = prune_pass(c, int(vs.size()));
+    view.resize(size_t(r.len));
+    return r;
+}
+
+}  // namespace st

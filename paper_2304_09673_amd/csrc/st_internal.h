@@ -1,0 +1,90 @@
+// Internal (non-ABI) state of a scene and the kernel launchers shared
+// between the translation units of the library.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "st_common.h"
+#include "st_prune.h"
+
+struct st_scene {
+    // tree, post-order numbering
+    int32_t n_nodes = 0, n_prims = 0, depth = 0, rmq_levels = 0;
+    std::vector<int32_t> post_of_caller;   // caller index -> post-order index
+    std::vector<int32_t> caller_of_post;   // post-order index -> caller index
+    std::vector<uint32_t> h_blob, h_kill, h_rmq, h_prims;
+    std::vector<st::NodePar> h_par;
+    std::vector<float> h_roi;
+    float extent = 0.f, lipschitz = 1.f;
+    float voi_lo[3] = {0, 0, 0}, voi_hi[3] = {0, 0, 0};
+
+    // device copies
+    uint32_t* d_blob = nullptr;
+    uint32_t* d_kill = nullptr;
+    uint32_t* d_rmq = nullptr;
+    uint32_t* d_prims = nullptr;     // post-order index of each primitive
+    st::NodePar* d_par = nullptr;
+    float* d_roi = nullptr;
+    st::Voi* d_voi = nullptr;
+    uint64_t device_bytes = 0;
+
+    // A-buffer (per camera)
+    bool ab_valid = false;
+    st_camera ab_cam{};
+    st_tuning ab_tune{};
+    st::DevCam dcam{};
+    int32_t tiles_x = 0, tiles_y = 0, n_tiles = 0;
+    float z_min = 0.f, z_max = 0.f;   // view-depth span of the VOI box
+    uint32_t* d_tile_off = nullptr;   // n_tiles + 1
+    uint32_t* d_tile_ovl = nullptr;   // per tile max depth overlap
+    uint32_t* d_e_node = nullptr;     // entries, SoA, sorted per tile
+    float* d_e_zin = nullptr;
+    float* d_e_zout = nullptr;
+    uint32_t* d_wide = nullptr;       // list of tiles that need the wide path, [0] = count
+    uint32_t* d_misc = nullptr;       // small device counters
+    int64_t n_entries = 0, ab_cap = 0;
+    uint32_t max_list = 0, max_overlap = 0, n_wide = 0;
+    int32_t ab_ma_fast = 0, ab_ma_wide = 0;
+
+    // scratch kept between builds
+    void* d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+
+    // step model (learned step)
+    float* d_mlp = nullptr;
+    bool has_model = false;
+
+    // device counters for one trace
+    unsigned long long* d_stats = nullptr;
+
+    st_allocator alloc{};
+    bool has_alloc = false;
+};
+
+namespace st {
+
+void set_error(const std::string& msg);
+st_status device_error(hipError_t e, const char* where);
+
+void* dev_alloc(st_scene* s, size_t bytes, hipStream_t stream);
+void dev_free(st_scene* s, void* p, hipStream_t stream);
+
+// binning.hip
+st_status launch_voi(st_scene* s, hipStream_t stream);
+st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stream);
+
+// trace.hip
+st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, hipStream_t stream);
+st_status debug_eval_device(const st_scene* s, const uint32_t* active_post, int n_active,
+                            const float* pts, int n_pts, float* out_f, float* out_grad,
+                            int* root_used, hipStream_t stream);
+
+// flatten.cpp (host)
+st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* s);
+PruneResult host_prune(const st_scene* s, std::vector<uint32_t> active_post,
+                       std::vector<uint32_t>& view);
+
+constexpr int kStatCount = 48;
+
+}  // namespace st

@@ -1,0 +1,753 @@
+// Synchronized tracing of tile subfrustums (Sections 7, 8 and 9 of Zanni
+// 2023; Algorithms 2 and 3), written for CDNA wave64.
+//
+// One wavefront owns one 8x8 pixel block (64 rays, one per lane) -- the
+// paper's 8x8 tile workgroup maps onto a single wave, so the whole
+// synchronization of Algorithm 2 is a wave vote and needs no barrier.  The
+// wave walks its tile's depth-sorted A-buffer list and cuts the frustum into
+// subfrustums [z_begin, z_end] with a fixed active primitive set (Section 8,
+// "Tracking active primitives"): exited primitives are dropped, new ones are
+// fetched while (no empty gap) and (z_b - z_begin < d) and (at most max_new
+// new) and (capacity), and z_end = min(next z_b, max active z_e).  All lanes
+// share the set, hence the pruned view, hence every node of every field
+// evaluation: node kinds and parameters are wave-uniform (scalar branches,
+// scalar loads), only the point differs per lane.
+//
+// The pruned view is built data-parallel (LCA queries, a wave bitonic sort,
+// a merge) plus one short bottom-up pass shared with the host code
+// (st_prune.h).  Each ray then sphere-traces its own span [t0, t1] of the
+// subfrustum, evaluating the view with the post-order stack machine of
+// Algorithm 3.  Steps are clamped at t1 because the pruned field is only
+// sign-equivalent to the full field inside the subfrustum.
+//
+// Stepping: the safe step is f/L with L the proven Lipschitz bound of the
+// view.  Once the safe step falls below eps the ray probes forward with
+// doubling steps from eps (a grazing ray is not stalled), a sign change is
+// bracketed and refined by regula falsi (Illinois), and the normal is the
+// normalised forward-mode gradient of the view at the root.
+#include <algorithm>
+
+#include "st_field.h"
+#include "st_internal.h"
+
+namespace st {
+
+// ---------------------------------------------------------------------------
+// wave helpers
+__device__ __forceinline__ int lane_id() { return int(threadIdx.x & 63u); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float unif(float x) { return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x))); }
+__device__ __forceinline__ uint32_t rdlane(uint32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ float rdlanef(float x, int l) { return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(x), l)); }
+// lane l of the result is v, every other lane keeps old (v and l uniform)
+__device__ __forceinline__ uint32_t wrlane(uint32_t v, int l, uint32_t old) { return int(threadIdx.x & 63u) == l ? v : old; }
+__device__ __forceinline__ float wrlanef(float v, int l, float old) { return int(threadIdx.x & 63u) == l ? v : old; }
+// orders LDS traffic of the wave (compiler and hardware) between phases
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+// ---------------------------------------------------------------------------
+struct TraceArgs {
+    const uint32_t* blob;
+    const NodePar* par;
+    const uint32_t* kill;
+    const uint32_t* rmq;
+    uint32_t n_nodes;
+    const uint32_t* tile_off;
+    const uint32_t* e_node;
+    const float* e_zin;
+    const float* e_zout;
+    const uint32_t* tile_ovl;
+    const uint32_t* wide;      // [0] count, [1..] tiles
+    DevCam cam;
+    int ts, tiles_x, tiles_y, sub_x;   // sub_x = ts / 8
+    uint32_t ma_fast;
+    float eps, d_sub, lip_fixed, omega;
+    int max_steps, refine_iters, max_new, step_mode;
+    float* out_depth;
+    float* out_normal;
+    unsigned long long* stats;
+};
+
+enum StatIdx {
+    S_RAYS = 0, S_HITS, S_UNCONV, S_EVALS, S_GEVALS, S_NODE = 5, S_GNODE = 9, S_STEPS = 13, S_SUBF, S_EMPTY,
+    S_VIEWN, S_MAXACT, S_WIDE, S_ACC, S_REJ, S_STALL, S_SMOOTH
+};
+
+// Per-wave LDS of capacity MA active primitives.
+template <int MA>
+struct WaveLds {
+    uint32_t act[2][MA];
+    float ze[2][MA];
+    uint32_t lca[MA];
+    uint32_t vs[2 * MA];
+    uint32_t view[2 * MA];
+};
+
+// ---------------------------------------------------------------------------
+// field of the pruned view at p (Algorithm 3: post-order stack machine).
+// The view entries are wave-uniform; `ent(j)` returns entry j as an SGPR.
+template <class T, class Ent>
+__device__ __forceinline__ T eval_view(const Ent& ent, int len, const NodePar* __restrict__ par, const P3<T>& p,
+                                       uint32_t& sm) {
+    T stk[kStack];
+    T acc = cst(0.f, p.x);
+    int sp = 0;
+    for (int j = 0; j < len; j++) {
+        uint32_t e = ent(j);
+        uint32_t kind = ventry_kind(e);
+        const float* q = par[ventry_node(e)].v;
+        // the index stays in [0, kStack) for any view (a well-formed view
+        // never leaves it: its depth is below the flatten limit)
+        if (kind <= ST_CAPSULE) {
+            if (j) { stk[sp & (kStack - 1)] = acc; sp++; }
+            acc = prim_eval<T>(kind, q, p);
+        } else {
+            sp--;
+            acc = op_eval<T>(kind, q, stk[sp & (kStack - 1)], acc, sm);
+        }
+    }
+    return acc;
+}
+
+// view entries held in VGPR chunks: lane l of chunk c has entry 64c + l
+template <int NCH>
+struct ChunkEnt {
+    uint32_t c[NCH];
+    __device__ __forceinline__ uint32_t operator()(int j) const { return rdlane(c[j >> 6], j & 63); }
+};
+// view entries read from LDS with a uniform address
+struct LdsEnt {
+    const uint32_t* v;
+    __device__ __forceinline__ uint32_t operator()(int j) const { return uni(v[j]); }
+};
+
+// ---------------------------------------------------------------------------
+// device context of the shared bottom-up pass (st_prune.h): per-position
+// data held in VGPR chunks read with readlane, the pass stack held across
+// lanes (lane k = stack slot k) with writelane/readlane.
+template <int NCH>
+struct DevPruneCtx {
+    uint32_t cn[NCH], cb[NCH], ck[NCH];
+    float cl[NCH];
+    uint32_t s_nu = 0, s_start = 0, s_kill = 0;
+    float s_L = 0.f;
+    uint32_t* view;
+    __device__ uint32_t node(int j) const { return rdlane(cn[j >> 6], j & 63); }
+    __device__ uint32_t blob(int j) const { return rdlane(cb[j >> 6], j & 63); }
+    __device__ uint32_t kill(int j) const { return rdlane(ck[j >> 6], j & 63); }
+    __device__ float lipf(int j) const { return rdlanef(cl[j >> 6], j & 63); }
+    __device__ void spush(int sp, uint32_t nu, uint32_t start, float L, uint32_t k) {
+        s_nu = wrlane(nu, sp, s_nu);
+        s_start = wrlane(start, sp, s_start);
+        s_kill = wrlane(k, sp, s_kill);
+        s_L = wrlanef(L, sp, s_L);
+    }
+    __device__ void sget(int sp, uint32_t& nu, uint32_t& start, float& L, uint32_t& k) const {
+        nu = rdlane(s_nu, sp);
+        start = rdlane(s_start, sp);
+        k = rdlane(s_kill, sp);
+        L = rdlanef(s_L, sp);
+    }
+    __device__ void emit(int pos, uint32_t e) {
+        if (lane_id() == 0) view[pos] = e;
+    }
+    __device__ void move(int dst, int src, int len) {
+        wave_sync();
+        for (int b = 0; b < len; b += 64) {
+            int i = b + lane_id();
+            uint32_t x = i < len ? view[src + i] : 0u;
+            wave_sync();
+            if (i < len) view[dst + i] = x;
+            wave_sync();
+        }
+    }
+};
+
+// same pass with per-position data in LDS (wide path, long views)
+struct LdsPruneCtx {
+    const uint32_t* vsn;   // nodes in post-order
+    const uint32_t* blobs;
+    const uint32_t* kills;
+    const NodePar* par;
+    uint32_t s_nu = 0, s_start = 0, s_kill = 0;
+    float s_L = 0.f;
+    uint32_t* view;
+    __device__ uint32_t node(int j) const { return uni(vsn[j]); }
+    __device__ uint32_t blob(int j) const { return uni(blobs[uni(vsn[j])]); }
+    __device__ uint32_t kill(int j) const { return uni(kills[uni(vsn[j])]); }
+    __device__ float lipf(int j) const { return unif(par[uni(vsn[j])].v[4]); }
+    __device__ void spush(int sp, uint32_t nu, uint32_t start, float L, uint32_t k) {
+        s_nu = wrlane(nu, sp, s_nu);
+        s_start = wrlane(start, sp, s_start);
+        s_kill = wrlane(k, sp, s_kill);
+        s_L = wrlanef(L, sp, s_L);
+    }
+    __device__ void sget(int sp, uint32_t& nu, uint32_t& start, float& L, uint32_t& k) const {
+        nu = rdlane(s_nu, sp);
+        start = rdlane(s_start, sp);
+        k = rdlane(s_kill, sp);
+        L = rdlanef(s_L, sp);
+    }
+    __device__ void emit(int pos, uint32_t e) {
+        if (lane_id() == 0) view[pos] = e;
+    }
+    __device__ void move(int dst, int src, int len) {
+        wave_sync();
+        for (int b = 0; b < len; b += 64) {
+            int i = b + lane_id();
+            uint32_t x = i < len ? view[src + i] : 0u;
+            wave_sync();
+            if (i < len) view[dst + i] = x;
+            wave_sync();
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// wave bitonic sort of a[0..np2) (u32) in LDS
+__device__ void wave_bitonic(uint32_t* a, int np2) {
+    for (int k = 2; k <= np2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            wave_sync();
+            for (int i = lane_id(); i < np2; i += 64) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    uint32_t x = a[i], y = a[ixj];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) { a[i] = y; a[ixj] = x; }
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// number of elements < x in sorted a[0..n)
+__device__ __forceinline__ int lower_count(const uint32_t* a, int n, uint32_t x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (a[m] < x) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+// Builds the pruned view of the active set S.act[buf][0..n) into S.view.
+template <int MA, bool kWide>
+__device__ PruneResult build_view(const TraceArgs& A, WaveLds<MA>& S, int buf, int n) {
+    const uint32_t* act = S.act[buf];
+    const int lane = lane_id();
+    int m;
+    if (n == 1) {
+        if (lane == 0) S.vs[0] = act[0];
+        m = 1;
+    } else {
+        // 1. LCAs of consecutive active primitives
+        int nl = n - 1;
+        int np2 = 1;
+        while (np2 < nl) np2 <<= 1;
+        for (int i = lane; i < np2; i += 64) {
+            uint32_t x = 0xFFFFFFFFu;
+            if (i < nl) x = lca_query(A.rmq, A.n_nodes, act[i], act[i + 1]);
+            S.lca[i] = x;
+        }
+        // 2. sort them
+        wave_bitonic(S.lca, np2);
+        // 3. merge with the (sorted) primitives into post-order
+        for (int i = lane; i < n; i += 64) {
+            uint32_t x = act[i];
+            S.vs[i + lower_count(S.lca, nl, x)] = x;
+        }
+        for (int i = lane; i < nl; i += 64) {
+            uint32_t x = S.lca[i];
+            S.vs[i + lower_count(act, n, x)] = x;
+        }
+        m = 2 * n - 1;
+    }
+    wave_sync();
+    // 4. bottom-up pass (usage, killing ancestors, compaction, Lipschitz)
+    if constexpr (!kWide) {
+        constexpr int NCH = (2 * MA + 63) / 64;
+        DevPruneCtx<NCH> c;
+        c.view = S.view;
+#pragma unroll
+        for (int q = 0; q < NCH; q++) {
+            int j = q * 64 + lane;
+            uint32_t v = j < m ? S.vs[j] : 0u;
+            c.cn[q] = v;
+            c.cb[q] = j < m ? A.blob[v] : 0u;
+            c.ck[q] = j < m ? A.kill[v] : kNoKill;
+            c.cl[q] = j < m ? A.par[v].v[4] : 1.f;
+        }
+        PruneResult r = prune_pass(c, m);
+        wave_sync();
+        return r;
+    } else {
+        LdsPruneCtx c;
+        c.vsn = S.vs;
+        c.blobs = A.blob;
+        c.kills = A.kill;
+        c.par = A.par;
+        c.view = S.view;
+        PruneResult r = prune_pass(c, m);
+        wave_sync();
+        return r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lane modes inside a subfrustum
+enum { M_IDLE = 0, M_TRACE = 1, M_REFINE = 2, M_GRAD = 3 };
+
+template <int MA, bool kWide>
+__device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, uint32_t sub,
+                            unsigned long long* cnt) {
+    const int lane = lane_id();
+    const int tx = int(tile % uint32_t(A.tiles_x)), ty = int(tile / uint32_t(A.tiles_x));
+    const int sx = int(sub % uint32_t(A.sub_x)), sy = int(sub / uint32_t(A.sub_x));
+    const int px = tx * A.ts + sx * 8 + (lane & 7);
+    const int py = ty * A.ts + sy * 8 + (lane >> 3);
+    const bool valid = px < A.cam.w && py < A.cam.h;
+    if (ballot(valid) == 0) return;
+    Ray ray = pixel_ray(A.cam, px, py);
+    const float inv_cos = 1.0f / ray.cosv;
+
+    // per-lane ray state
+    float t = 0.f;
+    bool done = !valid, hit = false, unconv = false;
+    float t_hit = __builtin_inff(), nx = 0.f, ny = 0.f, nz = 0.f;
+    int steps = 0;
+    uint32_t evals = 0, gevals = 0, smooth = 0;
+    float tp = 0.f, vp = 0.f, hp = 0.f;   // last positive point, its value, probe step
+    bool tp_ok = false, last_safe = true;
+
+    // wave state (uniform)
+    const uint32_t e0 = uni(A.tile_off[tile]), e1 = uni(A.tile_off[tile + 1]);
+    uint32_t i = e0;
+    int n = 0, buf = 0;
+    float z_end = -__builtin_inff();
+    uint64_t node_cnt[4] = {0, 0, 0, 0}, gnode_cnt[4] = {0, 0, 0, 0};
+    uint32_t n_subf = 0, n_empty = 0, max_act = 0;
+    uint64_t view_nodes = 0;
+    // every turn fetches, drops or closes a subfrustum that the next turn
+    // drops from; the bound only guards against a stalled capacity
+    uint32_t guard = 4u * (e1 - e0) + 8u;
+
+    while (true) {
+        if (ballot(!done) == 0) break;
+        if (i >= e1 && n == 0) break;
+        if (guard-- == 0u) {
+            if (lane == 0) atomicAdd(cnt + S_STALL, 1ull);
+            break;
+        }
+        // -- drop exited primitives (z_e <= z_end), compact in place
+        {
+            int kept = 0;
+            for (int b = 0; b < n; b += 64) {
+                int s = b + lane;
+                bool in = s < n;
+                uint32_t a = in ? S.act[buf][s] : 0u;
+                float z = in ? S.ze[buf][s] : 0.f;
+                bool keep = in && z > z_end;
+                uint64_t mk = ballot(keep);
+                int dst = kept + int(lanes_below(mk));
+                wave_sync();
+                if (keep) { S.act[buf][dst] = a; S.ze[buf][dst] = z; }
+                kept += __popcll(mk);
+            }
+            n = kept;
+            wave_sync();
+        }
+        if (i >= e1 && n == 0) break;
+        const float z_begin = n > 0 ? z_end : unif(A.e_zin[i]);
+        // max exit depth of the remaining active set
+        float mz = -__builtin_inff();
+        for (int s = lane; s < n; s += 64) mz = fmaxf(mz, S.ze[buf][s]);
+        mz = wave_max(mz);
+        // -- fetch new primitives (lane c considers list entry i + c)
+        int k = 0;
+        if (i < e1) {
+            uint32_t c = uint32_t(lane);
+            bool in = i + c < e1;
+            float zb = in ? A.e_zin[i + c] : __builtin_inff();
+            float zo = in ? A.e_zout[i + c] : -__builtin_inff();
+            uint32_t nd = in ? A.e_node[i + c] : 0u;
+            // exclusive prefix max of exit depths of earlier candidates
+            float pm = zo;
+            for (int o = 1; o < 64; o <<= 1) {
+                float y = __shfl_up(pm, o);
+                if (lane >= o) pm = fmaxf(pm, y);
+            }
+            float pex = __shfl_up(pm, 1);
+            if (lane == 0) pex = -__builtin_inff();
+            float reach = fmaxf(fmaxf(z_begin, mz), pex);
+            bool ok = in && lane < A.max_new && (n + lane) < MA && (zb - z_begin < A.d_sub || lane == 0) &&
+                      zb <= reach;
+            uint64_t okm = ballot(ok);
+            k = ~okm == 0ull ? 64 : int(__builtin_ctzll(~okm));
+            if (k > 0) {
+                // merge the k new primitives (lanes 0..k-1) into the sorted active list
+                int nb = buf ^ 1;
+                for (int b = 0; b < n; b += 64) {
+                    int s = b + lane;
+                    if (s < n) {
+                        uint32_t a = S.act[buf][s];
+                        int less = 0;
+                        for (int q = 0; q < k; q++) less += rdlane(nd, q) < a ? 1 : 0;
+                        S.act[nb][s + less] = a;
+                        S.ze[nb][s + less] = S.ze[buf][s];
+                    }
+                }
+                if (lane < k) {
+                    int pos = lower_count(S.act[buf], n, nd);
+                    int less = 0;
+                    for (int q = 0; q < k; q++) less += rdlane(nd, q) < nd ? 1 : 0;
+                    S.act[nb][pos + less] = nd;
+                    S.ze[nb][pos + less] = zo;
+                }
+                // the new ones also extend the reach
+                float nz_ = lane < k ? zo : -__builtin_inff();
+                mz = fmaxf(mz, wave_max(nz_));
+                buf = nb;
+                n += k;
+                i += uint32_t(k);
+                wave_sync();
+            }
+        }
+        const float z_next = i < e1 ? unif(A.e_zin[i]) : __builtin_inff();
+        z_end = fminf(z_next, mz);
+        max_act = max(max_act, uint32_t(n));
+        if (!(z_end > z_begin)) continue;
+        n_subf++;
+
+        // -- pruned view of the active set
+        PruneResult pr = build_view<MA, kWide>(A, S, buf, n);
+        const float t0 = z_begin * inv_cos, t1 = z_end * inv_cos;
+        if (!pr.used) {
+            n_empty++;
+            if (!done && t < t1) { t = t1; tp_ok = false; }
+            continue;
+        }
+        const int len = pr.len;
+        view_nodes += uint64_t(len);
+        const float L = A.lip_fixed > 0.f ? A.lip_fixed : pr.lip;
+        const float invL = 1.0f / L;
+        // kinds in the view (for node counts)
+        uint32_t kc[4] = {0, 0, 0, 0};
+        for (int j = lane; j < len; j += 64) {
+            uint32_t kd = ventry_kind(S.view[j]);
+            kc[kd <= ST_CAPSULE ? kd : 3]++;
+        }
+        for (int q = 0; q < 4; q++) kc[q] = wave_sum(kc[q]);
+
+        // -- trace every ray's span of the subfrustum
+        int mode = M_IDLE;
+        if (!done) {
+            if (t < t0) { t = t0; tp_ok = false; }
+            if (t < t1) mode = M_TRACE;
+        }
+        float ra = 0.f, fa = 0.f, rb = 0.f, fb = 0.f;   // refinement bracket
+        int nref = 0, side = 0;
+        uint32_t ev_here = 0;
+        constexpr int NCH = (2 * MA + 63) / 64;
+        ChunkEnt<kWide ? 1 : NCH> ce;
+        if constexpr (!kWide) {
+#pragma unroll
+            for (int q = 0; q < NCH; q++) {
+                int j = q * 64 + lane;
+                ce.c[q] = j < len ? S.view[j] : 0u;
+            }
+        }
+        LdsEnt le{S.view};
+        while (true) {
+            bool act = mode == M_TRACE || mode == M_REFINE;
+            if (ballot(act) == 0) break;
+            float v = 0.f;
+            if (act) {
+                P3<float> p{fmaf(t, ray.d[0], ray.o[0]), fmaf(t, ray.d[1], ray.o[1]), fmaf(t, ray.d[2], ray.o[2])};
+                if constexpr (kWide) v = eval_view<float>(le, len, A.par, p, smooth);
+                else v = eval_view<float>(ce, len, A.par, p, smooth);
+                ev_here++;
+            }
+            if (mode == M_TRACE) {
+                steps++;
+                if (v <= 0.f) {
+                    if (!tp_ok || last_safe) {
+                        // root at t: the open span before t is root-free
+                        t_hit = t;
+                        mode = M_GRAD;
+                    } else {
+                        ra = tp; fa = vp; rb = t; fb = v;
+                        nref = 0; side = 0;
+                        mode = M_REFINE;
+                        t = ra + (rb - ra) * (fa / (fa - fb));
+                        if (!(t > ra && t < rb)) t = 0.5f * (ra + rb);
+                    }
+                } else {
+                    float s = v * invL;
+                    bool safe = s >= A.eps;
+                    if (!safe) {
+                        s = (hp > 0.f && tp_ok && v < vp) ? 2.f * hp : A.eps;
+                        hp = s;
+                    } else {
+                        hp = 0.f;
+                    }
+                    last_safe = safe;
+                    tp = t; vp = v; tp_ok = true;
+                    float tn = t + s;
+                    if (tn >= t1) {
+                        t = t1;
+                        mode = M_IDLE;
+                    } else if (steps >= A.max_steps) {
+                        mode = M_IDLE;
+                        done = true;
+                        unconv = true;
+                    } else {
+                        t = tn;
+                    }
+                }
+            } else if (mode == M_REFINE) {
+                nref++;
+                if (v <= 0.f) {
+                    rb = t; fb = v;
+                    if (side == -1) fa *= 0.5f;   // Illinois
+                    side = -1;
+                } else {
+                    ra = t; fa = v;
+                    if (side == 1) fb *= 0.5f;
+                    side = 1;
+                }
+                if (nref >= A.refine_iters || rb - ra <= 1e-6f * fmaxf(1.f, rb)) {
+                    t_hit = ra + (rb - ra) * (fa / (fa - fb));
+                    if (!(t_hit >= ra && t_hit <= rb)) t_hit = rb;
+                    mode = M_GRAD;
+                } else {
+                    t = ra + (rb - ra) * (fa / (fa - fb));
+                    if (!(t > ra && t < rb)) t = 0.5f * (ra + rb);
+                }
+            }
+        }
+        // -- normals of the rays that found their root in this subfrustum
+        uint32_t g_here = __popcll(ballot(mode == M_GRAD));
+        for (int q = 0; q < 4; q++) gnode_cnt[q] += uint64_t(g_here) * kc[q];
+        if (g_here != 0) {
+            if (mode == M_GRAD) {
+                P3<Dual> p = make_point(fmaf(t_hit, ray.d[0], ray.o[0]), fmaf(t_hit, ray.d[1], ray.o[1]),
+                                        fmaf(t_hit, ray.d[2], ray.o[2]), Dual{});
+                Dual g;
+                uint32_t sm_g = 0;
+                if constexpr (kWide) g = eval_view<Dual>(le, len, A.par, p, sm_g);
+                else g = eval_view<Dual>(ce, len, A.par, p, sm_g);
+                float gn = sqrtf(g.gx * g.gx + g.gy * g.gy + g.gz * g.gz);
+                float ig = gn > 0.f ? 1.0f / gn : 0.f;
+                nx = g.gx * ig; ny = g.gy * ig; nz = g.gz * ig;
+                hit = true;
+                done = true;
+                gevals++;
+            }
+        }
+        uint32_t tot = wave_sum(ev_here);
+        evals += ev_here;
+        for (int q = 0; q < 4; q++) node_cnt[q] += uint64_t(tot) * kc[q];
+    }
+
+    // outputs
+    if (valid) {
+        size_t pix = size_t(py) * A.cam.w + px;
+        A.out_depth[pix] = hit ? t_hit : __builtin_inff();
+        A.out_normal[3 * pix + 0] = hit ? nx : 0.f;
+        A.out_normal[3 * pix + 1] = hit ? ny : 0.f;
+        A.out_normal[3 * pix + 2] = hit ? nz : 0.f;
+    }
+    // counters (one atomic per counter per wave)
+    uint32_t rays = __popcll(ballot(valid));
+    uint32_t hits = __popcll(ballot(valid && hit));
+    uint32_t unc = __popcll(ballot(valid && unconv));
+    uint32_t ev = wave_sum(evals + gevals), gev = wave_sum(gevals), st = wave_sum(uint32_t(steps));
+    uint32_t smt = wave_sum(smooth);
+    if (lane == 0) {
+        atomicAdd(cnt + S_RAYS, (unsigned long long)rays);
+        atomicAdd(cnt + S_HITS, (unsigned long long)hits);
+        atomicAdd(cnt + S_UNCONV, (unsigned long long)unc);
+        atomicAdd(cnt + S_EVALS, (unsigned long long)ev);
+        atomicAdd(cnt + S_GEVALS, (unsigned long long)gev);
+        atomicAdd(cnt + S_STEPS, (unsigned long long)st);
+        for (int q = 0; q < 4; q++) atomicAdd(cnt + S_NODE + q, (unsigned long long)node_cnt[q]);
+        for (int q = 0; q < 4; q++) atomicAdd(cnt + S_GNODE + q, (unsigned long long)gnode_cnt[q]);
+        atomicAdd(cnt + S_SUBF, (unsigned long long)n_subf);
+        atomicAdd(cnt + S_EMPTY, (unsigned long long)n_empty);
+        atomicAdd(cnt + S_VIEWN, (unsigned long long)view_nodes);
+        atomicMax(cnt + S_MAXACT, (unsigned long long)max_act);
+        atomicAdd(cnt + S_SMOOTH, (unsigned long long)smt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fast path: one wave per 8x8 block, 4 waves per workgroup, LDS view of
+// capacity MA.  Blocks of tiles that overlap more than MA go to the wide path.
+template <int MA>
+__global__ void __launch_bounds__(256) trace_fast_kernel(TraceArgs A, uint32_t n_jobs) {
+    __shared__ WaveLds<MA> lds[4];
+    const int w = threadIdx.x >> 6;
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
+    // so workgroup g runs on XCD g % 8; give each XCD a contiguous range of
+    // jobs (neighbouring tiles share primitives and their L2 lines).
+    uint32_t nwg = gridDim.x, g = blockIdx.x;
+    uint32_t x = g % 8u, idx = g / 8u, q = nwg / 8u, r = nwg % 8u;
+    uint32_t gg = x * q + min(x, r) + idx;
+    uint32_t job = gg * 4 + uint32_t(w);
+    if (job >= n_jobs) return;
+    uint32_t spt = uint32_t(A.sub_x * A.sub_x);
+    uint32_t tile = job / spt, sub = job % spt;
+    if (A.tile_ovl[tile] > A.ma_fast) return;   // wide path
+    trace_block<MA, false>(A, lds[w], tile, sub, A.stats);
+}
+
+// Wide path: one wave per workgroup, blocks of the listed tiles.
+template <int MA>
+__global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A) {
+    extern __shared__ char dyn[];
+    WaveLds<MA>& S = *reinterpret_cast<WaveLds<MA>*>(dyn);
+    uint32_t n_wide = A.wide[0];
+    uint32_t spt = uint32_t(A.sub_x * A.sub_x);
+    for (uint32_t job = blockIdx.x; job < n_wide * spt; job += gridDim.x) {
+        uint32_t tile = A.wide[1 + job / spt], sub = job % spt;
+        if (lane_id() == 0) atomicAdd(A.stats + S_WIDE, 1ull);
+        trace_block<MA, true>(A, S, tile, sub, A.stats);
+    }
+}
+
+constexpr int kMaFast = 128;
+constexpr int kMaWide = 1024;
+
+st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, hipStream_t stream) {
+    TraceArgs A;
+    A.blob = s->d_blob;
+    A.par = s->d_par;
+    A.kill = s->d_kill;
+    A.rmq = s->d_rmq;
+    A.n_nodes = uint32_t(s->n_nodes);
+    A.tile_off = s->d_tile_off;
+    A.e_node = s->d_e_node;
+    A.e_zin = s->d_e_zin;
+    A.e_zout = s->d_e_zout;
+    A.tile_ovl = s->d_tile_ovl;
+    A.wide = s->d_wide;
+    A.cam = s->dcam;
+    A.ts = t.tile;
+    A.tiles_x = s->tiles_x;
+    A.tiles_y = s->tiles_y;
+    A.sub_x = t.tile / 8;
+    A.ma_fast = uint32_t(s->ab_ma_fast);
+    A.eps = t.eps;
+    A.d_sub = t.sub_depth * (s->z_max - s->z_min);
+    A.lip_fixed = t.lipschitz;
+    A.omega = t.omega;
+    A.max_steps = t.max_steps;
+    A.refine_iters = t.refine_iters;
+    A.max_new = std::max(1, std::min(64, t.max_new));
+    A.step_mode = t.step_mode;
+    A.out_depth = depth;
+    A.out_normal = normal;
+    A.stats = s->d_stats;
+    hipError_t e = hipMemsetAsync(s->d_stats, 0, kStatCount * 8, stream);
+    if (e != hipSuccess) return device_error(e, "memset stats");
+    uint32_t spt = uint32_t(A.sub_x * A.sub_x);
+    uint32_t n_jobs = uint32_t(s->n_tiles) * spt;
+    uint32_t nwg = (n_jobs + 3) / 4;
+    hipLaunchKernelGGL(trace_fast_kernel<kMaFast>, dim3(nwg), dim3(256), 0, stream, A, n_jobs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return device_error(e, "trace_fast_kernel");
+    if (s->n_wide > 0) {
+        if (s->max_overlap > uint32_t(kMaWide)) {
+            set_error("trace: depth overlap " + std::to_string(s->max_overlap) + " exceeds the wide path capacity " +
+                      std::to_string(kMaWide));
+            return ST_E_CAPACITY;
+        }
+        size_t shm = sizeof(WaveLds<kMaWide>);
+        uint32_t grid = std::min<uint32_t>(s->n_wide * spt, 4096u);
+        hipLaunchKernelGGL(trace_wide_kernel<kMaWide>, dim3(grid), dim3(64), shm, stream, A);
+        e = hipGetLastError();
+        if (e != hipSuccess) return device_error(e, "trace_wide_kernel");
+    }
+    return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// test hook: pruned field of a given active set at points
+template <int MA>
+__global__ void __launch_bounds__(64) debug_eval_kernel(TraceArgs A, const uint32_t* act_sorted, int n,
+                                                         const float* pts, int n_pts, float* out_f, float* out_g,
+                                                         int* root_used, uint32_t* view_out) {
+    extern __shared__ char dyn[];
+    WaveLds<MA>& S = *reinterpret_cast<WaveLds<MA>*>(dyn);
+    const int lane = lane_id();
+    for (int s = lane; s < n; s += 64) { S.act[0][s] = act_sorted[s]; S.ze[0][s] = 0.f; }
+    wave_sync();
+    PruneResult pr = build_view<MA, true>(A, S, 0, n);
+    if (lane == 0) {
+        root_used[0] = pr.used;
+        root_used[1] = pr.len;
+        root_used[2] = __float_as_int(pr.lip);
+    }
+    for (int j = lane; j < pr.len; j += 64) view_out[j] = S.view[j];
+    LdsEnt le{S.view};
+    for (int b = int(blockIdx.x) * 64; b < n_pts; b += int(gridDim.x) * 64) {
+        int i = b + lane;
+        bool in = i < n_pts;
+        float x = in ? pts[3 * i] : 0.f, y = in ? pts[3 * i + 1] : 0.f, z = in ? pts[3 * i + 2] : 0.f;
+        if (!pr.used) {
+            if (in) {
+                out_f[i] = __builtin_inff();
+                if (out_g) { out_g[3 * i] = 0.f; out_g[3 * i + 1] = 0.f; out_g[3 * i + 2] = 0.f; }
+            }
+            continue;
+        }
+        if (out_g) {
+            P3<Dual> p = make_point(x, y, z, Dual{});
+            uint32_t sm = 0;
+            Dual g = eval_view<Dual>(le, pr.len, A.par, p, sm);
+            if (in) { out_f[i] = g.v; out_g[3 * i] = g.gx; out_g[3 * i + 1] = g.gy; out_g[3 * i + 2] = g.gz; }
+        } else {
+            P3<float> p{x, y, z};
+            uint32_t sm = 0;
+            float v = eval_view<float>(le, pr.len, A.par, p, sm);
+            if (in) out_f[i] = v;
+        }
+    }
+}
+
+st_status debug_eval_device(const st_scene* s, const uint32_t* act_sorted_dev, int n, const float* pts, int n_pts,
+                            float* out_f, float* out_g, int* root_used_dev, hipStream_t stream) {
+    TraceArgs A{};
+    A.blob = s->d_blob;
+    A.par = s->d_par;
+    A.kill = s->d_kill;
+    A.rmq = s->d_rmq;
+    A.n_nodes = uint32_t(s->n_nodes);
+    if (n > kMaWide) { set_error("debug_eval: active set larger than the wide path capacity"); return ST_E_CAPACITY; }
+    size_t shm = sizeof(WaveLds<kMaWide>);
+    uint32_t* view_out = reinterpret_cast<uint32_t*>(root_used_dev + 4);
+    int grid = std::max(1, std::min(1024, (n_pts + 63) / 64));
+    hipLaunchKernelGGL(debug_eval_kernel<kMaWide>, dim3(grid), dim3(64), shm, stream, A, act_sorted_dev, n, pts,
+                       n_pts, out_f, out_g, root_used_dev, view_out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ST_OK : device_error(e, "debug_eval_kernel");
+}
+
+}  // namespace st

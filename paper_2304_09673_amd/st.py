@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libsynctrace.so (include/st.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device memory and streams come from PyTorch.  There is no fallback:
+if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libsynctrace.so"
+
+ST_OK, ST_E_INVALID, ST_E_TREE, ST_E_CAPACITY, ST_E_NOMEM, ST_E_DEVICE, ST_E_STALE = range(7)
+ST_STEP_PLAIN, ST_STEP_OVERRELAX, ST_STEP_LEARNED = 0, 1, 2
+
+# every symbol include/st.h declares
+EXPORTS = (
+    "st_status_str", "st_last_error", "st_default_tuning", "st_flatten_blobtree", "st_scene_destroy",
+    "st_scene_get_info", "st_build_abuffer", "st_trace", "st_debug_eval_field", "st_debug_prune_tree",
+    "st_debug_abuffer",
+)
+
+
+class StError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"st error {code}: {msg}")
+        self.code = code
+
+
+class StNode(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("left", C.c_int32), ("right", C.c_int32), ("p", C.c_float * 16)]
+
+
+class StCamera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3),
+                ("vfov_deg", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class StTuning(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("max_active", C.c_int32), ("sub_depth", C.c_float),
+                ("max_new", C.c_int32), ("eps", C.c_float), ("max_steps", C.c_int32),
+                ("refine_iters", C.c_int32), ("step_mode", C.c_int32), ("omega", C.c_float),
+                ("lipschitz", C.c_float), ("reserved", C.c_int32 * 6)]
+
+
+class StStats(C.Structure):
+    _fields_ = [("rays", C.c_uint64), ("hits", C.c_uint64), ("unconverged", C.c_uint64),
+                ("field_evals", C.c_uint64), ("grad_evals", C.c_uint64),
+                ("node_evals", C.c_uint64 * 4), ("grad_node_evals", C.c_uint64 * 4),
+                ("steps", C.c_uint64), ("subfrustums", C.c_uint64), ("empty_views", C.c_uint64),
+                ("view_nodes", C.c_uint64), ("abuffer_entries", C.c_uint64), ("max_list", C.c_uint64),
+                ("max_overlap", C.c_uint64), ("max_active", C.c_uint64), ("wide_tiles", C.c_uint64),
+                ("learned_accepted", C.c_uint64), ("learned_rejected", C.c_uint64),
+                ("reserved", C.c_uint64 * 8)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if not isinstance(v, int) else int(v)
+        res = d.pop("reserved")
+        d["stalled"] = res[0]
+        d["smooth_evals"] = res[1]
+        return d
+
+
+class StSceneInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_prims", C.c_int32), ("depth", C.c_int32), ("extent", C.c_float),
+                ("lipschitz", C.c_float), ("voi_lo", C.c_float * 3), ("voi_hi", C.c_float * 3),
+                ("device_bytes", C.c_uint64), ("abuffer_bytes", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2304_09673_amd/build.py "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(str(LIB_PATH))
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        L.st_status_str.restype = C.c_char_p
+        L.st_status_str.argtypes = [C.c_int]
+        L.st_last_error.restype = C.c_char_p
+        L.st_last_error.argtypes = []
+        L.st_default_tuning.argtypes = [C.POINTER(StTuning)]
+        L.st_flatten_blobtree.argtypes = [C.POINTER(StNode), i32, i32, vp, vp, C.POINTER(vp)]
+        L.st_scene_destroy.restype = None
+        L.st_scene_destroy.argtypes = [vp]
+        L.st_scene_get_info.argtypes = [vp, C.POINTER(StSceneInfo)]
+        L.st_build_abuffer.argtypes = [vp, C.POINTER(StCamera), C.POINTER(StTuning), vp]
+        L.st_trace.argtypes = [vp, C.POINTER(StCamera), vp, vp, C.POINTER(StStats), vp]
+        L.st_debug_eval_field.argtypes = [vp, vp, i32, vp, i32, vp, vp, C.POINTER(i32), vp, i32, C.POINTER(i32), vp]
+        L.st_debug_prune_tree.argtypes = [C.POINTER(StNode), i32, i32, vp, i32, vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]
+        L.st_debug_abuffer.argtypes = [vp, vp, sz, vp, sz, C.POINTER(i32), C.POINTER(i64), vp]
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if f.restype is C.c_int or name in ("st_default_tuning",):
+                f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != ST_OK:
+        raise StError(code, lib().st_last_error().decode())
+
+
+def default_tuning(**kw) -> StTuning:
+    t = StTuning()
+    _check(lib().st_default_tuning(C.byref(t)))
+    for k, v in kw.items():
+        if not hasattr(t, k):
+            raise KeyError(k)
+        setattr(t, k, v)
+    return t
+
+
+def make_camera(cam) -> StCamera:
+    c = StCamera()
+    c.eye[:] = list(map(float, cam.eye))
+    c.target[:] = list(map(float, cam.target))
+    c.up[:] = list(map(float, cam.up))
+    c.vfov_deg = float(cam.vfov_deg)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def nodes_from_arrays(kind, left, right, params):
+    n = len(kind)
+    arr = (StNode * n)()
+    params = np.asarray(params, dtype=np.float32).reshape(n, 16)
+    for i in range(n):
+        arr[i].kind = int(kind[i])
+        arr[i].left = int(left[i])
+        arr[i].right = int(right[i])
+        arr[i].p[:] = params[i].tolist()
+    return arr
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Scene:
+    """A flattened blobtree on the GPU (st_flatten_blobtree)."""
+
+    def __init__(self, scene=None, *, kind=None, left=None, right=None, params=None, root=None, stream=None):
+        if scene is not None:
+            kind, left, right, params, root = scene.kind, scene.left, scene.right, scene.params, scene.root
+        self._nodes = nodes_from_arrays(kind, left, right, params)
+        self.n = len(self._nodes)
+        h = C.c_void_p()
+        _check(lib().st_flatten_blobtree(self._nodes, self.n, int(root), None, _stream_ptr(stream), C.byref(h)))
+        self._h = h
+        self._cam = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().st_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = StSceneInfo()
+        _check(lib().st_scene_get_info(self._h, C.byref(i)))
+        return {"n_nodes": i.n_nodes, "n_prims": i.n_prims, "depth": i.depth, "extent": i.extent,
+                "lipschitz": i.lipschitz, "voi_lo": list(i.voi_lo), "voi_hi": list(i.voi_hi),
+                "device_bytes": i.device_bytes, "abuffer_bytes": i.abuffer_bytes}
+
+    def build_abuffer(self, camera, tuning: StTuning | None = None, stream=None):
+        self._cam = make_camera(camera)
+        _check(lib().st_build_abuffer(self._h, C.byref(self._cam), C.byref(tuning) if tuning else None,
+                                      _stream_ptr(stream)))
+
+    def trace(self, camera=None, depth=None, normal=None, stats: bool = True, stream=None):
+        """Returns (depth[H,W], normal[H,W,3], stats dict or None) as torch CUDA tensors."""
+        import torch
+        cam = make_camera(camera) if camera is not None else self._cam
+        W, H = cam.width, cam.height
+        if depth is None:
+            depth = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        if normal is None:
+            normal = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        assert depth.is_cuda and depth.dtype == torch.float32 and depth.numel() == H * W and depth.is_contiguous()
+        assert normal.is_cuda and normal.dtype == torch.float32 and normal.numel() == 3 * H * W and normal.is_contiguous()
+        st = StStats() if stats else None
+        _check(lib().st_trace(self._h, C.byref(cam), C.c_void_p(depth.data_ptr()), C.c_void_p(normal.data_ptr()),
+                              C.byref(st) if st is not None else None, _stream_ptr(stream)))
+        return depth, normal, (st.as_dict() if st is not None else None)
+
+    def debug_eval(self, pts, active=None, grad: bool = False, stream=None):
+        """Pruned field f_A of the active primitives (caller node indices, None = all) at
+        points (n,3).  Returns (f, grad or None, root_used, device view as caller indices)."""
+        import torch
+        p = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float32)).cuda()
+        n = p.shape[0]
+        f = torch.empty(n, dtype=torch.float32, device="cuda")
+        g = torch.empty((n, 3), dtype=torch.float32, device="cuda") if grad else None
+        used = C.c_int32(0)
+        vlen = C.c_int32(0)
+        view = np.zeros(2048, dtype=np.int32)
+        if active is None:
+            a_ptr, na = None, 0
+        else:
+            a = np.ascontiguousarray(active, dtype=np.int32)
+            a_ptr, na = a.ctypes.data_as(C.c_void_p), a.shape[0]
+        _check(lib().st_debug_eval_field(self._h, a_ptr, na, C.c_void_p(p.data_ptr()), n, C.c_void_p(f.data_ptr()),
+                                         C.c_void_p(g.data_ptr()) if grad else None, C.byref(used),
+                                         view.ctypes.data_as(C.c_void_p), view.shape[0], C.byref(vlen),
+                                         _stream_ptr(stream)))
+        return f, g, int(used.value), view[: vlen.value].copy()
+
+    def debug_abuffer(self, stream=None):
+        """(tile_off[T+1], node[E], z_in[E], z_out[E]) of the current A-buffer (host numpy)."""
+        nt, ne = C.c_int32(0), C.c_int64(0)
+        _check(lib().st_debug_abuffer(self._h, None, 0, None, 0, C.byref(nt), C.byref(ne), _stream_ptr(stream)))
+        off = np.zeros(nt.value + 1, dtype=np.uint32)
+        ent = np.zeros(3 * max(ne.value, 1), dtype=np.uint32)
+        _check(lib().st_debug_abuffer(self._h, off.ctypes.data_as(C.c_void_p), off.shape[0],
+                                      ent.ctypes.data_as(C.c_void_p), ent.shape[0], C.byref(nt), C.byref(ne),
+                                      _stream_ptr(stream)))
+        e = ent[: 3 * ne.value].reshape(-1, 3)
+        return off, e[:, 0].astype(np.int64), e[:, 1].view(np.float32), e[:, 2].view(np.float32)
+
+
+def prune_tree(kind, left, right, params, root, active):
+    """Host-only pruned view (st_debug_prune_tree): (caller indices in evaluation order, Lipschitz)."""
+    nodes = nodes_from_arrays(kind, left, right, params)
+    n = len(nodes)
+    a = np.ascontiguousarray(active if active is not None else [], dtype=np.int32)
+    cap = 2 * n + 2
+    out = np.zeros(cap, dtype=np.int32)
+    ln = C.c_int32(0)
+    lip = C.c_float(0)
+    _check(lib().st_debug_prune_tree(nodes, n, int(root), a.ctypes.data_as(C.c_void_p) if active is not None else None,
+                                     a.shape[0], out.ctypes.data_as(C.c_void_p), cap, C.byref(ln), C.byref(lip)))
+    return out[: ln.value].copy(), float(lip.value)

@@ -1,0 +1,226 @@
+"""CPU-side checks of the C ABI library: it loads without a GPU, exports every
+function include/st.h declares, and its host logic (flatten validation, the
+pruned tree view) follows the paper's rules."""
+import ctypes as C
+import itertools
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from paper_2304_09673_amd import st
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def _declared():
+    text = (ROOT / "include" / "st.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(st_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 11
+    lib = st.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in st.EXPORTS, n
+    assert set(st.EXPORTS) == set(names)
+
+
+def test_status_strings_and_default_tuning():
+    lib = st.lib()
+    assert lib.st_status_str(0) == b"ok"
+    assert lib.st_status_str(6) == b"stale A-buffer"
+    t = st.default_tuning()
+    # the paper's defaults (Implementation details): 8x8 tiles are the trace
+    # granularity; d = 1/20 of scene depth, <= 6 new primitives per fetch
+    assert abs(t.sub_depth - 0.05) < 1e-7 and t.max_new == 6
+    assert t.eps == pytest.approx(1e-4) and t.max_steps == 128
+    assert abs(t.omega - 1.7) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# flatten validation (host only)
+
+def _prune(sc, active):
+    return st.prune_tree(sc.kind, sc.left, sc.right, sc.params, sc.root, active)
+
+
+def test_flatten_rejects_malformed_trees():
+    sc = sg.random_small_tree(1, 4)
+    # cycle: a child points back to the root
+    k, l, r, p = sc.kind.copy(), sc.left.copy(), sc.right.copy(), sc.params.copy()
+    op = int(np.nonzero(k >= 16)[0][0])
+    l[op] = sc.root
+    with pytest.raises(st.StError) as e:
+        st.prune_tree(k, l, r, p, sc.root, [])
+    assert e.value.code == st.ST_E_TREE
+    # unknown kind
+    k = sc.kind.copy()
+    k[0] = 7
+    with pytest.raises(st.StError) as e:
+        st.prune_tree(k, sc.left, sc.right, sc.params, sc.root, [])
+    assert e.value.code == st.ST_E_TREE
+    # unreachable node (extra primitive)
+    k = np.append(sc.kind, sg.SPHERE).astype(np.int32)
+    l = np.append(sc.left, -1).astype(np.int32)
+    r = np.append(sc.right, -1).astype(np.int32)
+    p = np.vstack([sc.params, sc.params[:1]])
+    with pytest.raises(st.StError) as e:
+        st.prune_tree(k, l, r, p, sc.root, [])
+    assert e.value.code == st.ST_E_TREE
+
+
+@pytest.mark.parametrize("field,value", [("radius", 0.0), ("radius", float("nan")), ("k", -0.1), ("k", float("inf"))])
+def test_flatten_rejects_bad_parameters(field, value):
+    sc = sg.tree_from_shape((0, 0), [sg.SUNION])
+    p = sc.params.copy()
+    if field == "radius":
+        p[sc.left[sc.root], 3] = value
+    else:
+        p[sc.root, 0] = value
+    with pytest.raises(st.StError) as e:
+        st.prune_tree(sc.kind, sc.left, sc.right, p, sc.root, [])
+    assert e.value.code == st.ST_E_INVALID
+
+
+def test_flatten_rejects_too_deep_tree():
+    # left comb of 33 leaves: depth 32 > 31
+    shape = 0
+    for _ in range(32):
+        shape = (shape, 0)
+    sc = sg.tree_from_shape(shape, [sg.UNION] * 32)
+    with pytest.raises(st.StError) as e:
+        _prune(sc, [])
+    assert e.value.code == st.ST_E_TREE
+
+
+# ---------------------------------------------------------------------------
+# Pruned view semantics (Sections 7-9): expected view computed recursively
+# from the paper's rules, independently of the library's LCA construction.
+ABSENT, UNUSED = "absent", "unused"
+IGNORE = {sg.UNION: 0, sg.SUNION: 0, sg.INTER: 3, sg.SINTER: 3, sg.DIFF: 2, sg.SDIFF: 2}
+
+
+def _expected(sc, active):
+    """Post-order list of the evaluated nodes and the view's Lipschitz bound.
+
+    A subtree without active primitive is absent.  An operator whose
+    operand usage bits b = (left used << 1) | right used satisfy
+    (~b & ignoreMod) == 0 takes op_type b, else 0 (Section 9):
+    3 evaluates the operator, 2 returns the left operand, 1 the right one,
+    0 returns +inf (the branch is unused)."""
+    act = set(int(a) for a in active)
+
+    def lipf(v):
+        if sc.kind[v] >= sg.SUNION:
+            k = float(sc.params[v, 0])
+            d = float(sc.params[v, 1]) if sc.params[v, 1] > 0 else 7 * k / 6
+            return 1 + k / (6 * d - k)
+        return 1.0
+
+    def rec(v):
+        if sc.kind[v] < 16:
+            return ([v], 1.0) if v in act else ABSENT
+        a, b = rec(sc.left[v]), rec(sc.right[v])
+        if a == ABSENT and b == ABSENT:
+            return ABSENT
+        lu = 0 if a in (ABSENT, UNUSED) else 1
+        ru = 0 if b in (ABSENT, UNUSED) else 1
+        bits = (lu << 1) | ru
+        im = IGNORE[int(sc.kind[v])]
+        op = bits if ((~bits & im) & 3) == 0 else 0
+        if op == 3:
+            return (a[0] + b[0] + [v], max(a[1], b[1]) * lipf(v))
+        if op == 2:
+            return a
+        if op == 1:
+            return b
+        return UNUSED
+
+    r = rec(sc.root)
+    if r in (ABSENT, UNUSED):
+        return [], 0.0
+    return r[0], r[1]
+
+
+def _shapes(n):
+    if n == 1:
+        yield 0
+        return
+    for k in range(1, n):
+        for a in _shapes(k):
+            for b in _shapes(n - k):
+                yield (a, b)
+
+
+OPS = [sg.UNION, sg.INTER, sg.DIFF, sg.SUNION, sg.SINTER, sg.SDIFF]
+
+
+@pytest.mark.parametrize("n_leaves", [1, 2, 3, 4, 5, 6])
+def test_prune_exhaustive_small_trees(n_leaves):
+    """Every tree shape with n leaves, several operator assignments, every
+    active subset."""
+    rng = np.random.default_rng(n_leaves)
+    cases = 0
+    for shape in _shapes(n_leaves):
+        n_ops = n_leaves - 1
+        assigns = [[op] * n_ops for op in OPS] if n_ops else [[]]
+        assigns += [list(rng.choice(OPS, n_ops)) for _ in range(4)] if n_ops else []
+        for ops in assigns:
+            sc = sg.tree_from_shape(shape, ops, seed=cases, k=float(rng.uniform(0.05, 0.3)))
+            prims = np.nonzero(sc.kind < 16)[0]
+            for mask in range(1 << n_leaves):
+                active = [int(prims[i]) for i in range(n_leaves) if mask >> i & 1]
+                got, lip = _prune(sc, active)
+                exp, elip = _expected(sc, active)
+                assert list(got) == exp, (shape, ops, active)
+                assert lip == pytest.approx(elip, rel=1e-6)
+                cases += 1
+    assert cases > 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_prune_random_larger_trees(seed):
+    rng = np.random.default_rng(100 + seed)
+    for rep in range(40):
+        n = int(rng.integers(7, 40))
+        sc = sg.random_small_tree(seed * 1000 + rep, n, ops=tuple(OPS))
+        prims = np.nonzero(sc.kind < 16)[0]
+        for _ in range(10):
+            active = [int(p) for p in prims if rng.random() < rng.uniform(0.1, 0.9)]
+            got, lip = _prune(sc, active)
+            exp, elip = _expected(sc, active)
+            assert list(got) == exp
+            assert lip == pytest.approx(elip, rel=1e-6)
+
+
+def test_prune_left_comb_union_only_keeps_active_operators():
+    """Left comb of unions (Section 7 inset): with k active primitives the
+    view holds those k primitives and k-1 operators, never the skipped ones."""
+    shape = 0
+    for _ in range(9):
+        shape = (shape, 0)
+    sc = sg.tree_from_shape(shape, [sg.SUNION] * 9)
+    prims = list(np.nonzero(sc.kind < 16)[0])
+    got, lip = _prune(sc, [prims[2], prims[7]])
+    assert len(got) == 3
+    assert lip == pytest.approx(7 / 6, rel=1e-6)
+
+
+def test_prune_intersection_with_lone_operand_is_unused():
+    """Section 9: an intersection with one active operand is ignored; a
+    difference without its left operand too; with only its left operand it
+    returns it."""
+    sc = sg.tree_from_shape((0, 0), [sg.SINTER])
+    a, b = sc.left[sc.root], sc.right[sc.root]
+    assert len(_prune(sc, [a])[0]) == 0
+    assert len(_prune(sc, [a, b])[0]) == 3
+    sc = sg.tree_from_shape((0, 0), [sg.SDIFF])
+    a, b = sc.left[sc.root], sc.right[sc.root]
+    assert list(_prune(sc, [a])[0]) == [a]
+    assert len(_prune(sc, [b])[0]) == 0

@@ -1,0 +1,190 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+from gpu_util import all_pixels, compare, gpu_render, sample_pixels
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09673_amd import st
+    st.lib()   # fails loudly without the built library
+
+
+def _report(name, r):
+    print(f"\n[{name}] " + " ".join(f"{k}={v}" for k, v in r.items() if k != "fail_idx"), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# field evaluation
+
+@pytest.mark.parametrize("make", [lambda: sg.config1(0), lambda: sg.config2(0), lambda: sg.random_small_tree(14, 9)],
+                         ids=["c1", "c2", "small"])
+def test_full_tree_field_matches_oracle(make):
+    """All primitives active: the pruned view is the whole tree and f_A = f."""
+    from paper_2304_09673_amd import st
+    sc = make()
+    s = st.Scene(sc)
+    osc = oracle.OracleScene(sc)
+    pts = np.random.default_rng(0).uniform(-1.3, 1.3, size=(4096, 3)).astype(np.float32)
+    f, g, used, view = s.debug_eval(pts, None, grad=True)
+    fo, go = osc.eval(pts.astype(np.float64), grad=True)
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    assert used == 1
+    assert len(view) == sc.n_nodes
+    err = np.abs(f - fo)
+    assert err.max() < 2e-5 * (1 + np.abs(fo).max()), err.max()
+    # gradients away from kinks
+    ok = np.linalg.norm(g - go, axis=1) < 1e-3
+    assert ok.mean() > 0.99
+
+
+@pytest.mark.parametrize("make", [lambda: sg.config2(1), lambda: sg.config2(2), lambda: sg.random_small_tree(21, 12)],
+                         ids=["c2s1", "c2s2", "small"])
+def test_pruned_field_sign_equivalence(make):
+    """Local equivalence (Section 3): with A the primitives whose volume of
+    interest contains p, sign f_A(p) = sign f(p); the device view equals the
+    host view of the same set."""
+    from paper_2304_09673_amd import st
+    sc = make()
+    s = st.Scene(sc)
+    osc = oracle.OracleScene(sc)
+    prims = osc.prim_ids()
+    rng = np.random.default_rng(1)
+    n_checked = 0
+    for _ in range(150):
+        p = rng.uniform(-1.2, 1.2, size=3)
+        act = [int(i) for i in prims if osc.in_voi(i, p)]
+        if not act:
+            continue
+        f, _, used, view = s.debug_eval(p[None].astype(np.float32), act)
+        host_view, _ = st.prune_tree(sc.kind, sc.left, sc.right, sc.params, sc.root, act)
+        assert list(view) == list(host_view)
+        fo = osc.eval(p[None])[0]
+        fa = float(f.cpu().numpy()[0])
+        if abs(fo) > 1e-4:
+            assert (fa > 0) == (fo > 0), (p, act, fa, fo)
+            n_checked += 1
+    assert n_checked > 20
+
+
+# ---------------------------------------------------------------------------
+# A-buffer
+
+@pytest.mark.parametrize("cfg,tile", [(1, 8), (2, 16), (2, 8), (2, 32)])
+def test_abuffer_covers_every_ray_interval(cfg, tile):
+    """Tile lists are a superset of the brute-force per-ray intervals: every
+    primitive whose volume of interest meets a pixel-centre ray of the tile is
+    listed with [z_in, z_out] covering that ray's interval; lists are sorted
+    by (z_in, primitive)."""
+    from paper_2304_09673_amd import st
+    sc = sg.config1(0, 128, 128) if cfg == 1 else sg.config2(0, 96, 80)
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera, st.default_tuning(tile=tile))
+    off, node, zin, zout = s.debug_abuffer()
+    osc = oracle.OracleScene(sc)
+    cam = sc.camera
+    px, py = sample_pixels(cam, 600, 5)
+    prims = osc.prim_ids()
+    z = osc.voi_intervals(cam, px + 0.5, py + 0.5, prims)
+    tiles_x = (cam.width + tile - 1) // tile
+    for r in range(px.shape[0]):
+        t = (py[r] // tile) * tiles_x + px[r] // tile
+        seg = slice(off[t], off[t + 1])
+        lst = {int(a): (float(b), float(c)) for a, b, c in zip(node[seg], zin[seg], zout[seg])}
+        for q, i in enumerate(prims):
+            z0, z1 = z[r, q]
+            if np.isnan(z0):
+                continue
+            assert int(i) in lst, (r, i)
+            a, b = lst[int(i)]
+            assert a <= z0 + 1e-5 and b >= z1 - 1e-5, (a, b, z0, z1)
+    # sorted by (z_in, primitive) per tile
+    for t in range(off.shape[0] - 1):
+        seg = slice(off[t], off[t + 1])
+        keys = list(zip(zin[seg].tolist(), node[seg].tolist()))
+        assert keys == sorted(keys)
+
+
+def test_abuffer_is_deterministic():
+    from paper_2304_09673_amd import st
+    sc = sg.config2(4, 128, 128)
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera)
+    a = s.debug_abuffer()
+    s.build_abuffer(sc.camera)
+    b = s.debug_abuffer()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# images
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_c1_full_image_parity(seed):
+    """16 spheres, compact smooth unions, 256x256, plain sphere tracing."""
+    sc = sg.config1(seed)
+    s, depth, normal, stats = gpu_render(sc)
+    px, py = all_pixels(sc.camera)
+    r = compare(sc, depth, normal, px, py)
+    _report(f"c1 seed {seed}", r)
+    print("stats", {k: stats[k] for k in ("rays", "hits", "unconverged", "field_evals", "subfrustums", "stalled")})
+    assert stats["stalled"] == 0
+    assert r["hits_oracle"] > 1000
+    assert r["fail"] == 0, r
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_c2_parity_tiles(tile):
+    """142 primitives, mixed compact operators, at 256x256 for every A-buffer
+    tile size (the image must not depend on it)."""
+    from paper_2304_09673_amd import st
+    sc = sg.config2(0, 256, 256)
+    s, depth, normal, stats = gpu_render(sc, st.default_tuning(tile=tile))
+    px, py = all_pixels(sc.camera)
+    r = compare(sc, depth, normal, px, py)
+    _report(f"c2 tile {tile}", r)
+    assert stats["stalled"] == 0
+    assert r["fail"] == 0, r
+
+
+def test_c2_full_resolution_sampled():
+    sc = sg.config2(1)
+    s, depth, normal, stats = gpu_render(sc)
+    px, py = sample_pixels(sc.camera, 20000, 11)
+    r = compare(sc, depth, normal, px, py)
+    _report("c2 1024^2 sampled", r)
+    assert r["fail"] == 0, r
+
+
+def test_c3_sampled():
+    """4096 primitives at 1920x1080, seeded ray sample."""
+    sc = sg.config3(0)
+    s, depth, normal, stats = gpu_render(sc)
+    px, py = sample_pixels(sc.camera, 3000, 12)
+    r = compare(sc, depth, normal, px, py)
+    _report("c3 sampled", r)
+    print("stats", stats)
+    assert stats["stalled"] == 0
+    assert r["fail"] == 0, r
+
+
+def test_trace_rejects_stale_camera():
+    from paper_2304_09673_amd import st
+    sc = sg.config1(0, 64, 64)
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera)
+    other = sg.Camera(width=64, height=64, eye=(0.0, 0.5, 4.0))
+    with pytest.raises(st.StError) as e:
+        s.trace(other)
+    assert e.value.code == st.ST_E_STALE
