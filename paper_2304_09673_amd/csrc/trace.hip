@@ -100,41 +100,38 @@ struct WaveLds {
 
 // ---------------------------------------------------------------------------
 // field of the pruned view at p (Algorithm 3: post-order stack machine).
-// The view entries are wave-uniform; `ent(j)` returns entry j as an SGPR.
-template <class T, class Ent>
-__device__ __forceinline__ T eval_view(const Ent& ent, int len, const NodePar* __restrict__ par, const P3<T>& p,
-                                       uint32_t& sm) {
+// The view entries are wave-uniform.  They are fetched 64 at a time from LDS
+// into one VGPR and read with readlane; this is a cross-lane read, so the
+// function must be called with every lane of the wave active (inactive rays
+// simply evaluate at their stale point and ignore the result).
+template <class T>
+__device__ __forceinline__ T eval_view(const uint32_t* view, int len_in, const NodePar* __restrict__ par,
+                                       uint32_t n_nodes, const P3<T>& p, uint32_t& sm) {
     T stk[kStack];
     T acc = cst(0.f, p.x);
     int sp = 0;
-    for (int j = 0; j < len; j++) {
-        uint32_t e = ent(j);
-        uint32_t kind = ventry_kind(e);
-        const float* q = par[ventry_node(e)].v;
-        // the index stays in [0, kStack) for any view (a well-formed view
-        // never leaves it: its depth is below the flatten limit)
-        if (kind <= ST_CAPSULE) {
-            if (j) { stk[sp & (kStack - 1)] = acc; sp++; }
-            acc = prim_eval<T>(kind, q, p);
-        } else {
-            sp--;
-            acc = op_eval<T>(kind, q, stk[sp & (kStack - 1)], acc, sm);
+    const int len = int(uni(uint32_t(len_in)));
+    for (int base = 0; base < len; base += 64) {
+        const uint32_t chunk = view[base + lane_id()];
+        const int cnt = int(uni(uint32_t(min(64, len - base))));
+        for (int jj = 0; jj < cnt; jj++) {
+            uint32_t e = rdlane(chunk, jj);
+            uint32_t kind = ventry_kind(e);
+            // clamp: a malformed entry reads a wrong node, never outside the array
+            const float* q = par[min(ventry_node(e), n_nodes - 1u)].v;
+            // the index stays in [0, kStack) for any view (a well-formed view
+            // never leaves it: its depth is below the flatten limit)
+            if (kind <= ST_CAPSULE) {
+                if (base + jj) { stk[sp & (kStack - 1)] = acc; sp++; }
+                acc = prim_eval<T>(kind, q, p);
+            } else {
+                sp--;
+                acc = op_eval<T>(kind, q, stk[sp & (kStack - 1)], acc, sm);
+            }
         }
     }
     return acc;
 }
-
-// view entries held in VGPR chunks: lane l of chunk c has entry 64c + l
-template <int NCH>
-struct ChunkEnt {
-    uint32_t c[NCH];
-    __device__ __forceinline__ uint32_t operator()(int j) const { return rdlane(c[j >> 6], j & 63); }
-};
-// view entries read from LDS with a uniform address
-struct LdsEnt {
-    const uint32_t* v;
-    __device__ __forceinline__ uint32_t operator()(int j) const { return uni(v[j]); }
-};
 
 // ---------------------------------------------------------------------------
 // device context of the shared bottom-up pass (st_prune.h): per-position
@@ -187,10 +184,12 @@ struct LdsPruneCtx {
     uint32_t s_nu = 0, s_start = 0, s_kill = 0;
     float s_L = 0.f;
     uint32_t* view;
-    __device__ uint32_t node(int j) const { return uni(vsn[j]); }
-    __device__ uint32_t blob(int j) const { return uni(blobs[uni(vsn[j])]); }
-    __device__ uint32_t kill(int j) const { return uni(kills[uni(vsn[j])]); }
-    __device__ float lipf(int j) const { return unif(par[uni(vsn[j])].v[4]); }
+    uint32_t n_nodes;
+    __device__ uint32_t at(int j) const { return min(uni(vsn[j]), n_nodes - 1u); }
+    __device__ uint32_t node(int j) const { return at(j); }
+    __device__ uint32_t blob(int j) const { return uni(blobs[at(j)]); }
+    __device__ uint32_t kill(int j) const { return uni(kills[at(j)]); }
+    __device__ float lipf(int j) const { return unif(par[at(j)].v[4]); }
     __device__ void spush(int sp, uint32_t nu, uint32_t start, float L, uint32_t k) {
         s_nu = wrlane(nu, sp, s_nu);
         s_start = wrlane(start, sp, s_start);
@@ -263,7 +262,12 @@ __device__ PruneResult build_view(const TraceArgs& A, WaveLds<MA>& S, int buf, i
         while (np2 < nl) np2 <<= 1;
         for (int i = lane; i < np2; i += 64) {
             uint32_t x = 0xFFFFFFFFu;
-            if (i < nl) x = lca_query(A.rmq, A.n_nodes, act[i], act[i + 1]);
+            if (i < nl) {
+                // a < b always holds for a duplicate-free sorted set; the
+                // guard keeps a corrupted set from reading outside the table
+                uint32_t a = act[i], b = act[i + 1];
+                x = (a < b && b < A.n_nodes) ? lca_query(A.rmq, A.n_nodes, a, b) : 0u;
+            }
             S.lca[i] = x;
         }
         // 2. sort them
@@ -288,7 +292,7 @@ __device__ PruneResult build_view(const TraceArgs& A, WaveLds<MA>& S, int buf, i
 #pragma unroll
         for (int q = 0; q < NCH; q++) {
             int j = q * 64 + lane;
-            uint32_t v = j < m ? S.vs[j] : 0u;
+            uint32_t v = j < m ? min(S.vs[j], A.n_nodes - 1u) : 0u;
             c.cn[q] = v;
             c.cb[q] = j < m ? A.blob[v] : 0u;
             c.ck[q] = j < m ? A.kill[v] : kNoKill;
@@ -299,6 +303,7 @@ __device__ PruneResult build_view(const TraceArgs& A, WaveLds<MA>& S, int buf, i
         return r;
     } else {
         LdsPruneCtx c;
+        c.n_nodes = A.n_nodes;
         c.vsn = S.vs;
         c.blobs = A.blob;
         c.kills = A.kill;
@@ -402,23 +407,28 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             k = ~okm == 0ull ? 64 : int(__builtin_ctzll(~okm));
             if (k > 0) {
                 // merge the k new primitives (lanes 0..k-1) into the sorted active list
+                // (cross-lane reads stay outside the divergent stores)
                 int nb = buf ^ 1;
                 for (int b = 0; b < n; b += 64) {
                     int s = b + lane;
-                    if (s < n) {
-                        uint32_t a = S.act[buf][s];
-                        int less = 0;
-                        for (int q = 0; q < k; q++) less += rdlane(nd, q) < a ? 1 : 0;
+                    bool in_s = s < n;
+                    uint32_t a = in_s ? S.act[buf][s] : 0xFFFFFFFFu;
+                    float az = in_s ? S.ze[buf][s] : 0.f;
+                    int less = 0;
+                    for (int q = 0; q < k; q++) less += rdlane(nd, q) < a ? 1 : 0;
+                    if (in_s) {
                         S.act[nb][s + less] = a;
-                        S.ze[nb][s + less] = S.ze[buf][s];
+                        S.ze[nb][s + less] = az;
                     }
                 }
-                if (lane < k) {
+                {
                     int pos = lower_count(S.act[buf], n, nd);
                     int less = 0;
                     for (int q = 0; q < k; q++) less += rdlane(nd, q) < nd ? 1 : 0;
-                    S.act[nb][pos + less] = nd;
-                    S.ze[nb][pos + less] = zo;
+                    if (lane < k) {
+                        S.act[nb][pos + less] = nd;
+                        S.ze[nb][pos + less] = zo;
+                    }
                 }
                 // the new ones also extend the reach
                 float nz_ = lane < k ? zo : -__builtin_inff();
@@ -443,7 +453,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             if (!done && t < t1) { t = t1; tp_ok = false; }
             continue;
         }
-        const int len = pr.len;
+        const int len = int(uni(uint32_t(pr.len)));
         view_nodes += uint64_t(len);
         const float L = A.lip_fixed > 0.f ? A.lip_fixed : pr.lip;
         const float invL = 1.0f / L;
@@ -464,25 +474,15 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
         float ra = 0.f, fa = 0.f, rb = 0.f, fb = 0.f;   // refinement bracket
         int nref = 0, side = 0;
         uint32_t ev_here = 0;
-        constexpr int NCH = (2 * MA + 63) / 64;
-        ChunkEnt<kWide ? 1 : NCH> ce;
-        if constexpr (!kWide) {
-#pragma unroll
-            for (int q = 0; q < NCH; q++) {
-                int j = q * 64 + lane;
-                ce.c[q] = j < len ? S.view[j] : 0u;
-            }
-        }
-        LdsEnt le{S.view};
         while (true) {
             bool act = mode == M_TRACE || mode == M_REFINE;
             if (ballot(act) == 0) break;
-            float v = 0.f;
+            P3<float> p{fmaf(t, ray.d[0], ray.o[0]), fmaf(t, ray.d[1], ray.o[1]), fmaf(t, ray.d[2], ray.o[2])};
+            uint32_t sm_l = 0;
+            float v = eval_view<float>(S.view, len, A.par, A.n_nodes, p, sm_l);
             if (act) {
-                P3<float> p{fmaf(t, ray.d[0], ray.o[0]), fmaf(t, ray.d[1], ray.o[1]), fmaf(t, ray.d[2], ray.o[2])};
-                if constexpr (kWide) v = eval_view<float>(le, len, A.par, p, smooth);
-                else v = eval_view<float>(ce, len, A.par, p, smooth);
                 ev_here++;
+                smooth += sm_l;
             }
             if (mode == M_TRACE) {
                 steps++;
@@ -546,13 +546,12 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
         uint32_t g_here = __popcll(ballot(mode == M_GRAD));
         for (int q = 0; q < 4; q++) gnode_cnt[q] += uint64_t(g_here) * kc[q];
         if (g_here != 0) {
+            float th = mode == M_GRAD ? t_hit : t;
+            P3<Dual> p = make_point(fmaf(th, ray.d[0], ray.o[0]), fmaf(th, ray.d[1], ray.o[1]),
+                                    fmaf(th, ray.d[2], ray.o[2]), Dual{});
+            uint32_t sm_g = 0;
+            Dual g = eval_view<Dual>(S.view, len, A.par, A.n_nodes, p, sm_g);
             if (mode == M_GRAD) {
-                P3<Dual> p = make_point(fmaf(t_hit, ray.d[0], ray.o[0]), fmaf(t_hit, ray.d[1], ray.o[1]),
-                                        fmaf(t_hit, ray.d[2], ray.o[2]), Dual{});
-                Dual g;
-                uint32_t sm_g = 0;
-                if constexpr (kWide) g = eval_view<Dual>(le, len, A.par, p, sm_g);
-                else g = eval_view<Dual>(ce, len, A.par, p, sm_g);
                 float gn = sqrtf(g.gx * g.gx + g.gy * g.gy + g.gz * g.gz);
                 float ig = gn > 0.f ? 1.0f / gn : 0.f;
                 nx = g.gx * ig; ny = g.gy * ig; nz = g.gz * ig;
@@ -706,7 +705,6 @@ __global__ void __launch_bounds__(64) debug_eval_kernel(TraceArgs A, const uint3
         root_used[2] = __float_as_int(pr.lip);
     }
     for (int j = lane; j < pr.len; j += 64) view_out[j] = S.view[j];
-    LdsEnt le{S.view};
     for (int b = int(blockIdx.x) * 64; b < n_pts; b += int(gridDim.x) * 64) {
         int i = b + lane;
         bool in = i < n_pts;
@@ -721,12 +719,12 @@ __global__ void __launch_bounds__(64) debug_eval_kernel(TraceArgs A, const uint3
         if (out_g) {
             P3<Dual> p = make_point(x, y, z, Dual{});
             uint32_t sm = 0;
-            Dual g = eval_view<Dual>(le, pr.len, A.par, p, sm);
+            Dual g = eval_view<Dual>(S.view, pr.len, A.par, A.n_nodes, p, sm);
             if (in) { out_f[i] = g.v; out_g[3 * i] = g.gx; out_g[3 * i + 1] = g.gy; out_g[3 * i + 2] = g.gz; }
         } else {
             P3<float> p{x, y, z};
             uint32_t sm = 0;
-            float v = eval_view<float>(le, pr.len, A.par, p, sm);
+            float v = eval_view<float>(S.view, pr.len, A.par, A.n_nodes, p, sm);
             if (in) out_f[i] = v;
         }
     }
