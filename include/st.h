@@ -206,6 +206,19 @@ st_status st_trace(st_scene *s, const st_camera *cam, float *out_depth, float *o
                    st_stats *out_stats, void *stream);
 
 /*
+ * st_trace_ex -- st_trace with a per-pixel record (the paper's heat maps of
+ * field evaluations per ray, Figure 1 and the Temple figure).
+ *   out_info (device, uint32[H*W], may be NULL):
+ *     bits 0-15  field evaluations of the ray (saturating),
+ *     bit 16     hit, bit 17 stopped by max_steps (unconverged),
+ *     bit 18     crossing refined by bracketing,
+ *     bits 20-31 subfrustums the ray was traced in (saturating).
+ * Other arguments, ownership and errors as st_trace.
+ */
+st_status st_trace_ex(st_scene *s, const st_camera *cam, float *out_depth, float *out_normal,
+                      uint32_t *out_info, st_stats *out_stats, void *stream);
+
+/*
  * st_debug_eval_field -- test hook: evaluates the pruned field f_A of a given
  * active primitive set at points (pruning semantics of Sections 7-9).  The
  * view is built by the same device code the tracer uses.

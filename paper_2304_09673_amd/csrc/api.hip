@@ -124,7 +124,7 @@ st_status st_default_tuning(st_tuning* t) {
     t->sub_depth = 1.0f / 20.0f;
     t->max_new = 6;
     t->eps = 1e-4f;
-    t->max_steps = 128;
+    t->max_steps = 1024;
     t->refine_iters = 8;
     t->step_mode = ST_STEP_PLAIN;
     t->omega = 1.7f;
@@ -267,13 +267,18 @@ st_status st_build_abuffer(st_scene* s, const st_camera* cam, const st_tuning* t
 
 st_status st_trace(st_scene* s, const st_camera* cam, float* out_depth, float* out_normal, st_stats* out_stats,
                    void* stream_v) {
+    return st_trace_ex(s, cam, out_depth, out_normal, nullptr, out_stats, stream_v);
+}
+
+st_status st_trace_ex(st_scene* s, const st_camera* cam, float* out_depth, float* out_normal, uint32_t* out_info,
+                      st_stats* out_stats, void* stream_v) {
     if (!s || !cam || !out_depth || !out_normal) { set_error("trace: NULL argument"); return ST_E_INVALID; }
     hipStream_t stream = (hipStream_t)stream_v;
     if (!s->ab_valid || std::memcmp(cam, &s->ab_cam, sizeof(st_camera)) != 0) {
         set_error("trace: the A-buffer was not built for this camera");
         return ST_E_STALE;
     }
-    st_status r = trace_device(s, s->ab_tune, out_depth, out_normal, stream);
+    st_status r = trace_device(s, s->ab_tune, out_depth, out_normal, out_info, stream);
     if (r != ST_OK) return r;
     if (out_stats) {
         unsigned long long h[kStatCount];

@@ -75,7 +75,8 @@ st_status launch_voi(st_scene* s, hipStream_t stream);
 st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stream);
 
 // trace.hip
-st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, hipStream_t stream);
+st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
+                       hipStream_t stream);
 st_status debug_eval_device(const st_scene* s, const uint32_t* active_post, int n_active,
                             const float* pts, int n_pts, float* out_f, float* out_grad,
                             int* root_used, hipStream_t stream);

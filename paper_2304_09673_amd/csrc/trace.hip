@@ -80,6 +80,7 @@ struct TraceArgs {
     int max_steps, refine_iters, max_new, step_mode;
     float* out_depth;
     float* out_normal;
+    uint32_t* out_info;
     unsigned long long* stats;
 };
 
@@ -339,7 +340,8 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
     int steps = 0;
     uint32_t evals = 0, gevals = 0, smooth = 0;
     float tp = 0.f, vp = 0.f, hp = 0.f;   // last positive point, its value, probe step
-    bool tp_ok = false, last_safe = true;
+    bool tp_ok = false, last_safe = true, refined = false;
+    uint32_t n_sub_lane = 0;
 
     // wave state (uniform)
     const uint32_t e0 = uni(A.tile_off[tile]), e1 = uni(A.tile_off[tile + 1]);
@@ -469,7 +471,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
         int mode = M_IDLE;
         if (!done) {
             if (t < t0) { t = t0; tp_ok = false; }
-            if (t < t1) mode = M_TRACE;
+            if (t < t1) { mode = M_TRACE; n_sub_lane++; }
         }
         float ra = 0.f, fa = 0.f, rb = 0.f, fb = 0.f;   // refinement bracket
         int nref = 0, side = 0;
@@ -495,6 +497,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
                         ra = tp; fa = vp; rb = t; fb = v;
                         nref = 0; side = 0;
                         mode = M_REFINE;
+                        refined = true;
                         t = ra + (rb - ra) * (fa / (fa - fb));
                         if (!(t > ra && t < rb)) t = 0.5f * (ra + rb);
                     }
@@ -572,6 +575,11 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
         A.out_normal[3 * pix + 0] = hit ? nx : 0.f;
         A.out_normal[3 * pix + 1] = hit ? ny : 0.f;
         A.out_normal[3 * pix + 2] = hit ? nz : 0.f;
+        if (A.out_info) {
+            uint32_t e = min(evals + gevals, 0xFFFFu);
+            A.out_info[pix] = e | (hit ? 1u << 16 : 0u) | (unconv ? 1u << 17 : 0u) | (refined ? 1u << 18 : 0u) |
+                              (min(n_sub_lane, 0xFFFu) << 20);
+        }
     }
     // counters (one atomic per counter per wave)
     uint32_t rays = __popcll(ballot(valid));
@@ -634,7 +642,8 @@ __global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A) {
 constexpr int kMaFast = 128;
 constexpr int kMaWide = 1024;
 
-st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, hipStream_t stream) {
+st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
+                       hipStream_t stream) {
     TraceArgs A;
     A.blob = s->d_blob;
     A.par = s->d_par;
@@ -663,6 +672,7 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
     A.step_mode = t.step_mode;
     A.out_depth = depth;
     A.out_normal = normal;
+    A.out_info = info;
     A.stats = s->d_stats;
     hipError_t e = hipMemsetAsync(s->d_stats, 0, kStatCount * 8, stream);
     if (e != hipSuccess) return device_error(e, "memset stats");

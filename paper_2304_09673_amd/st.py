@@ -20,7 +20,7 @@ ST_STEP_PLAIN, ST_STEP_OVERRELAX, ST_STEP_LEARNED = 0, 1, 2
 # every symbol include/st.h declares
 EXPORTS = (
     "st_status_str", "st_last_error", "st_default_tuning", "st_flatten_blobtree", "st_scene_destroy",
-    "st_scene_get_info", "st_build_abuffer", "st_trace", "st_debug_eval_field", "st_debug_prune_tree",
+    "st_scene_get_info", "st_build_abuffer", "st_trace", "st_trace_ex", "st_debug_eval_field", "st_debug_prune_tree",
     "st_debug_abuffer",
 )
 
@@ -96,6 +96,7 @@ def lib():
         L.st_scene_get_info.argtypes = [vp, C.POINTER(StSceneInfo)]
         L.st_build_abuffer.argtypes = [vp, C.POINTER(StCamera), C.POINTER(StTuning), vp]
         L.st_trace.argtypes = [vp, C.POINTER(StCamera), vp, vp, C.POINTER(StStats), vp]
+        L.st_trace_ex.argtypes = [vp, C.POINTER(StCamera), vp, vp, vp, C.POINTER(StStats), vp]
         L.st_debug_eval_field.argtypes = [vp, vp, i32, vp, i32, vp, vp, C.POINTER(i32), vp, i32, C.POINTER(i32), vp]
         L.st_debug_prune_tree.argtypes = [C.POINTER(StNode), i32, i32, vp, i32, vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]
         L.st_debug_abuffer.argtypes = [vp, vp, sz, vp, sz, C.POINTER(i32), C.POINTER(i64), vp]
@@ -189,8 +190,9 @@ class Scene:
         _check(lib().st_build_abuffer(self._h, C.byref(self._cam), C.byref(tuning) if tuning else None,
                                       _stream_ptr(stream)))
 
-    def trace(self, camera=None, depth=None, normal=None, stats: bool = True, stream=None):
-        """Returns (depth[H,W], normal[H,W,3], stats dict or None) as torch CUDA tensors."""
+    def trace(self, camera=None, depth=None, normal=None, stats: bool = True, stream=None, info=None):
+        """Returns (depth[H,W], normal[H,W,3], stats dict or None) as torch CUDA tensors.
+        info: optional int32/uint32 CUDA tensor [H,W] receiving the per-pixel record."""
         import torch
         cam = make_camera(camera) if camera is not None else self._cam
         W, H = cam.width, cam.height
@@ -200,9 +202,12 @@ class Scene:
             normal = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
         assert depth.is_cuda and depth.dtype == torch.float32 and depth.numel() == H * W and depth.is_contiguous()
         assert normal.is_cuda and normal.dtype == torch.float32 and normal.numel() == 3 * H * W and normal.is_contiguous()
+        if info is not None:
+            assert info.is_cuda and info.element_size() == 4 and info.numel() == H * W and info.is_contiguous()
         st = StStats() if stats else None
-        _check(lib().st_trace(self._h, C.byref(cam), C.c_void_p(depth.data_ptr()), C.c_void_p(normal.data_ptr()),
-                              C.byref(st) if st is not None else None, _stream_ptr(stream)))
+        _check(lib().st_trace_ex(self._h, C.byref(cam), C.c_void_p(depth.data_ptr()), C.c_void_p(normal.data_ptr()),
+                                 C.c_void_p(info.data_ptr()) if info is not None else None,
+                                 C.byref(st) if st is not None else None, _stream_ptr(stream)))
         return depth, normal, (st.as_dict() if st is not None else None)
 
     def debug_eval(self, pts, active=None, grad: bool = False, stream=None):

@@ -39,7 +39,7 @@ def test_status_strings_and_default_tuning():
     # the paper's defaults (Implementation details): 8x8 tiles are the trace
     # granularity; d = 1/20 of scene depth, <= 6 new primitives per fetch
     assert abs(t.sub_depth - 0.05) < 1e-7 and t.max_new == 6
-    assert t.eps == pytest.approx(1e-4) and t.max_steps == 128
+    assert t.eps == pytest.approx(1e-4) and t.max_steps == 1024
     assert abs(t.omega - 1.7) < 1e-6
 
 
