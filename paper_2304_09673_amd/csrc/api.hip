@@ -120,7 +120,7 @@ st_status st_default_tuning(st_tuning* t) {
     if (!t) { set_error("NULL tuning"); return ST_E_INVALID; }
     std::memset(t, 0, sizeof(*t));
     t->tile = 16;
-    t->max_active = 128;
+    t->max_active = 256;
     t->sub_depth = 1.0f / 20.0f;
     t->max_new = 6;
     t->eps = 1e-4f;
@@ -254,7 +254,7 @@ st_status st_build_abuffer(st_scene* s, const st_camera* cam, const st_tuning* t
     }
     s->z_min = float(std::max(zmin, 0.0));
     s->z_max = float(std::max(zmax, 0.0));
-    s->ab_ma_fast = std::min(t.max_active, 128);
+    s->ab_ma_fast = std::min(t.max_active, 256);
     s->ab_ma_wide = 1024;
     s->ab_valid = false;
     r = build_abuffer_device(s, t, stream);

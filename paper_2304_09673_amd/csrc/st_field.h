@@ -22,6 +22,11 @@ struct Dual {
     float v, gx, gy, gz;
 };
 
+// Node parameters are read through the constant address space: the addresses
+// are wave-uniform and the data is read-only while tracing, so the loads
+// become scalar loads into SGPRs instead of per-lane vector copies.
+typedef __attribute__((address_space(4))) const float cfloat;
+
 // ---- scalar helpers, overloaded for float and Dual ---------------------------
 __device__ __forceinline__ float val(float a) { return a; }
 __device__ __forceinline__ float val(const Dual& a) { return a.v; }
@@ -80,13 +85,13 @@ __device__ __forceinline__ P3<Dual> make_point(float x, float y, float z, const 
 
 // ---- primitives -----------------------------------------------------------
 template <class T>
-__device__ __forceinline__ T prim_sphere(const float* q, const P3<T>& p) {
+__device__ __forceinline__ T prim_sphere(const cfloat* q, const P3<T>& p) {
     T dx = p.x - q[0], dy = p.y - q[1], dz = p.z - q[2];
     return sqrt_(dx * dx + dy * dy + dz * dz) - q[3];
 }
 
 template <class T>
-__device__ __forceinline__ T prim_box(const float* q, const P3<T>& p) {
+__device__ __forceinline__ T prim_box(const cfloat* q, const P3<T>& p) {
     T dx = p.x - q[0], dy = p.y - q[1], dz = p.z - q[2];
     T l0 = fabs_(dx * q[4] + dy * q[5] + dz * q[6]) - q[7];
     T l1 = fabs_(dx * q[8] + dy * q[9] + dz * q[10]) - q[11];
@@ -98,7 +103,7 @@ __device__ __forceinline__ T prim_box(const float* q, const P3<T>& p) {
 }
 
 template <class T>
-__device__ __forceinline__ T prim_capsule(const float* q, const P3<T>& p) {
+__device__ __forceinline__ T prim_capsule(const cfloat* q, const P3<T>& p) {
     T ax = p.x - q[0], ay = p.y - q[1], az = p.z - q[2];
     T h = clamp01_((ax * q[4] + ay * q[5] + az * q[6]) * q[7]);
     T wx = ax - h * q[4], wy = ay - h * q[5], wz = az - h * q[6];
@@ -114,7 +119,7 @@ __device__ __forceinline__ T disp_(const T& diff, const T& K) {
 }
 
 template <class T>
-__device__ __forceinline__ T op_eval(uint32_t kind, const float* q, const T& a, const T& b, uint32_t& sm) {
+__device__ __forceinline__ T op_eval(uint32_t kind, const cfloat* q, const T& a, const T& b, uint32_t& sm) {
     switch (kind) {
     case ST_UNION: return fmin_(a, b);
     case ST_INTER: return fmax_(a, b);
@@ -161,7 +166,7 @@ __device__ __forceinline__ T op_eval(uint32_t kind, const float* q, const T& a, 
 }
 
 template <class T>
-__device__ __forceinline__ T prim_eval(uint32_t kind, const float* q, const P3<T>& p) {
+__device__ __forceinline__ T prim_eval(uint32_t kind, const cfloat* q, const P3<T>& p) {
     if (kind == ST_SPHERE) return prim_sphere(q, p);
     if (kind == ST_BOX) return prim_box(q, p);
     return prim_capsule(q, p);

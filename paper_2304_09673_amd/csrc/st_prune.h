@@ -61,7 +61,7 @@ struct PruneResult {
 // node's subtree, Lipschitz bound of the subtree, the node's nearest killing
 // ancestor.
 template <class Ctx>
-HD PruneResult prune_pass(Ctx& c, int m) {
+__host__ __device__ inline PruneResult prune_pass(Ctx& c, int m) {
     int sp = 0;
     int cur = 0;
     for (int j = 0; j < m; j++) {

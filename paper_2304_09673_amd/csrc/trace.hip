@@ -21,10 +21,11 @@
 // sign-equivalent to the full field inside the subfrustum.
 //
 // Stepping: the safe step is f/L with L the proven Lipschitz bound of the
-// view.  Once the safe step falls below eps the ray probes forward with
-// doubling steps from eps (a grazing ray is not stalled), a sign change is
-// bracketed and refined by regula falsi (Illinois), and the normal is the
-// normalised forward-mode gradient of the view at the root.
+// view.  Once the safe step falls below eps the ray probes forward by the
+// secant estimate of the distance to the root (at least eps, growing at most
+// 4x per probe); a sign change is bracketed and refined by regula falsi
+// (Illinois), and the normal is the normalised forward-mode gradient of the
+// view at the root.
 #include <algorithm>
 
 #include "st_field.h"
@@ -105,10 +106,10 @@ struct WaveLds {
 // into one VGPR and read with readlane; this is a cross-lane read, so the
 // function must be called with every lane of the wave active (inactive rays
 // simply evaluate at their stale point and ignore the result).
-template <class T>
+template <class T, int KS>
 __device__ __forceinline__ T eval_view(const uint32_t* view, int len_in, const NodePar* __restrict__ par,
                                        uint32_t n_nodes, const P3<T>& p, uint32_t& sm) {
-    T stk[kStack];
+    T stk[KS];
     T acc = cst(0.f, p.x);
     int sp = 0;
     const int len = int(uni(uint32_t(len_in)));
@@ -119,15 +120,15 @@ __device__ __forceinline__ T eval_view(const uint32_t* view, int len_in, const N
             uint32_t e = rdlane(chunk, jj);
             uint32_t kind = ventry_kind(e);
             // clamp: a malformed entry reads a wrong node, never outside the array
-            const float* q = par[min(ventry_node(e), n_nodes - 1u)].v;
-            // the index stays in [0, kStack) for any view (a well-formed view
-            // never leaves it: its depth is below the flatten limit)
+            const cfloat* q = (const cfloat*)(par[min(ventry_node(e), n_nodes - 1u)].v);
+            // the index stays in [0, KS) for any view; a well-formed view never
+            // leaves it (KS is at least the tree depth)
             if (kind <= ST_CAPSULE) {
-                if (base + jj) { stk[sp & (kStack - 1)] = acc; sp++; }
+                if (base + jj) { stk[sp & (KS - 1)] = acc; sp++; }
                 acc = prim_eval<T>(kind, q, p);
             } else {
                 sp--;
-                acc = op_eval<T>(kind, q, stk[sp & (kStack - 1)], acc, sm);
+                acc = op_eval<T>(kind, q, stk[sp & (KS - 1)], acc, sm);
             }
         }
     }
@@ -135,20 +136,40 @@ __device__ __forceinline__ T eval_view(const uint32_t* view, int len_in, const N
 }
 
 // ---------------------------------------------------------------------------
-// device context of the shared bottom-up pass (st_prune.h): per-position
-// data held in VGPR chunks read with readlane, the pass stack held across
-// lanes (lane k = stack slot k) with writelane/readlane.
-template <int NCH>
+// device context of the shared bottom-up pass (st_prune.h).  The pass walks
+// positions j = 0, 1, ... in order; the data of the current block of 64
+// positions sits in four VGPRs (lane l holds position 64c + l) and is read with
+// readlane; crossing into the next block reloads it.  The pass stack is held
+// across lanes (lane k = stack slot k).  The pass runs with every lane active.
 struct DevPruneCtx {
-    uint32_t cn[NCH], cb[NCH], ck[NCH];
-    float cl[NCH];
+    const uint32_t* vs;
+    const uint32_t* gblob;
+    const uint32_t* gkill;
+    const NodePar* gpar;
+    uint32_t n_nodes;
+    int m;
+    int cur = -1;
+    uint32_t cn = 0, cb = 0, ck = 0;
+    float cl = 1.f;
     uint32_t s_nu = 0, s_start = 0, s_kill = 0;
     float s_L = 0.f;
     uint32_t* view;
-    __device__ uint32_t node(int j) const { return rdlane(cn[j >> 6], j & 63); }
-    __device__ uint32_t blob(int j) const { return rdlane(cb[j >> 6], j & 63); }
-    __device__ uint32_t kill(int j) const { return rdlane(ck[j >> 6], j & 63); }
-    __device__ float lipf(int j) const { return rdlanef(cl[j >> 6], j & 63); }
+    __device__ void ensure(int j) {
+        int c = j >> 6;
+        if (c != cur) {
+            cur = c;
+            int p = c * 64 + lane_id();
+            uint32_t v = p < m ? min(vs[p], n_nodes - 1u) : 0u;
+            cn = v;
+            cb = p < m ? gblob[v] : 0u;
+            ck = p < m ? gkill[v] : kNoKill;
+            cl = p < m ? gpar[v].v[4] : 1.f;
+        }
+    }
+    __device__ uint32_t node(int j) { ensure(j); return rdlane(cn, j & 63); }
+    __device__ uint32_t blob(int j) { ensure(j); return rdlane(cb, j & 63); }
+    __device__ uint32_t kill(int j) { ensure(j); return rdlane(ck, j & 63); }
+    __device__ float lipf(int j) { ensure(j); return rdlanef(cl, j & 63); }
     __device__ void spush(int sp, uint32_t nu, uint32_t start, float L, uint32_t k) {
         s_nu = wrlane(nu, sp, s_nu);
         s_start = wrlane(start, sp, s_start);
@@ -287,18 +308,14 @@ __device__ PruneResult build_view(const TraceArgs& A, WaveLds<MA>& S, int buf, i
     wave_sync();
     // 4. bottom-up pass (usage, killing ancestors, compaction, Lipschitz)
     if constexpr (!kWide) {
-        constexpr int NCH = (2 * MA + 63) / 64;
-        DevPruneCtx<NCH> c;
+        DevPruneCtx c;
+        c.vs = S.vs;
+        c.gblob = A.blob;
+        c.gkill = A.kill;
+        c.gpar = A.par;
+        c.n_nodes = A.n_nodes;
+        c.m = m;
         c.view = S.view;
-#pragma unroll
-        for (int q = 0; q < NCH; q++) {
-            int j = q * 64 + lane;
-            uint32_t v = j < m ? min(S.vs[j], A.n_nodes - 1u) : 0u;
-            c.cn[q] = v;
-            c.cb[q] = j < m ? A.blob[v] : 0u;
-            c.ck[q] = j < m ? A.kill[v] : kNoKill;
-            c.cl[q] = j < m ? A.par[v].v[4] : 1.f;
-        }
         PruneResult r = prune_pass(c, m);
         wave_sync();
         return r;
@@ -320,7 +337,7 @@ __device__ PruneResult build_view(const TraceArgs& A, WaveLds<MA>& S, int buf, i
 // Lane modes inside a subfrustum
 enum { M_IDLE = 0, M_TRACE = 1, M_REFINE = 2, M_GRAD = 3 };
 
-template <int MA, bool kWide>
+template <int MA, bool kWide, int KS>
 __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, uint32_t sub,
                             unsigned long long* cnt) {
     const int lane = lane_id();
@@ -465,7 +482,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             uint32_t kd = ventry_kind(S.view[j]);
             kc[kd <= ST_CAPSULE ? kd : 3]++;
         }
-        for (int q = 0; q < 4; q++) kc[q] = wave_sum(kc[q]);
+        for (int q = 0; q < 4; q++) kc[q] = uni(wave_sum(kc[q]));
 
         // -- trace every ray's span of the subfrustum
         int mode = M_IDLE;
@@ -481,7 +498,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             if (ballot(act) == 0) break;
             P3<float> p{fmaf(t, ray.d[0], ray.o[0]), fmaf(t, ray.d[1], ray.o[1]), fmaf(t, ray.d[2], ray.o[2])};
             uint32_t sm_l = 0;
-            float v = eval_view<float>(S.view, len, A.par, A.n_nodes, p, sm_l);
+            float v = eval_view<float, KS>(S.view, len, A.par, A.n_nodes, p, sm_l);
             if (act) {
                 ev_here++;
                 smooth += sm_l;
@@ -505,7 +522,12 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
                     float s = v * invL;
                     bool safe = s >= A.eps;
                     if (!safe) {
-                        s = (hp > 0.f && tp_ok && v < vp) ? 2.f * hp : A.eps;
+                        // probe: the secant estimate of the distance to the
+                        // root (it under-estimates the entry of a convex dip,
+                        // so a thin sliver is not jumped), at least eps, at
+                        // most 4x the previous probe
+                        float sec = (tp_ok && vp > v) ? v * (t - tp) / (vp - v) : 0.f;
+                        s = fminf(fmaxf(sec, A.eps), 4.f * fmaxf(hp, A.eps));
                         hp = s;
                     } else {
                         hp = 0.f;
@@ -553,7 +575,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             P3<Dual> p = make_point(fmaf(th, ray.d[0], ray.o[0]), fmaf(th, ray.d[1], ray.o[1]),
                                     fmaf(th, ray.d[2], ray.o[2]), Dual{});
             uint32_t sm_g = 0;
-            Dual g = eval_view<Dual>(S.view, len, A.par, A.n_nodes, p, sm_g);
+            Dual g = eval_view<Dual, KS>(S.view, len, A.par, A.n_nodes, p, sm_g);
             if (mode == M_GRAD) {
                 float gn = sqrtf(g.gx * g.gx + g.gy * g.gy + g.gz * g.gz);
                 float ig = gn > 0.f ? 1.0f / gn : 0.f;
@@ -563,7 +585,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
                 gevals++;
             }
         }
-        uint32_t tot = wave_sum(ev_here);
+        uint32_t tot = uni(wave_sum(ev_here));
         evals += ev_here;
         for (int q = 0; q < 4; q++) node_cnt[q] += uint64_t(tot) * kc[q];
     }
@@ -607,7 +629,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
 // ---------------------------------------------------------------------------
 // Fast path: one wave per 8x8 block, 4 waves per workgroup, LDS view of
 // capacity MA.  Blocks of tiles that overlap more than MA go to the wide path.
-template <int MA>
+template <int MA, int KS>
 __global__ void __launch_bounds__(256) trace_fast_kernel(TraceArgs A, uint32_t n_jobs) {
     __shared__ WaveLds<MA> lds[4];
     const int w = threadIdx.x >> 6;
@@ -622,11 +644,11 @@ __global__ void __launch_bounds__(256) trace_fast_kernel(TraceArgs A, uint32_t n
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     uint32_t tile = job / spt, sub = job % spt;
     if (A.tile_ovl[tile] > A.ma_fast) return;   // wide path
-    trace_block<MA, false>(A, lds[w], tile, sub, A.stats);
+    trace_block<MA, false, KS>(A, lds[w], tile, sub, A.stats);
 }
 
 // Wide path: one wave per workgroup, blocks of the listed tiles.
-template <int MA>
+template <int MA, int KS>
 __global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A) {
     extern __shared__ char dyn[];
     WaveLds<MA>& S = *reinterpret_cast<WaveLds<MA>*>(dyn);
@@ -635,11 +657,11 @@ __global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A) {
     for (uint32_t job = blockIdx.x; job < n_wide * spt; job += gridDim.x) {
         uint32_t tile = A.wide[1 + job / spt], sub = job % spt;
         if (lane_id() == 0) atomicAdd(A.stats + S_WIDE, 1ull);
-        trace_block<MA, true>(A, S, tile, sub, A.stats);
+        trace_block<MA, true, KS>(A, S, tile, sub, A.stats);
     }
 }
 
-constexpr int kMaFast = 128;
+constexpr int kMaFast = 256;
 constexpr int kMaWide = 1024;
 
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
@@ -679,7 +701,10 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     uint32_t n_jobs = uint32_t(s->n_tiles) * spt;
     uint32_t nwg = (n_jobs + 3) / 4;
-    hipLaunchKernelGGL(trace_fast_kernel<kMaFast>, dim3(nwg), dim3(256), 0, stream, A, n_jobs);
+    // evaluation stack: at least the tree depth (views are never deeper)
+    const bool shallow = s->depth <= 16;
+    if (shallow) hipLaunchKernelGGL((trace_fast_kernel<kMaFast, 16>), dim3(nwg), dim3(256), 0, stream, A, n_jobs);
+    else hipLaunchKernelGGL((trace_fast_kernel<kMaFast, 32>), dim3(nwg), dim3(256), 0, stream, A, n_jobs);
     e = hipGetLastError();
     if (e != hipSuccess) return device_error(e, "trace_fast_kernel");
     if (s->n_wide > 0) {
@@ -690,7 +715,8 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
         }
         size_t shm = sizeof(WaveLds<kMaWide>);
         uint32_t grid = std::min<uint32_t>(s->n_wide * spt, 4096u);
-        hipLaunchKernelGGL(trace_wide_kernel<kMaWide>, dim3(grid), dim3(64), shm, stream, A);
+        if (shallow) hipLaunchKernelGGL((trace_wide_kernel<kMaWide, 16>), dim3(grid), dim3(64), shm, stream, A);
+        else hipLaunchKernelGGL((trace_wide_kernel<kMaWide, 32>), dim3(grid), dim3(64), shm, stream, A);
         e = hipGetLastError();
         if (e != hipSuccess) return device_error(e, "trace_wide_kernel");
     }
@@ -729,12 +755,12 @@ __global__ void __launch_bounds__(64) debug_eval_kernel(TraceArgs A, const uint3
         if (out_g) {
             P3<Dual> p = make_point(x, y, z, Dual{});
             uint32_t sm = 0;
-            Dual g = eval_view<Dual>(S.view, pr.len, A.par, A.n_nodes, p, sm);
+            Dual g = eval_view<Dual, kStack>(S.view, pr.len, A.par, A.n_nodes, p, sm);
             if (in) { out_f[i] = g.v; out_g[3 * i] = g.gx; out_g[3 * i + 1] = g.gy; out_g[3 * i + 2] = g.gz; }
         } else {
             P3<float> p{x, y, z};
             uint32_t sm = 0;
-            float v = eval_view<float>(S.view, pr.len, A.par, A.n_nodes, p, sm);
+            float v = eval_view<float, kStack>(S.view, pr.len, A.par, A.n_nodes, p, sm);
             if (in) out_f[i] = v;
         }
     }
