@@ -219,6 +219,21 @@ st_status st_trace_ex(st_scene *s, const st_camera *cam, float *out_depth, float
                       uint32_t *out_info, st_stats *out_stats, void *stream);
 
 /*
+ * st_autotune -- picks, for this scene and camera, the tuning with the
+ * shortest A-buffer build + trace time among a grid of A-buffer tile sizes
+ * {8, 16, 32}, fetch caps max_new {6, 16, 64} (the paper's 6 first) and
+ * fetch-ahead depths sub_depth {1/20, 1/4} (the paper's 1/20 first).  Every
+ * candidate is timed on the device with HIP events (median of `reps` runs,
+ * reps >= 1) into temporary output buffers; the A-buffer is left built with
+ * the winner, so st_trace can follow directly.
+ *   base (host, NULL = defaults): fields other than the three searched ones.
+ *   out (host): the chosen tuning; out_ms (host, may be NULL): its time.
+ * Synchronous.  Errors: as st_build_abuffer and st_trace, ST_E_NOMEM.
+ */
+st_status st_autotune(st_scene *s, const st_camera *cam, const st_tuning *base, int32_t reps,
+                      st_tuning *out, float *out_ms, void *stream);
+
+/*
  * st_debug_eval_field -- test hook: evaluates the pruned field f_A of a given
  * active primitive set at points (pruning semantics of Sections 7-9).  The
  * view is built by the same device code the tracer uses.

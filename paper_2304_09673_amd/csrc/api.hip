@@ -42,6 +42,8 @@ static void free_abuffer(st_scene* s, hipStream_t stream) {
     dev_free(s, s->d_e_zout, stream); s->d_e_zout = nullptr;
     dev_free(s, s->d_wide, stream); s->d_wide = nullptr;
     dev_free(s, s->d_scratch, stream); s->d_scratch = nullptr;
+    dev_free(s, s->d_slots, stream); s->d_slots = nullptr;
+    s->slots_bytes = 0;
     s->scratch_bytes = 0;
     s->ab_cap = 0;
     s->n_tiles = 0;
@@ -329,6 +331,65 @@ static st_status active_to_post(const st_scene* s, const int32_t* active, int32_
     }
     std::sort(post.begin(), post.end());
     if (std::adjacent_find(post.begin(), post.end()) != post.end()) { set_error("duplicate active primitive"); return ST_E_INVALID; }
+    return ST_OK;
+}
+
+st_status st_autotune(st_scene* s, const st_camera* cam, const st_tuning* base, int32_t reps, st_tuning* out,
+                      float* out_ms, void* stream_v) {
+    if (!s || !cam || !out || reps < 1) { set_error("autotune: NULL argument or reps < 1"); return ST_E_INVALID; }
+    hipStream_t stream = (hipStream_t)stream_v;
+    st_tuning b;
+    if (base) b = *base; else st_default_tuning(&b);
+    size_t pix = size_t(cam->width > 0 ? cam->width : 0) * size_t(cam->height > 0 ? cam->height : 0);
+    float* buf = (float*)dev_alloc(s, pix * 16 + 256, stream);
+    if (!buf) { set_error("autotune: output buffer allocation failed"); return ST_E_NOMEM; }
+    float* depth = buf;
+    float* normal = buf + pix;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) { dev_free(s, buf, stream); return device_error(he, "autotune events"); }
+    const int tiles[3] = {8, 16, 32};
+    const int news[3] = {6, 16, 64};
+    const float subs[2] = {1.0f / 20.0f, 0.25f};
+    float best = INFINITY;
+    st_tuning best_t = b;
+    st_status r = ST_OK;
+    for (int ti = 0; ti < 3 && r == ST_OK; ti++)
+        for (int ni = 0; ni < 3 && r == ST_OK; ni++)
+            for (int si = 0; si < 2 && r == ST_OK; si++) {
+                st_tuning t = b;
+                t.tile = tiles[ti];
+                t.max_new = news[ni];
+                t.sub_depth = subs[si];
+                std::vector<float> ms;
+                for (int k = 0; k <= reps && r == ST_OK; k++) {   // first run warms up
+                    he = hipEventRecord(e0, stream);
+                    if (he != hipSuccess) { r = device_error(he, "autotune record"); break; }
+                    r = st_build_abuffer(s, cam, &t, stream_v);
+                    if (r != ST_OK) break;
+                    r = trace_device(s, s->ab_tune, depth, normal, nullptr, stream);
+                    if (r != ST_OK) break;
+                    he = hipEventRecord(e1, stream);
+                    if (he == hipSuccess) he = hipEventSynchronize(e1);
+                    float dt = 0.f;
+                    if (he == hipSuccess) he = hipEventElapsedTime(&dt, e0, e1);
+                    if (he != hipSuccess) { r = device_error(he, "autotune timing"); break; }
+                    if (k > 0) ms.push_back(dt);
+                }
+                if (r != ST_OK) break;
+                std::sort(ms.begin(), ms.end());
+                float med = ms[ms.size() / 2];
+                if (med < best) { best = med; best_t = t; }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dev_free(s, buf, stream);
+    if (r != ST_OK) return r;
+    r = st_build_abuffer(s, cam, &best_t, stream_v);
+    if (r != ST_OK) return r;
+    *out = best_t;
+    if (out_ms) *out_ms = best;
     return ST_OK;
 }
 

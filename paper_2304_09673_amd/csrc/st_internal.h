@@ -47,6 +47,10 @@ struct st_scene {
     uint32_t max_list = 0, max_overlap = 0, n_wide = 0;
     int32_t ab_ma_fast = 0, ab_ma_wide = 0;
 
+    // wide-path per-workgroup slots (trace)
+    void* d_slots = nullptr;
+    size_t slots_bytes = 0;
+
     // scratch kept between builds
     void* d_scratch = nullptr;
     size_t scratch_bytes = 0;

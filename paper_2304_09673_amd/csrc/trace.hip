@@ -90,14 +90,37 @@ enum StatIdx {
     S_VIEWN, S_MAXACT, S_WIDE, S_ACC, S_REJ, S_STALL, S_SMOOTH
 };
 
-// Per-wave LDS of capacity MA active primitives.
+// Per-wave storage of the active set and the view.  Two layouts share the
+// tracing code through accessors: LDS arrays of compile-time capacity MA
+// (fast path), and a slot of global memory of run-time capacity (tiles whose
+// volumes of interest overlap more than the LDS capacity).  Capacities are
+// powers of two.  Within one wave, the workgroup-scope fences of wave_sync()
+// order both kinds of traffic.
 template <int MA>
 struct WaveLds {
-    uint32_t act[2][MA];
-    float ze[2][MA];
-    uint32_t lca[MA];
-    uint32_t vs[2 * MA];
-    uint32_t view[2 * MA];
+    uint32_t act_[2][MA];
+    float ze_[2][MA];
+    uint32_t lca_[MA];
+    uint32_t vs_[2 * MA];
+    uint32_t view_[2 * MA];
+    __device__ __forceinline__ uint32_t* act(int b) { return act_[b]; }
+    __device__ __forceinline__ float* ze(int b) { return ze_[b]; }
+    __device__ __forceinline__ uint32_t* lca() { return lca_; }
+    __device__ __forceinline__ uint32_t* vs() { return vs_; }
+    __device__ __forceinline__ uint32_t* view() { return view_; }
+    __device__ __forceinline__ int cap() const { return MA; }
+};
+
+// 9 * ma 32-bit words per slot: act 2ma, ze 2ma, lca ma, vs 2ma, view 2ma
+struct WaveGlob {
+    uint32_t* base;
+    int ma;
+    __device__ __forceinline__ uint32_t* act(int b) { return base + b * ma; }
+    __device__ __forceinline__ float* ze(int b) { return reinterpret_cast<float*>(base + 2 * ma + b * ma); }
+    __device__ __forceinline__ uint32_t* lca() { return base + 4 * ma; }
+    __device__ __forceinline__ uint32_t* vs() { return base + 5 * ma; }
+    __device__ __forceinline__ uint32_t* view() { return base + 7 * ma; }
+    __device__ __forceinline__ int cap() const { return ma; }
 };
 
 // ---------------------------------------------------------------------------
@@ -197,48 +220,6 @@ struct DevPruneCtx {
     }
 };
 
-// same pass with per-position data in LDS (wide path, long views)
-struct LdsPruneCtx {
-    const uint32_t* vsn;   // nodes in post-order
-    const uint32_t* blobs;
-    const uint32_t* kills;
-    const NodePar* par;
-    uint32_t s_nu = 0, s_start = 0, s_kill = 0;
-    float s_L = 0.f;
-    uint32_t* view;
-    uint32_t n_nodes;
-    __device__ uint32_t at(int j) const { return min(uni(vsn[j]), n_nodes - 1u); }
-    __device__ uint32_t node(int j) const { return at(j); }
-    __device__ uint32_t blob(int j) const { return uni(blobs[at(j)]); }
-    __device__ uint32_t kill(int j) const { return uni(kills[at(j)]); }
-    __device__ float lipf(int j) const { return unif(par[at(j)].v[4]); }
-    __device__ void spush(int sp, uint32_t nu, uint32_t start, float L, uint32_t k) {
-        s_nu = wrlane(nu, sp, s_nu);
-        s_start = wrlane(start, sp, s_start);
-        s_kill = wrlane(k, sp, s_kill);
-        s_L = wrlanef(L, sp, s_L);
-    }
-    __device__ void sget(int sp, uint32_t& nu, uint32_t& start, float& L, uint32_t& k) const {
-        nu = rdlane(s_nu, sp);
-        start = rdlane(s_start, sp);
-        k = rdlane(s_kill, sp);
-        L = rdlanef(s_L, sp);
-    }
-    __device__ void emit(int pos, uint32_t e) {
-        if (lane_id() == 0) view[pos] = e;
-    }
-    __device__ void move(int dst, int src, int len) {
-        wave_sync();
-        for (int b = 0; b < len; b += 64) {
-            int i = b + lane_id();
-            uint32_t x = i < len ? view[src + i] : 0u;
-            wave_sync();
-            if (i < len) view[dst + i] = x;
-            wave_sync();
-        }
-    }
-};
-
 // ---------------------------------------------------------------------------
 // wave bitonic sort of a[0..np2) (u32) in LDS
 __device__ void wave_bitonic(uint32_t* a, int np2) {
@@ -268,14 +249,14 @@ __device__ __forceinline__ int lower_count(const uint32_t* a, int n, uint32_t x)
     return lo;
 }
 
-// Builds the pruned view of the active set S.act[buf][0..n) into S.view.
-template <int MA, bool kWide>
-__device__ PruneResult build_view(const TraceArgs& A, WaveLds<MA>& S, int buf, int n) {
-    const uint32_t* act = S.act[buf];
+// Builds the pruned view of the active set S.act(buf)[0..n) into S.view().
+template <class Mem>
+__device__ PruneResult build_view(const TraceArgs& A, Mem& S, int buf, int n) {
+    const uint32_t* act = S.act(buf);
     const int lane = lane_id();
     int m;
     if (n == 1) {
-        if (lane == 0) S.vs[0] = act[0];
+        if (lane == 0) S.vs()[0] = act[0];
         m = 1;
     } else {
         // 1. LCAs of consecutive active primitives
@@ -290,55 +271,42 @@ __device__ PruneResult build_view(const TraceArgs& A, WaveLds<MA>& S, int buf, i
                 uint32_t a = act[i], b = act[i + 1];
                 x = (a < b && b < A.n_nodes) ? lca_query(A.rmq, A.n_nodes, a, b) : 0u;
             }
-            S.lca[i] = x;
+            S.lca()[i] = x;
         }
         // 2. sort them
-        wave_bitonic(S.lca, np2);
+        wave_bitonic(S.lca(), np2);
         // 3. merge with the (sorted) primitives into post-order
         for (int i = lane; i < n; i += 64) {
             uint32_t x = act[i];
-            S.vs[i + lower_count(S.lca, nl, x)] = x;
+            S.vs()[i + lower_count(S.lca(), nl, x)] = x;
         }
         for (int i = lane; i < nl; i += 64) {
-            uint32_t x = S.lca[i];
-            S.vs[i + lower_count(act, n, x)] = x;
+            uint32_t x = S.lca()[i];
+            S.vs()[i + lower_count(act, n, x)] = x;
         }
         m = 2 * n - 1;
     }
     wave_sync();
     // 4. bottom-up pass (usage, killing ancestors, compaction, Lipschitz)
-    if constexpr (!kWide) {
-        DevPruneCtx c;
-        c.vs = S.vs;
-        c.gblob = A.blob;
-        c.gkill = A.kill;
-        c.gpar = A.par;
-        c.n_nodes = A.n_nodes;
-        c.m = m;
-        c.view = S.view;
-        PruneResult r = prune_pass(c, m);
-        wave_sync();
-        return r;
-    } else {
-        LdsPruneCtx c;
-        c.n_nodes = A.n_nodes;
-        c.vsn = S.vs;
-        c.blobs = A.blob;
-        c.kills = A.kill;
-        c.par = A.par;
-        c.view = S.view;
-        PruneResult r = prune_pass(c, m);
-        wave_sync();
-        return r;
-    }
+    DevPruneCtx c;
+    c.vs = S.vs();
+    c.gblob = A.blob;
+    c.gkill = A.kill;
+    c.gpar = A.par;
+    c.n_nodes = A.n_nodes;
+    c.m = m;
+    c.view = S.view();
+    PruneResult r = prune_pass(c, m);
+    wave_sync();
+    return r;
 }
 
 // ---------------------------------------------------------------------------
 // Lane modes inside a subfrustum
 enum { M_IDLE = 0, M_TRACE = 1, M_REFINE = 2, M_GRAD = 3 };
 
-template <int MA, bool kWide, int KS>
-__device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, uint32_t sub,
+template <class Mem, int KS>
+__device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t sub,
                             unsigned long long* cnt) {
     const int lane = lane_id();
     const int tx = int(tile % uint32_t(A.tiles_x)), ty = int(tile / uint32_t(A.tiles_x));
@@ -385,13 +353,13 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             for (int b = 0; b < n; b += 64) {
                 int s = b + lane;
                 bool in = s < n;
-                uint32_t a = in ? S.act[buf][s] : 0u;
-                float z = in ? S.ze[buf][s] : 0.f;
+                uint32_t a = in ? S.act(buf)[s] : 0u;
+                float z = in ? S.ze(buf)[s] : 0.f;
                 bool keep = in && z > z_end;
                 uint64_t mk = ballot(keep);
                 int dst = kept + int(lanes_below(mk));
                 wave_sync();
-                if (keep) { S.act[buf][dst] = a; S.ze[buf][dst] = z; }
+                if (keep) { S.act(buf)[dst] = a; S.ze(buf)[dst] = z; }
                 kept += __popcll(mk);
             }
             n = kept;
@@ -401,7 +369,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
         const float z_begin = n > 0 ? z_end : unif(A.e_zin[i]);
         // max exit depth of the remaining active set
         float mz = -__builtin_inff();
-        for (int s = lane; s < n; s += 64) mz = fmaxf(mz, S.ze[buf][s]);
+        for (int s = lane; s < n; s += 64) mz = fmaxf(mz, S.ze(buf)[s]);
         mz = wave_max(mz);
         // -- fetch new primitives (lane c considers list entry i + c)
         int k = 0;
@@ -420,7 +388,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             float pex = __shfl_up(pm, 1);
             if (lane == 0) pex = -__builtin_inff();
             float reach = fmaxf(fmaxf(z_begin, mz), pex);
-            bool ok = in && lane < A.max_new && (n + lane) < MA && (zb - z_begin < A.d_sub || lane == 0) &&
+            bool ok = in && lane < A.max_new && (n + lane) < S.cap() && (zb - z_begin < A.d_sub || lane == 0) &&
                       zb <= reach;
             uint64_t okm = ballot(ok);
             k = ~okm == 0ull ? 64 : int(__builtin_ctzll(~okm));
@@ -431,22 +399,22 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
                 for (int b = 0; b < n; b += 64) {
                     int s = b + lane;
                     bool in_s = s < n;
-                    uint32_t a = in_s ? S.act[buf][s] : 0xFFFFFFFFu;
-                    float az = in_s ? S.ze[buf][s] : 0.f;
+                    uint32_t a = in_s ? S.act(buf)[s] : 0xFFFFFFFFu;
+                    float az = in_s ? S.ze(buf)[s] : 0.f;
                     int less = 0;
                     for (int q = 0; q < k; q++) less += rdlane(nd, q) < a ? 1 : 0;
                     if (in_s) {
-                        S.act[nb][s + less] = a;
-                        S.ze[nb][s + less] = az;
+                        S.act(nb)[s + less] = a;
+                        S.ze(nb)[s + less] = az;
                     }
                 }
                 {
-                    int pos = lower_count(S.act[buf], n, nd);
+                    int pos = lower_count(S.act(buf), n, nd);
                     int less = 0;
                     for (int q = 0; q < k; q++) less += rdlane(nd, q) < nd ? 1 : 0;
                     if (lane < k) {
-                        S.act[nb][pos + less] = nd;
-                        S.ze[nb][pos + less] = zo;
+                        S.act(nb)[pos + less] = nd;
+                        S.ze(nb)[pos + less] = zo;
                     }
                 }
                 // the new ones also extend the reach
@@ -465,7 +433,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
         n_subf++;
 
         // -- pruned view of the active set
-        PruneResult pr = build_view<MA, kWide>(A, S, buf, n);
+        PruneResult pr = build_view(A, S, buf, n);
         const float t0 = z_begin * inv_cos, t1 = z_end * inv_cos;
         if (!pr.used) {
             n_empty++;
@@ -479,7 +447,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
         // kinds in the view (for node counts)
         uint32_t kc[4] = {0, 0, 0, 0};
         for (int j = lane; j < len; j += 64) {
-            uint32_t kd = ventry_kind(S.view[j]);
+            uint32_t kd = ventry_kind(S.view()[j]);
             kc[kd <= ST_CAPSULE ? kd : 3]++;
         }
         for (int q = 0; q < 4; q++) kc[q] = uni(wave_sum(kc[q]));
@@ -498,7 +466,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             if (ballot(act) == 0) break;
             P3<float> p{fmaf(t, ray.d[0], ray.o[0]), fmaf(t, ray.d[1], ray.o[1]), fmaf(t, ray.d[2], ray.o[2])};
             uint32_t sm_l = 0;
-            float v = eval_view<float, KS>(S.view, len, A.par, A.n_nodes, p, sm_l);
+            float v = eval_view<float, KS>(S.view(), len, A.par, A.n_nodes, p, sm_l);
             if (act) {
                 ev_here++;
                 smooth += sm_l;
@@ -575,7 +543,7 @@ __device__ void trace_block(const TraceArgs& A, WaveLds<MA>& S, uint32_t tile, u
             P3<Dual> p = make_point(fmaf(th, ray.d[0], ray.o[0]), fmaf(th, ray.d[1], ray.o[1]),
                                     fmaf(th, ray.d[2], ray.o[2]), Dual{});
             uint32_t sm_g = 0;
-            Dual g = eval_view<Dual, KS>(S.view, len, A.par, A.n_nodes, p, sm_g);
+            Dual g = eval_view<Dual, KS>(S.view(), len, A.par, A.n_nodes, p, sm_g);
             if (mode == M_GRAD) {
                 float gn = sqrtf(g.gx * g.gx + g.gy * g.gy + g.gz * g.gz);
                 float ig = gn > 0.f ? 1.0f / gn : 0.f;
@@ -644,25 +612,26 @@ __global__ void __launch_bounds__(256) trace_fast_kernel(TraceArgs A, uint32_t n
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     uint32_t tile = job / spt, sub = job % spt;
     if (A.tile_ovl[tile] > A.ma_fast) return;   // wide path
-    trace_block<MA, false, KS>(A, lds[w], tile, sub, A.stats);
+    trace_block<WaveLds<MA>, KS>(A, lds[w], tile, sub, A.stats);
 }
 
-// Wide path: one wave per workgroup, blocks of the listed tiles.
-template <int MA, int KS>
-__global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A) {
-    extern __shared__ char dyn[];
-    WaveLds<MA>& S = *reinterpret_cast<WaveLds<MA>*>(dyn);
+// Wide path: blocks of the listed tiles, one wave per workgroup, each
+// workgroup with its own global-memory slot of capacity ma; the grid strides
+// over the jobs.
+template <int KS>
+__global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A, uint32_t* slots, int ma) {
+    WaveGlob S{slots + size_t(blockIdx.x) * 9u * uint32_t(ma), ma};
     uint32_t n_wide = A.wide[0];
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     for (uint32_t job = blockIdx.x; job < n_wide * spt; job += gridDim.x) {
         uint32_t tile = A.wide[1 + job / spt], sub = job % spt;
         if (lane_id() == 0) atomicAdd(A.stats + S_WIDE, 1ull);
-        trace_block<MA, true, KS>(A, S, tile, sub, A.stats);
+        trace_block<WaveGlob, KS>(A, S, tile, sub, A.stats);
     }
 }
 
 constexpr int kMaFast = 256;
-constexpr int kMaWide = 1024;
+constexpr int kMaDebug = 1024;
 
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
                        hipStream_t stream) {
@@ -708,15 +677,22 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
     e = hipGetLastError();
     if (e != hipSuccess) return device_error(e, "trace_fast_kernel");
     if (s->n_wide > 0) {
-        if (s->max_overlap > uint32_t(kMaWide)) {
-            set_error("trace: depth overlap " + std::to_string(s->max_overlap) + " exceeds the wide path capacity " +
-                      std::to_string(kMaWide));
-            return ST_E_CAPACITY;
+        // capacity: a power of two above the largest depth overlap, so the
+        // active set can always advance
+        int ma = 512;
+        while (uint32_t(ma) <= s->max_overlap) ma <<= 1;
+        uint32_t jobs = s->n_wide * spt;
+        uint32_t grid = std::min<uint32_t>(jobs, 3072u);
+        size_t need = size_t(grid) * 9u * size_t(ma) * 4u;
+        if (need > s->slots_bytes) {
+            dev_free(s, s->d_slots, stream);
+            s->d_slots = dev_alloc(s, need, stream);
+            s->slots_bytes = s->d_slots ? need : 0;
+            if (!s->d_slots) { set_error("trace: wide-path slot allocation failed"); return ST_E_NOMEM; }
         }
-        size_t shm = sizeof(WaveLds<kMaWide>);
-        uint32_t grid = std::min<uint32_t>(s->n_wide * spt, 4096u);
-        if (shallow) hipLaunchKernelGGL((trace_wide_kernel<kMaWide, 16>), dim3(grid), dim3(64), shm, stream, A);
-        else hipLaunchKernelGGL((trace_wide_kernel<kMaWide, 32>), dim3(grid), dim3(64), shm, stream, A);
+        uint32_t* slots = reinterpret_cast<uint32_t*>(s->d_slots);
+        if (shallow) hipLaunchKernelGGL((trace_wide_kernel<16>), dim3(grid), dim3(64), 0, stream, A, slots, ma);
+        else hipLaunchKernelGGL((trace_wide_kernel<32>), dim3(grid), dim3(64), 0, stream, A, slots, ma);
         e = hipGetLastError();
         if (e != hipSuccess) return device_error(e, "trace_wide_kernel");
     }
@@ -732,15 +708,15 @@ __global__ void __launch_bounds__(64) debug_eval_kernel(TraceArgs A, const uint3
     extern __shared__ char dyn[];
     WaveLds<MA>& S = *reinterpret_cast<WaveLds<MA>*>(dyn);
     const int lane = lane_id();
-    for (int s = lane; s < n; s += 64) { S.act[0][s] = act_sorted[s]; S.ze[0][s] = 0.f; }
+    for (int s = lane; s < n; s += 64) { S.act(0)[s] = act_sorted[s]; S.ze(0)[s] = 0.f; }
     wave_sync();
-    PruneResult pr = build_view<MA, true>(A, S, 0, n);
+    PruneResult pr = build_view(A, S, 0, n);
     if (lane == 0) {
         root_used[0] = pr.used;
         root_used[1] = pr.len;
         root_used[2] = __float_as_int(pr.lip);
     }
-    for (int j = lane; j < pr.len; j += 64) view_out[j] = S.view[j];
+    for (int j = lane; j < pr.len; j += 64) view_out[j] = S.view()[j];
     for (int b = int(blockIdx.x) * 64; b < n_pts; b += int(gridDim.x) * 64) {
         int i = b + lane;
         bool in = i < n_pts;
@@ -755,12 +731,12 @@ __global__ void __launch_bounds__(64) debug_eval_kernel(TraceArgs A, const uint3
         if (out_g) {
             P3<Dual> p = make_point(x, y, z, Dual{});
             uint32_t sm = 0;
-            Dual g = eval_view<Dual, kStack>(S.view, pr.len, A.par, A.n_nodes, p, sm);
+            Dual g = eval_view<Dual, kStack>(S.view(), pr.len, A.par, A.n_nodes, p, sm);
             if (in) { out_f[i] = g.v; out_g[3 * i] = g.gx; out_g[3 * i + 1] = g.gy; out_g[3 * i + 2] = g.gz; }
         } else {
             P3<float> p{x, y, z};
             uint32_t sm = 0;
-            float v = eval_view<float, kStack>(S.view, pr.len, A.par, A.n_nodes, p, sm);
+            float v = eval_view<float, kStack>(S.view(), pr.len, A.par, A.n_nodes, p, sm);
             if (in) out_f[i] = v;
         }
     }
@@ -774,11 +750,11 @@ st_status debug_eval_device(const st_scene* s, const uint32_t* act_sorted_dev, i
     A.kill = s->d_kill;
     A.rmq = s->d_rmq;
     A.n_nodes = uint32_t(s->n_nodes);
-    if (n > kMaWide) { set_error("debug_eval: active set larger than the wide path capacity"); return ST_E_CAPACITY; }
-    size_t shm = sizeof(WaveLds<kMaWide>);
+    if (n > kMaDebug) { set_error("debug_eval: active set larger than 1024"); return ST_E_CAPACITY; }
+    size_t shm = sizeof(WaveLds<kMaDebug>);
     uint32_t* view_out = reinterpret_cast<uint32_t*>(root_used_dev + 4);
     int grid = std::max(1, std::min(1024, (n_pts + 63) / 64));
-    hipLaunchKernelGGL(debug_eval_kernel<kMaWide>, dim3(grid), dim3(64), shm, stream, A, act_sorted_dev, n, pts,
+    hipLaunchKernelGGL(debug_eval_kernel<kMaDebug>, dim3(grid), dim3(64), shm, stream, A, act_sorted_dev, n, pts,
                        n_pts, out_f, out_g, root_used_dev, view_out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ST_OK : device_error(e, "debug_eval_kernel");

@@ -20,7 +20,8 @@ ST_STEP_PLAIN, ST_STEP_OVERRELAX, ST_STEP_LEARNED = 0, 1, 2
 # every symbol include/st.h declares
 EXPORTS = (
     "st_status_str", "st_last_error", "st_default_tuning", "st_flatten_blobtree", "st_scene_destroy",
-    "st_scene_get_info", "st_build_abuffer", "st_trace", "st_trace_ex", "st_debug_eval_field", "st_debug_prune_tree",
+    "st_scene_get_info", "st_build_abuffer", "st_trace", "st_trace_ex", "st_autotune", "st_debug_eval_field",
+    "st_debug_prune_tree",
     "st_debug_abuffer",
 )
 
@@ -97,6 +98,7 @@ def lib():
         L.st_build_abuffer.argtypes = [vp, C.POINTER(StCamera), C.POINTER(StTuning), vp]
         L.st_trace.argtypes = [vp, C.POINTER(StCamera), vp, vp, C.POINTER(StStats), vp]
         L.st_trace_ex.argtypes = [vp, C.POINTER(StCamera), vp, vp, vp, C.POINTER(StStats), vp]
+        L.st_autotune.argtypes = [vp, C.POINTER(StCamera), C.POINTER(StTuning), i32, C.POINTER(StTuning), C.POINTER(C.c_float), vp]
         L.st_debug_eval_field.argtypes = [vp, vp, i32, vp, i32, vp, vp, C.POINTER(i32), vp, i32, C.POINTER(i32), vp]
         L.st_debug_prune_tree.argtypes = [C.POINTER(StNode), i32, i32, vp, i32, vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]
         L.st_debug_abuffer.argtypes = [vp, vp, sz, vp, sz, C.POINTER(i32), C.POINTER(i64), vp]
@@ -189,6 +191,16 @@ class Scene:
         self._cam = make_camera(camera)
         _check(lib().st_build_abuffer(self._h, C.byref(self._cam), C.byref(tuning) if tuning else None,
                                       _stream_ptr(stream)))
+
+    def autotune(self, camera, base: StTuning | None = None, reps: int = 3, stream=None):
+        """st_autotune: returns (chosen tuning, its build+trace milliseconds); the
+        A-buffer is left built with it."""
+        self._cam = make_camera(camera)
+        out = StTuning()
+        ms = C.c_float(0)
+        _check(lib().st_autotune(self._h, C.byref(self._cam), C.byref(base) if base else None, int(reps),
+                                 C.byref(out), C.byref(ms), _stream_ptr(stream)))
+        return out, float(ms.value)
 
     def trace(self, camera=None, depth=None, normal=None, stats: bool = True, stream=None, info=None):
         """Returns (depth[H,W], normal[H,W,3], stats dict or None) as torch CUDA tensors.
