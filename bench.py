@@ -32,6 +32,50 @@ SMOOTH_EXTRA = 20
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector, packed
 PEAK_FP32_NONPACKED = 78.6e12
 
+# HBM traffic of the trace kernel, measured with rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters and calibrated against a copy kernel of known size; it is
+# reported only while the kernel sources hash to what was measured.
+TRAFFIC_FILE = ROOT / "profiles" / "trace_c3_traffic.md"
+TRACE_SOURCES = ["trace.hip", "st_trace.h", "st_field.h", "st_prune.h", "st_common.h", "st_mlp.h"]
+
+
+def trace_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRACE_SOURCES:
+        h.update((ROOT / "paper_2304_09673_amd" / "csrc" / name).read_bytes())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per trace launch from the committed counter summary, or None."""
+    if not TRAFFIC_FILE.exists():
+        return None
+    kv = {}
+    for line in TRAFFIC_FILE.read_text().splitlines():
+        line = line.strip().lstrip("-* ")
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip().strip("`")] = v.strip().strip("`")
+    if kv.get("trace_source_sha256") != trace_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calib_copy(mib: int, reps: int = 5):
+    """A plain device copy of known size, for scaling the HBM counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": n * 4, "calib_copy_bytes_written": n * 4, "reps": reps}), flush=True)
+
 
 def algorithmic_flops(stats) -> float:
     ne = stats["node_evals"]
@@ -54,6 +98,63 @@ def cpu_baseline(sc, n_rays: int, seed: int = 1234):
                       f"tracing (no pruning, no A-buffer); {dt:.1f} s, {int(ev.sum())} full-tree evaluations"}
 
 
+def bench_batch(args):
+    """The 64-scene batch: one graph launch per frame (replayed A-buffer builds
+    of every scene + persistent trace kernels over a shared job queue)."""
+    import torch
+    import scenegen as sg
+    from paper_2304_09673_amd import st
+
+    scs = sg.config4(args.n_scenes)
+    handles = [st.Scene(sc) for sc in scs]
+    cams = [sc.camera for sc in scs]
+    t0 = time.perf_counter()
+    if args.no_autotune:
+        b = st.Batch(handles, cams, tuning=st.default_tuning(tile=args.tile))
+        tuned = "defaults"
+    else:
+        b = st.Batch(handles, cams, autotune=True, reps=1)
+        tuned = "autotuned"
+    setup_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        b.render()
+    torch.cuda.synchronize()
+    stats = b.stats()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record()
+        b.render()
+        evs[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    frame_ms = float(np.median([a.elapsed_time(c) for a, c in evs]))
+    rays = sum(c.width * c.height for c in cams)
+    evals = sum(x["field_evals"] for x in stats)
+    flops = sum(algorithmic_flops(x) for x in stats)
+    line = {
+        "metric": "Mrays/s + field evals/s at 1080p, 4096 prims; learned vs plain step at equal depth err",
+        "value": round(rays / (ms_per_step * 1e-3) / 1e6, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch of {len(scs)} scenes (primitives log-uniform in [32, 8192], resolutions "
+                               f"from 256x256 to 1920x1080), one graph launch per frame, plain sphere tracing",
+                   "rays": rays, "tuning": {"source": tuned, "tile": b.tuning.tile, "max_new": b.tuning.max_new,
+                                            "sub_depth": round(b.tuning.sub_depth, 4)}},
+        "frame_ms_device": round(frame_ms, 4),
+        "field_evals_per_s": evals / (frame_ms * 1e-3),
+        "setup_s": round(setup_s, 2),
+        "roofline": {"bound": "alu", "kernel": "batch (binning replay + batch_fast_kernel + batch_wide_kernel)",
+                     "achieved": flops / (frame_ms * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": flops / (frame_ms * 1e-3) / PEAK_FP32, "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
+    b.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,11 +165,22 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=6144)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
+    ap.add_argument("--n-scenes", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design (screen tiles sharded "
               "across GPUs, no exchange during a frame) is described but not built.", file=sys.stderr)
         sys.exit(2)
+
+    if args.calib_copy:
+        calib_copy(args.calib_copy)
+        return
+
+    if args.config == 4:
+        bench_batch(args)
+        return
 
     import torch
     import scenegen as sg
@@ -76,12 +188,19 @@ def main():
 
     sc = sg.by_config(args.config, seed=args.seed)
     cam = sc.camera
-    tune = st.default_tuning(tile=args.tile)
     stream = torch.cuda.current_stream()
 
     t0 = time.perf_counter()
     scene = st.Scene(sc)
     flatten_ms = (time.perf_counter() - t0) * 1e3
+    if args.no_autotune:
+        tune = st.default_tuning(tile=args.tile)
+        tuned = "defaults"
+    else:
+        # set-up, outside the timed region: grid search of tile size, fetch
+        # cap and fetch-ahead depth with device timing
+        tune, _ = scene.autotune(cam, reps=3)
+        tuned = "autotuned"
     depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda")
     normal = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda")
 
@@ -134,8 +253,9 @@ def main():
         "config": {"workload": f"{sc.name} seed {args.seed}: {sc.n_prims} primitives (spheres, boxes, capsules; "
                                f"32-cluster Gaussian mixture), random tree depth<=16, compact smooth "
                                f"union/intersection/difference 60/20/20%, {cam.width}x{cam.height}, "
-                               f"A-buffer tile {args.tile}, plain sphere tracing",
-                   "rays": rays},
+                               f"plain sphere tracing",
+                   "rays": rays, "tuning": {"source": tuned, "tile": tune.tile, "max_new": tune.max_new,
+                                            "sub_depth": round(tune.sub_depth, 4), "eps": tune.eps}},
         "field_evals_per_s": evals_per_s,
         "trace_ms": round(trace_ms_avg, 4),
         "build_ms": round(build_ms, 4),
@@ -151,7 +271,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "trace (trace_fast_kernel + trace_wide_kernel)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "frac_nonpacked": achieved / PEAK_FP32_NONPACKED,
-                     "flops_per_launch": flops, "traffic": None},
+                     "flops_per_launch": flops, "traffic": measured_traffic()},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_rays)

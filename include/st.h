@@ -95,8 +95,14 @@ typedef struct {
     float eps;             /* minimum step and probing step, scene units */
     int32_t max_steps;     /* field evaluations per ray for stepping */
     int32_t refine_iters;  /* bracket refinement iterations after a crossing */
-    int32_t step_mode;     /* ST_STEP_* */
-    float omega;           /* over-relaxation factor for ST_STEP_OVERRELAX (paper: 1.7) */
+    int32_t step_mode;     /* ST_STEP_*: PLAIN, the safe step f/L; OVERRELAX,
+                              the step omega f/L accepted only when the spheres
+                              of radius f/L at both ends overlap, else the plain
+                              step (Section 10, Ray processing); LEARNED, the
+                              same test with omega from the step model
+                              (st_set_step_model; not in the paper) */
+    float omega;           /* over-relaxation factor for ST_STEP_OVERRELAX, in
+                              [1, 4] (paper: 1.7) */
     float lipschitz;       /* 0: proven bound of each pruned view; > 0: this
                               fixed global bound (paper: 1.45, not proven) */
     int32_t reserved[6];
@@ -120,7 +126,7 @@ typedef struct {
     uint64_t max_overlap;     /* largest depth overlap of volumes of interest in a tile */
     uint64_t max_active;      /* largest active set used by the tracer */
     uint64_t wide_tiles;      /* tiles traced on the wide-capacity path */
-    uint64_t learned_accepted, learned_rejected;
+    uint64_t learned_accepted, learned_rejected;   /* relaxed steps (OVERRELAX, LEARNED) */
     uint64_t reserved[8];
 } st_stats;
 
@@ -232,6 +238,121 @@ st_status st_trace_ex(st_scene *s, const st_camera *cam, float *out_depth, float
  */
 st_status st_autotune(st_scene *s, const st_camera *cam, const st_tuning *base, int32_t reps,
                       st_tuning *out, float *out_ms, void *stream);
+
+/*
+ * Step model (not in the paper; proposes omega for ST_STEP_LEARNED): an MLP
+ * 8 -> 32 -> 32 -> 1 with ReLU and omega = 1 + 3 sigmoid(z), in [1, 4].
+ * Parameters (ST_MLP_PARAMS floats, FP32 master copy): W1[32][8], b1[32],
+ * W2[32][32], b2[32], w3[32], b3.  Features of a ray at a step (8 floats): the
+ * plain step f/L, f/f_prev, the previous step, log2(1 + step index), the secant
+ * slope of f along the ray divided by L, log2(1 + active primitives), t, and
+ * log2(1 + pruned-view length); the model standardises them with norm[16] =
+ * means[8], inverse standard deviations[8].  Arithmetic: binary16 inputs,
+ * weights and hidden activations, FP32 accumulation (matrix cores).
+ * All array arguments of the st_mlp_* calls are device memory owned by the
+ * caller; the calls are asynchronous on `stream`.
+ */
+#define ST_MLP_PARAMS 1377
+#define ST_MLP_FEATURES 8
+#define ST_MLP_TABLE_WORDS (59 * 64 + 16)
+
+/* Pack weights and norm into the per-lane operand table of the inference
+ * (uint32[ST_MLP_TABLE_WORDS]).  Errors: ST_E_INVALID (NULL), ST_E_DEVICE. */
+st_status st_mlp_pack(const float *weights, const float *norm, uint32_t *table, void *stream);
+
+/* omega[n] of raw features x[n][8] with a packed table, by the same device
+ * function the tracer calls.  Errors: ST_E_INVALID (NULL with n > 0, n < 0),
+ * ST_E_DEVICE. */
+st_status st_mlp_forward(const uint32_t *table, const float *x, int32_t n, float *omega, void *stream);
+
+/* Loss sum_i w_i (omega_i - target_i)^2 / n with w_i = 4 where omega_i >
+ * target_i (an over-long proposal costs a rejected evaluation), and its
+ * gradient with respect to weights (the binary16 roundings of the forward
+ * pass are passed through).  grad[ST_MLP_PARAMS] and loss[1] are
+ * overwritten.  Errors: ST_E_INVALID, ST_E_DEVICE. */
+st_status st_mlp_grad(const float *weights, const float *norm, const float *x, const float *target, int32_t n,
+                      float *grad, float *loss, void *stream);
+
+/* One Adam update of w[n] with moments m[n], v[n] (updated in place), bias
+ * corrections for update number step >= 1.  Errors: ST_E_INVALID, ST_E_DEVICE. */
+st_status st_mlp_adam(float *w, float *m, float *v, const float *grad, int32_t n, int32_t step, float lr,
+                      float beta1, float beta2, float eps, void *stream);
+
+/* Install a step model in the scene (weights and norm: device; packed into a
+ * table the scene owns).  Required before tracing with ST_STEP_LEARNED.
+ * Errors: ST_E_INVALID, ST_E_NOMEM, ST_E_DEVICE. */
+st_status st_set_step_model(st_scene *s, const float *weights, const float *norm, void *stream);
+
+/*
+ * st_trace_dump -- training samples from the plain tracer: traces like
+ * st_trace in ST_STEP_PLAIN whatever the tuning's step mode (same outputs),
+ * and at each step where a relaxed step would be proposed (plain step >= eps
+ * and ending before the subfrustum end) writes the ray's 8 features and the
+ * target omega*: the largest omega in {1, 1.25, ..., 4} whose step (clamped
+ * at the subfrustum end) passes the sphere-overlap test (1 if none).
+ *   features (device, float[cap][8]), targets (device, float[cap]);
+ *   *n_samples (host): samples produced; only the first min(n, cap) slots
+ *   are written; their order is unspecified.  Synchronous.
+ * Errors: as st_trace.
+ */
+st_status st_trace_dump(st_scene *s, const st_camera *cam, float *out_depth, float *out_normal,
+                        float *features, float *targets, int64_t cap, int64_t *n_samples, void *stream);
+
+/*
+ * Batched rendering (not in the paper): many scenes, each with its camera,
+ * rendered per frame by one graph launch.  A frame is: every scene's A-buffer
+ * build replayed with the sizes of its first build (no host synchronization,
+ * no allocation), then two persistent kernels pulling (scene, tile, 8x8
+ * block) jobs from global atomic queues, longest tile list first (tiles within
+ * the LDS capacity, then the wider ones).  Outputs are bitwise those of
+ * st_trace on each scene with the same tuning.
+ */
+typedef struct st_batch st_batch;
+
+/*
+ * st_batch_create -- builds every scene's A-buffer once (sizing; synchronizes
+ * `stream`), orders the jobs, and captures one frame into a HIP graph.
+ *   scenes[n] (distinct handles; they must outlive the batch, and rebuilding
+ *   one of their A-buffers elsewhere makes the batch stale), cams[n] (host),
+ *   tuning (host, NULL = defaults; step mode must be ST_STEP_PLAIN),
+ *   depths[n], normals[n]: device output buffers of each scene (as st_trace),
+ *   fixed for the life of the batch.
+ * Errors: ST_E_INVALID (NULL, n <= 0, repeated scene, non-plain step mode),
+ * those of st_build_abuffer, ST_E_NOMEM, ST_E_DEVICE.
+ */
+st_status st_batch_create(st_scene *const *scenes, const st_camera *cams, int32_t n, const st_tuning *tuning,
+                          float *const *depths, float *const *normals, void *stream, st_batch **out);
+
+/* One frame: use_graph != 0 launches the captured graph on `stream`, 0
+ * enqueues the same kernels directly.  Asynchronous.  Errors: ST_E_STALE (a
+ * scene's A-buffer was rebuilt since creation), ST_E_DEVICE. */
+st_status st_batch_render(st_batch *b, int32_t use_graph, void *stream);
+
+/* Counters of the last frame, one st_stats per scene (out[cap], cap >= n).
+ * Synchronizes `stream`. */
+st_status st_batch_stats(const st_batch *b, st_stats *out, int32_t cap, void *stream);
+
+void st_batch_destroy(st_batch *b);
+
+/* Picks the batch tuning with the shortest graph frame among the grid of
+ * st_autotune (tile {8,16,32}, max_new {6,16,64}, sub_depth {1/20, 1/4}),
+ * timing `reps` replays of each candidate with HIP events (median).  Renders
+ * into depths/normals; leaves the scenes' A-buffers built with the last
+ * candidate.  Synchronous.  Errors: those of st_batch_create/render. */
+st_status st_batch_autotune(st_scene *const *scenes, const st_camera *cams, int32_t n, const st_tuning *base,
+                            float *const *depths, float *const *normals, int32_t reps, st_tuning *out,
+                            float *out_ms, void *stream);
+
+/* One-shot: create with default tuning, render once through the graph,
+ * optional stats (stats[n], host), destroy.  Synchronous. */
+st_status st_trace_batch(st_scene *const *scenes, const st_camera *cams, int32_t n, float *const *depths,
+                         float *const *normals, st_stats *stats, void *stream);
+
+/* Test hook: D (float[32][32], row-major) = A (float[32][8]) . B (float[8][32])
+ * rounded to binary16 and multiplied by one matrix instruction, with D read
+ * back through the accumulator layout the inference assumes.  Device arrays.
+ * Errors: ST_E_INVALID, ST_E_DEVICE. */
+st_status st_debug_mfma_probe(const float *A, const float *B, float *D, void *stream);
 
 /*
  * st_debug_eval_field -- test hook: evaluates the pruned field f_A of a given

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "st_internal.h"
+#include "st_mlp.h"
 
 namespace st {
 
@@ -82,6 +83,32 @@ static bool make_devcam(const st_camera& c, DevCam& d) {
     d.w = c.width;
     d.h = c.height;
     return true;
+}
+
+void stats_from_counters(const st_scene* s, const unsigned long long* h, st_stats* out) {
+    std::memset(out, 0, sizeof(*out));
+    out->rays = h[0];
+    out->hits = h[1];
+    out->unconverged = h[2];
+    out->field_evals = h[3];
+    out->grad_evals = h[4];
+    for (int q = 0; q < 4; q++) {
+        out->node_evals[q] = h[5 + q];
+        out->grad_node_evals[q] = h[9 + q];
+    }
+    out->steps = h[13];
+    out->subfrustums = h[14];
+    out->empty_views = h[15];
+    out->view_nodes = h[16];
+    out->max_active = h[17];
+    out->wide_tiles = h[18];
+    out->learned_accepted = h[19];
+    out->learned_rejected = h[20];
+    out->reserved[0] = h[21];   // stalled blocks (must be 0)
+    out->reserved[1] = h[22];   // compact operators evaluated on their smooth branch
+    out->abuffer_entries = uint64_t(s->n_entries);
+    out->max_list = s->max_list;
+    out->max_overlap = s->max_overlap;
 }
 
 static st_status check_tuning(const st_tuning& t) {
@@ -197,6 +224,8 @@ void st_scene_destroy(st_scene* s) {
     dev_free(s, s->d_stats, stream);
     dev_free(s, s->d_misc, stream);
     dev_free(s, s->d_mlp, stream);
+    dev_free(s, s->d_cand, stream);
+    dev_free(s, s->d_long, stream);
     delete s;
 }
 
@@ -264,6 +293,7 @@ st_status st_build_abuffer(st_scene* s, const st_camera* cam, const st_tuning* t
     s->ab_cam = *cam;
     s->ab_tune = t;
     s->ab_valid = true;
+    s->ab_gen++;
     return ST_OK;
 }
 
@@ -287,29 +317,7 @@ st_status st_trace_ex(st_scene* s, const st_camera* cam, float* out_depth, float
         hipError_t e = hipMemcpyAsync(h, s->d_stats, sizeof(h), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return device_error(e, "trace stats");
-        std::memset(out_stats, 0, sizeof(*out_stats));
-        out_stats->rays = h[0];
-        out_stats->hits = h[1];
-        out_stats->unconverged = h[2];
-        out_stats->field_evals = h[3];
-        out_stats->grad_evals = h[4];
-        for (int q = 0; q < 4; q++) {
-            out_stats->node_evals[q] = h[5 + q];
-            out_stats->grad_node_evals[q] = h[9 + q];
-        }
-        out_stats->steps = h[13];
-        out_stats->subfrustums = h[14];
-        out_stats->empty_views = h[15];
-        out_stats->view_nodes = h[16];
-        out_stats->max_active = h[17];
-        out_stats->wide_tiles = h[18];
-        out_stats->learned_accepted = h[19];
-        out_stats->learned_rejected = h[20];
-        out_stats->reserved[0] = h[21];   // stalled blocks (must be 0)
-        out_stats->reserved[1] = h[22];   // compact operators evaluated on their smooth branch
-        out_stats->abuffer_entries = uint64_t(s->n_entries);
-        out_stats->max_list = s->max_list;
-        out_stats->max_overlap = s->max_overlap;
+        stats_from_counters(s, h, out_stats);
     }
     return ST_OK;
 }
@@ -494,6 +502,41 @@ st_status st_debug_abuffer(const st_scene* s, uint32_t* tile_off, size_t tile_ca
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return device_error(e, "abuffer copy");
+    return ST_OK;
+}
+
+st_status st_set_step_model(st_scene* s, const float* weights, const float* norm, void* stream_v) {
+    if (!s || !weights || !norm) { set_error("set_step_model: NULL argument"); return ST_E_INVALID; }
+    hipStream_t stream = (hipStream_t)stream_v;
+    if (!s->d_mlp) {
+        s->d_mlp = (uint32_t*)dev_alloc(s, size_t(kMlpTabWords) * 4, stream);
+        if (!s->d_mlp) { set_error("set_step_model: allocation failed"); return ST_E_NOMEM; }
+    }
+    st_status r = st_mlp_pack(weights, norm, s->d_mlp, stream);
+    if (r == ST_OK) s->has_model = true;
+    return r;
+}
+
+st_status st_trace_dump(st_scene* s, const st_camera* cam, float* out_depth, float* out_normal, float* features,
+                        float* targets, int64_t cap, int64_t* n_samples, void* stream_v) {
+    if (!s || !cam || !out_depth || !out_normal || !n_samples || cap < 0 || (cap > 0 && (!features || !targets))) {
+        set_error("trace_dump: bad argument");
+        return ST_E_INVALID;
+    }
+    hipStream_t stream = (hipStream_t)stream_v;
+    if (!s->ab_valid || std::memcmp(cam, &s->ab_cam, sizeof(st_camera)) != 0) {
+        set_error("trace_dump: the A-buffer was not built for this camera");
+        return ST_E_STALE;
+    }
+    // the sample counter is the last stats word (cleared with the stats)
+    DumpTarget d{features, targets, s->d_stats + (kStatCount - 1), (unsigned long long)cap};
+    st_status r = trace_device(s, s->ab_tune, out_depth, out_normal, nullptr, stream, &d);
+    if (r != ST_OK) return r;
+    unsigned long long h = 0;
+    hipError_t e = hipMemcpyAsync(&h, s->d_stats + (kStatCount - 1), 8, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error(e, "trace_dump count");
+    *n_samples = int64_t(h);
     return ST_OK;
 }
 

@@ -506,7 +506,22 @@ st_status launch_voi(st_scene* s, hipStream_t stream) {
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stream) {
+// clears device words with a kernel (graph-capture safe, unlike memset nodes)
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t n, uint32_t v) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+// replay: the same kernel sequence for an unchanged scene, camera and tuning,
+// reusing the sizes and buffers of the previous build (the counts are
+// deterministic): no host synchronization, no allocation, no memset nodes.
+st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stream, bool replay) {
     const int P = s->n_prims;
     const int T = s->n_tiles;
     const int ts = t.tile;
@@ -522,6 +537,10 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     size_t off_long = align_up(off_cur + size_t(T) * 4);
     size_t off_misc = align_up(off_long + size_t(T) * 4);
     size_t need = align_up(off_misc + 64 * 4);
+    if (replay && (need > s->scratch_bytes || !s->ab_valid)) {
+        set_error("build replay: no previous build of this size");
+        return ST_E_STALE;
+    }
     if (need > s->scratch_bytes) {
         if (s->d_scratch) dev_free(s, s->d_scratch, stream);
         s->d_scratch = dev_alloc(s, need, stream);
@@ -543,27 +562,37 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
                        s->tiles_x, s->tiles_y, rect, count);
     exclusive_scan(count, coff, P, sums, misc + 8, coff + P, stream);
-    uint32_t n_cand = 0;
-    ST_CHECK(hipMemcpyAsync(&n_cand, misc + 8, 4, hipMemcpyDeviceToHost, stream), "copy candidate count");
-    ST_CHECK(hipStreamSynchronize(stream), "sync (candidates)");
+    uint32_t n_cand = replay ? s->n_cand : 0u;
+    if (!replay) {
+        ST_CHECK(hipMemcpyAsync(&n_cand, misc + 8, 4, hipMemcpyDeviceToHost, stream), "copy candidate count");
+        ST_CHECK(hipStreamSynchronize(stream), "sync (candidates)");
+        s->n_cand = n_cand;
+    }
 
     // candidate results: z pair + tile id
     size_t cand_bytes = align_up(size_t(n_cand) * 8) + align_up(size_t(n_cand) * 4) + 256;
-    char* cbuf = (char*)dev_alloc(s, cand_bytes, stream);
-    if (!cbuf && cand_bytes) { set_error("build: candidate buffer allocation failed"); return ST_E_NOMEM; }
+    if (cand_bytes > s->cand_bytes) {   // kept between builds, grown on demand
+        dev_free(s, s->d_cand, stream);
+        s->d_cand = dev_alloc(s, cand_bytes + cand_bytes / 4, stream);
+        s->cand_bytes = s->d_cand ? cand_bytes + cand_bytes / 4 : 0;
+        if (!s->d_cand) { set_error("build: candidate buffer allocation failed"); return ST_E_NOMEM; }
+    }
+    char* cbuf = (char*)s->d_cand;
     float2* cz = (float2*)cbuf;
     uint32_t* ctile = (uint32_t*)(cbuf + align_up(size_t(n_cand) * 8));
 
-    ST_CHECK(hipMemsetAsync(tcnt, 0, size_t(T + 1) * 4, stream), "memset tile counts");
-    ST_CHECK(hipMemsetAsync(misc, 0, 64 * 4, stream), "memset misc");
+    ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
+    ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
     if (n_cand)
         hipLaunchKernelGGL(test_kernel, dim3((n_cand + 255) / 256), dim3(256), 0, stream, s->d_voi, rect, coff, P,
                            n_cand, s->dcam, ts, s->tiles_x, cz, ctile, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
-    uint32_t n_ent = 0;
-    ST_CHECK(hipMemcpyAsync(&n_ent, misc + 9, 4, hipMemcpyDeviceToHost, stream), "copy entry count");
-    ST_CHECK(hipStreamSynchronize(stream), "sync (entries)");
-    s->n_entries = n_ent;
+    uint32_t n_ent = replay ? uint32_t(s->n_entries) : 0u;
+    if (!replay) {
+        ST_CHECK(hipMemcpyAsync(&n_ent, misc + 9, 4, hipMemcpyDeviceToHost, stream), "copy entry count");
+        ST_CHECK(hipStreamSynchronize(stream), "sync (entries)");
+        s->n_entries = n_ent;
+    }
 
     // entry arrays (grown on demand) + long-sort scratch
     if (int64_t(n_ent) > s->ab_cap) {
@@ -575,38 +604,44 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         s->d_e_zin = (float*)dev_alloc(s, size_t(cap) * 4, stream);
         s->d_e_zout = (float*)dev_alloc(s, size_t(cap) * 4, stream);
         if (!s->d_e_node || !s->d_e_zin || !s->d_e_zout) {
-            dev_free(s, cbuf, stream);
             set_error("build: A-buffer allocation failed");
             s->ab_cap = 0;
             return ST_E_NOMEM;
         }
         s->ab_cap = cap;
     }
-    ST_CHECK(hipMemsetAsync(cur, 0, size_t(T) * 4, stream), "memset cursors");
+    ST_CHECK(fill_u32(cur, uint32_t(T), 0u, stream), "clear cursors");
     if (n_cand)
         hipLaunchKernelGGL(scatter_kernel, dim3((n_cand + 255) / 256), dim3(256), 0, stream, s->d_voi, coff, P,
                            n_cand, cz, ctile, s->d_tile_off, cur, s->d_e_node, s->d_e_zin, s->d_e_zout);
-    ST_CHECK(hipMemsetAsync(s->d_wide, 0, 4, stream), "memset wide list");
+    ST_CHECK(fill_u32(s->d_wide, 1u, 0u, stream), "clear wide list");
     hipLaunchKernelGGL(tile_sort_kernel, dim3(T), dim3(kSortThreads), 0, stream, s->d_tile_off, T, s->d_e_node,
                        s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, uint32_t(s->ab_ma_fast), s->d_wide);
     // long tiles, if any (the kernel reads their count on the device)
     size_t long_bytes = size_t(2) * n_ent * (8 + 4 + 4) + 64;
-    char* lbuf = (char*)dev_alloc(s, long_bytes, stream);
-    if (!lbuf) { dev_free(s, cbuf, stream); set_error("build: sort scratch allocation failed"); return ST_E_NOMEM; }
+    if (long_bytes > s->long_bytes) {
+        dev_free(s, s->d_long, stream);
+        s->d_long = dev_alloc(s, long_bytes + long_bytes / 4, stream);
+        s->long_bytes = s->d_long ? long_bytes + long_bytes / 4 : 0;
+        if (!s->d_long) { set_error("build: sort scratch allocation failed"); return ST_E_NOMEM; }
+    }
+    char* lbuf = (char*)s->d_long;
     uint64_t* sk = (uint64_t*)lbuf;
     uint32_t* sv = (uint32_t*)(lbuf + size_t(2) * n_ent * 8);
     uint32_t* sz = (uint32_t*)(lbuf + size_t(2) * n_ent * 12);
     hipLaunchKernelGGL(tile_sort_long_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream,
                        s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, sk, sv, sz,
                        uint32_t(s->ab_ma_fast), s->d_wide);
+    if (replay) {
+        e = hipGetLastError();
+        return e == hipSuccess ? ST_OK : device_error(e, "binning kernels");
+    }
     uint32_t h_misc[4] = {0, 0, 0, 0}, h_wide = 0;
     ST_CHECK(hipMemcpyAsync(h_misc, misc, 16, hipMemcpyDeviceToHost, stream), "copy build stats");
     ST_CHECK(hipMemcpyAsync(&h_wide, s->d_wide, 4, hipMemcpyDeviceToHost, stream), "copy wide count");
     e = hipGetLastError();
-    if (e != hipSuccess) { dev_free(s, cbuf, stream); dev_free(s, lbuf, stream); return device_error(e, "binning kernels"); }
+    if (e != hipSuccess) return device_error(e, "binning kernels");
     ST_CHECK(hipStreamSynchronize(stream), "sync (build)");
-    dev_free(s, cbuf, stream);
-    dev_free(s, lbuf, stream);
     s->max_overlap = h_misc[1];
     s->max_list = h_misc[2];
     s->n_wide = h_wide;

@@ -192,7 +192,7 @@ st_status st_mlp_adam(float* w, float* m, float* v, const float* grad, int32_t n
     return e == hipSuccess ? ST_OK : device_error(e, "mlp_adam_kernel");
 }
 
-st_status st_mfma_probe(const float* A, const float* B, float* D, void* stream) {
+st_status st_debug_mfma_probe(const float* A, const float* B, float* D, void* stream) {
     if (!A || !B || !D) { set_error("mfma_probe: NULL argument"); return ST_E_INVALID; }
     hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, A, B, D);
     hipError_t e = hipGetLastError();

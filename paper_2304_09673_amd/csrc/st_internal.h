@@ -44,6 +44,8 @@ struct st_scene {
     uint32_t* d_wide = nullptr;       // list of tiles that need the wide path, [0] = count
     uint32_t* d_misc = nullptr;       // small device counters
     int64_t n_entries = 0, ab_cap = 0;
+    uint32_t n_cand = 0;        // (primitive, tile) candidates of the last build
+    uint64_t ab_gen = 0;        // bumped by every st_build_abuffer
     uint32_t max_list = 0, max_overlap = 0, n_wide = 0;
     int32_t ab_ma_fast = 0, ab_ma_wide = 0;
 
@@ -54,9 +56,13 @@ struct st_scene {
     // scratch kept between builds
     void* d_scratch = nullptr;
     size_t scratch_bytes = 0;
+    void* d_cand = nullptr;     // candidate (primitive, tile) results
+    size_t cand_bytes = 0;
+    void* d_long = nullptr;     // sort scratch of long tile lists
+    size_t long_bytes = 0;
 
     // step model (learned step)
-    float* d_mlp = nullptr;
+    uint32_t* d_mlp = nullptr;   // packed operand table
     bool has_model = false;
 
     // device counters for one trace
@@ -76,11 +82,19 @@ void dev_free(st_scene* s, void* p, hipStream_t stream);
 
 // binning.hip
 st_status launch_voi(st_scene* s, hipStream_t stream);
-st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stream);
+st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stream, bool replay = false);
+hipError_t fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t stream);
 
 // trace.hip
+// training-sample output of the dump mode (device pointers)
+struct DumpTarget {
+    float* x;                  // [cap][8] features
+    float* t;                  // [cap] target omega
+    unsigned long long* n;     // samples produced (may exceed cap)
+    unsigned long long cap;
+};
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
-                       hipStream_t stream);
+                       hipStream_t stream, const DumpTarget* dump = nullptr);
 st_status debug_eval_device(const st_scene* s, const uint32_t* active_post, int n_active,
                             const float* pts, int n_pts, float* out_f, float* out_grad,
                             int* root_used, hipStream_t stream);
@@ -91,5 +105,8 @@ PruneResult host_prune(const st_scene* s, std::vector<uint32_t> active_post,
                        std::vector<uint32_t>& view);
 
 constexpr int kStatCount = 48;
+
+// st_stats from the device counters of one trace (api.hip)
+void stats_from_counters(const st_scene* s, const unsigned long long* counters, st_stats* out);
 
 }  // namespace st

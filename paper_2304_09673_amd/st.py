@@ -22,8 +22,14 @@ EXPORTS = (
     "st_status_str", "st_last_error", "st_default_tuning", "st_flatten_blobtree", "st_scene_destroy",
     "st_scene_get_info", "st_build_abuffer", "st_trace", "st_trace_ex", "st_autotune", "st_debug_eval_field",
     "st_debug_prune_tree",
-    "st_debug_abuffer",
+    "st_debug_abuffer", "st_mlp_pack", "st_mlp_forward", "st_mlp_grad", "st_mlp_adam", "st_set_step_model",
+    "st_trace_dump", "st_debug_mfma_probe", "st_batch_create", "st_batch_render", "st_batch_stats",
+    "st_batch_destroy", "st_batch_autotune", "st_trace_batch",
 )
+
+MLP_PARAMS = 1377
+MLP_FEATURES = 8
+MLP_TABLE_WORDS = 59 * 64 + 16
 
 
 class StError(RuntimeError):
@@ -102,6 +108,23 @@ def lib():
         L.st_debug_eval_field.argtypes = [vp, vp, i32, vp, i32, vp, vp, C.POINTER(i32), vp, i32, C.POINTER(i32), vp]
         L.st_debug_prune_tree.argtypes = [C.POINTER(StNode), i32, i32, vp, i32, vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]
         L.st_debug_abuffer.argtypes = [vp, vp, sz, vp, sz, C.POINTER(i32), C.POINTER(i64), vp]
+        L.st_mlp_pack.argtypes = [vp, vp, vp, vp]
+        L.st_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+        L.st_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+        L.st_mlp_adam.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.st_set_step_model.argtypes = [vp, vp, vp, vp]
+        L.st_trace_dump.argtypes = [vp, C.POINTER(StCamera), vp, vp, vp, vp, i64, C.POINTER(i64), vp]
+        L.st_debug_mfma_probe.argtypes = [vp, vp, vp, vp]
+        L.st_batch_create.argtypes = [C.POINTER(vp), C.POINTER(StCamera), i32, C.POINTER(StTuning), C.POINTER(vp),
+                                      C.POINTER(vp), vp, C.POINTER(vp)]
+        L.st_batch_render.argtypes = [vp, i32, vp]
+        L.st_batch_stats.argtypes = [vp, C.POINTER(StStats), i32, vp]
+        L.st_batch_destroy.restype = None
+        L.st_batch_destroy.argtypes = [vp]
+        L.st_batch_autotune.argtypes = [C.POINTER(vp), C.POINTER(StCamera), i32, C.POINTER(StTuning), C.POINTER(vp),
+                                        C.POINTER(vp), i32, C.POINTER(StTuning), C.POINTER(C.c_float), vp]
+        L.st_trace_batch.argtypes = [C.POINTER(vp), C.POINTER(StCamera), i32, C.POINTER(vp), C.POINTER(vp),
+                                     C.POINTER(StStats), vp]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is C.c_int or name in ("st_default_tuning",):
@@ -244,6 +267,32 @@ class Scene:
                                          _stream_ptr(stream)))
         return f, g, int(used.value), view[: vlen.value].copy()
 
+    def set_step_model(self, weights, norm, stream=None):
+        """st_set_step_model: weights float32 CUDA [1377], norm float32 CUDA [16]."""
+        _f32_cuda(weights, MLP_PARAMS)
+        _f32_cuda(norm, 16)
+        _check(lib().st_set_step_model(self._h, _ptr(weights), _ptr(norm), _stream_ptr(stream)))
+
+    def trace_dump(self, features, targets, camera=None, depth=None, normal=None, stream=None):
+        """st_trace_dump into float32 CUDA tensors features [cap, 8] and targets [cap].
+        Returns (samples produced, depth, normal)."""
+        import torch
+        cam = make_camera(camera) if camera is not None else self._cam
+        W, H = cam.width, cam.height
+        if depth is None:
+            depth = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        if normal is None:
+            normal = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        _f32_cuda(depth, H * W)
+        _f32_cuda(normal, 3 * H * W)
+        cap = targets.numel()
+        _f32_cuda(targets, cap)
+        _f32_cuda(features, 8 * cap)
+        n = C.c_int64(0)
+        _check(lib().st_trace_dump(self._h, C.byref(cam), _ptr(depth), _ptr(normal), _ptr(features), _ptr(targets),
+                                   cap, C.byref(n), _stream_ptr(stream)))
+        return int(n.value), depth, normal
+
     def debug_abuffer(self, stream=None):
         """(tile_off[T+1], node[E], z_in[E], z_out[E]) of the current A-buffer (host numpy)."""
         nt, ne = C.c_int32(0), C.c_int64(0)
@@ -255,6 +304,125 @@ class Scene:
                                       _stream_ptr(stream)))
         e = ent[: 3 * ne.value].reshape(-1, 3)
         return off, e[:, 0].astype(np.int64), e[:, 1].view(np.float32), e[:, 2].view(np.float32)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _f32_cuda(t, numel):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == numel):
+        raise ValueError(f"expected a contiguous float32 CUDA tensor of {numel} elements")
+
+
+def mlp_pack(weights, norm, table=None, stream=None):
+    """st_mlp_pack -> packed table (int32 CUDA tensor [MLP_TABLE_WORDS])."""
+    import torch
+    _f32_cuda(weights, MLP_PARAMS)
+    _f32_cuda(norm, 16)
+    if table is None:
+        table = torch.empty(MLP_TABLE_WORDS, dtype=torch.int32, device="cuda")
+    _check(lib().st_mlp_pack(_ptr(weights), _ptr(norm), _ptr(table), _stream_ptr(stream)))
+    return table
+
+
+def mlp_forward(table, x, out=None, stream=None):
+    """st_mlp_forward: omega of raw features x [n, 8] (float32 CUDA)."""
+    import torch
+    n = x.numel() // 8
+    _f32_cuda(x, 8 * n)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+    _f32_cuda(out, n)
+    _check(lib().st_mlp_forward(_ptr(table), _ptr(x), n, _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def mlp_grad(weights, norm, x, target, grad=None, loss=None, stream=None):
+    """st_mlp_grad -> (grad [1377], loss [1]) CUDA tensors."""
+    import torch
+    n = target.numel()
+    _f32_cuda(weights, MLP_PARAMS)
+    _f32_cuda(norm, 16)
+    _f32_cuda(x, 8 * n)
+    _f32_cuda(target, n)
+    if grad is None:
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().st_mlp_grad(_ptr(weights), _ptr(norm), _ptr(x), _ptr(target), n, _ptr(grad), _ptr(loss),
+                             _stream_ptr(stream)))
+    return grad, loss
+
+
+def mlp_adam(w, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """st_mlp_adam: in-place update of w, m, v (float32 CUDA, same size)."""
+    n = w.numel()
+    for t in (w, m, v, grad):
+        _f32_cuda(t, n)
+    _check(lib().st_mlp_adam(_ptr(w), _ptr(m), _ptr(v), _ptr(grad), n, int(step), float(lr), float(beta1),
+                             float(beta2), float(eps), _stream_ptr(stream)))
+
+
+def debug_mfma_probe(a, b, stream=None):
+    """st_debug_mfma_probe: D [32, 32] = A [32, 8] . B [8, 32] (float32 CUDA)."""
+    import torch
+    _f32_cuda(a, 256)
+    _f32_cuda(b, 256)
+    d = torch.empty((32, 32), dtype=torch.float32, device="cuda")
+    _check(lib().st_debug_mfma_probe(_ptr(a), _ptr(b), _ptr(d), _stream_ptr(stream)))
+    return d
+
+
+class Batch:
+    """Many scenes rendered per frame by one graph launch (st_batch_*).  Owns
+    its output tensors (depths[i] [H,W], normals[i] [H,W,3]); the Scene
+    objects must stay alive while the batch exists."""
+
+    def __init__(self, scenes, cameras, tuning: StTuning | None = None, stream=None, autotune: bool = False,
+                 reps: int = 2):
+        import torch
+        self.scenes = list(scenes)
+        n = len(self.scenes)
+        self._cams = (StCamera * n)(*[make_camera(c) for c in cameras])
+        self.depths = [torch.empty((c.height, c.width), dtype=torch.float32, device="cuda") for c in self._cams]
+        self.normals = [torch.empty((c.height, c.width, 3), dtype=torch.float32, device="cuda") for c in self._cams]
+        self._hs = (C.c_void_p * n)(*[sc._h.value for sc in self.scenes])
+        self._dp = (C.c_void_p * n)(*[d.data_ptr() for d in self.depths])
+        self._np = (C.c_void_p * n)(*[x.data_ptr() for x in self.normals])
+        self.tune_ms = None
+        if autotune:
+            out = StTuning()
+            ms = C.c_float(0)
+            _check(lib().st_batch_autotune(self._hs, self._cams, n, C.byref(tuning) if tuning else None, self._dp,
+                                           self._np, int(reps), C.byref(out), C.byref(ms), _stream_ptr(stream)))
+            tuning, self.tune_ms = out, float(ms.value)
+        self.tuning = tuning if tuning is not None else default_tuning()
+        h = C.c_void_p()
+        _check(lib().st_batch_create(self._hs, self._cams, n, C.byref(self.tuning), self._dp, self._np,
+                                     _stream_ptr(stream), C.byref(h)))
+        self._h = h
+
+    def render(self, use_graph: bool = True, stream=None):
+        _check(lib().st_batch_render(self._h, int(bool(use_graph)), _stream_ptr(stream)))
+
+    def stats(self, stream=None):
+        n = len(self.scenes)
+        arr = (StStats * n)()
+        _check(lib().st_batch_stats(self._h, arr, n, _stream_ptr(stream)))
+        return [a.as_dict() for a in arr]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().st_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def prune_tree(kind, left, right, params, root, active):

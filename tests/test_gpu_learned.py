@@ -1,0 +1,179 @@
+"""Relaxed stepping: the dump tracer, the over-relaxed tracer (factor 1.7) and
+the learned step.  Each must give the plain tracer's images up to the parity
+rules (the sphere-overlap test keeps every accepted step conservative), and
+the learned one is compared with the plain one at equal depth error."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+from gpu_util import all_pixels, compare, sample_pixels
+
+pytestmark = pytest.mark.gpu
+
+GRID = 1.0 + 0.25 * np.arange(13)
+
+
+def _st():
+    from paper_2304_09673_amd import st
+    return st
+
+
+@pytest.fixture(scope="module")
+def model():
+    """Step model trained on dumps of small first- and second-workload scenes."""
+    from paper_2304_09673_amd import stepmodel
+    scenes = [sg.config1(seed=s, width=128, height=128) for s in range(4)] + [sg.config2(seed=s, width=256, height=256) for s in range(2)]
+    X, T = stepmodel.collect(scenes, cap_per_scene=1 << 19)
+    assert X.shape[0] > 10000
+    w, norm, losses = stepmodel.fit(X, T, epochs=6, batch=4096, lr=3e-3, seed=0)
+    assert losses[-1] < losses[0]
+    return w, norm
+
+
+def _render(sc, mode, model=None, tuning_kw=None):
+    import torch
+    st = _st()
+    kw = dict(tuning_kw or {})
+    tune = st.default_tuning(step_mode=mode, **kw)
+    s = st.Scene(sc)
+    if model is not None:
+        s.set_step_model(*model)
+    s.build_abuffer(sc.camera, tune)
+    d, n, stats = s.trace()
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), n.cpu().numpy(), stats
+
+
+def test_dump_outputs_equal_plain_and_targets_on_grid():
+    import torch
+    st = _st()
+    sc = sg.config1(seed=0, width=128, height=128)
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera, st.default_tuning())
+    d0, n0, _ = s.trace()
+    d0, n0 = d0.cpu().numpy(), n0.cpu().numpy()
+    cap = 1 << 18
+    feats = torch.empty((cap, 8), dtype=torch.float32, device="cuda")
+    targ = torch.empty(cap, dtype=torch.float32, device="cuda")
+    n, d1, n1 = s.trace_dump(feats, targ)
+    assert 0 < n <= cap
+    np.testing.assert_array_equal(d1.cpu().numpy(), d0)
+    np.testing.assert_array_equal(n1.cpu().numpy(), n0)
+    f = feats[:n].cpu().numpy()
+    t = targ[:n].cpu().numpy()
+    assert np.isfinite(f).all()
+    assert np.isin(t, GRID).all()
+    assert (f[:, 0] >= 1e-4).all()          # proposals only at safe steps >= eps
+    assert (t > 1.0).mean() > 0.5           # relaxation usually possible
+
+
+def test_dump_capacity_truncates():
+    import torch
+    st = _st()
+    sc = sg.config1(seed=1, width=64, height=64)
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera, st.default_tuning())
+    feats = torch.full((16, 8), -7.0, device="cuda")
+    targ = torch.full((17,), -7.0, device="cuda")
+    n, _, _ = s.trace_dump(feats, targ[:16])
+    assert n > 16
+    assert float(targ[16].cpu()) == -7.0     # nothing written past cap
+    assert (targ[:16].cpu().numpy() >= 1.0).all()
+
+
+@pytest.mark.parametrize("which,seed", [("c1", 0), ("c1", 3), ("c2", 0), ("c2", 2)])
+def test_overrelaxed_parity(which, seed):
+    st = _st()
+    sc = sg.config1(seed=seed, width=128, height=128) if which == "c1" else sg.config2(seed=seed, width=256, height=256)
+    d_p, _, s_p = _render(sc, st.ST_STEP_PLAIN)
+    d_o, n_o, s_o = _render(sc, st.ST_STEP_OVERRELAX, tuning_kw={"omega": 1.7})
+    px, py = all_pixels(sc.camera)
+    r = compare(sc, d_o, n_o, px, py)
+    assert r["fail"] == 0, r
+    np.testing.assert_array_equal(np.isfinite(d_o), np.isfinite(d_p))
+    assert s_o["learned_accepted"] > 0
+    assert s_o["unconverged"] == 0
+
+
+@pytest.mark.parametrize("which,seed", [("c1", 5), ("c2", 3), ("c2", 4)])
+def test_learned_parity(model, which, seed):
+    st = _st()
+    sc = sg.config1(seed=seed, width=128, height=128) if which == "c1" else sg.config2(seed=seed, width=256, height=256)
+    d_p, _, s_p = _render(sc, st.ST_STEP_PLAIN)
+    d_l, n_l, s_l = _render(sc, st.ST_STEP_LEARNED, model=model)
+    px, py = all_pixels(sc.camera)
+    r = compare(sc, d_l, n_l, px, py)
+    assert r["fail"] == 0, r
+    np.testing.assert_array_equal(np.isfinite(d_l), np.isfinite(d_p))
+    assert s_l["learned_accepted"] > 0
+    assert s_l["unconverged"] == 0
+    # fewer stepping evaluations than plain
+    assert s_l["steps"] < s_p["steps"], (s_l["steps"], s_p["steps"])
+
+
+def test_learned_requires_model():
+    st = _st()
+    sc = sg.config1(seed=0, width=64, height=64)
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera, st.default_tuning(step_mode=st.ST_STEP_LEARNED))
+    with pytest.raises(st.StError):
+        s.trace()
+
+
+def _timed(s, reps=3):
+    import torch
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        d, n, _ = s.trace(stats=False)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts)), d, n
+
+
+def test_learned_vs_plain_on_large_scene(model):
+    """16384 primitives of the second workload's laws at 480x270: identical hit
+    masks, depth error against the oracle no worse than plain on sampled hit
+    rays; steps and time are reported."""
+    st = _st()
+    sc = sg.config5(width=480, height=270)
+    kw = {"tile": 16, "max_new": 64, "sub_depth": 0.25}
+    out = {}
+    for name, mode in (("plain", st.ST_STEP_PLAIN), ("overrelax", st.ST_STEP_OVERRELAX),
+                       ("learned", st.ST_STEP_LEARNED)):
+        s = st.Scene(sc)
+        if mode == st.ST_STEP_LEARNED:
+            s.set_step_model(*model)
+        s.build_abuffer(sc.camera, st.default_tuning(step_mode=mode, **kw))
+        _, _, stats = s.trace()
+        ms, d, n = _timed(s)
+        out[name] = (ms, d.cpu().numpy(), n.cpu().numpy(), stats)
+    d_p = out["plain"][1]
+    hit = np.isfinite(d_p)
+    for name in ("overrelax", "learned"):
+        np.testing.assert_array_equal(np.isfinite(out[name][1]), hit)
+    # depth error on up to 96 hit pixels plus 32 random ones
+    jj, ii = np.nonzero(hit)
+    rng = np.random.default_rng(3)
+    pick = rng.permutation(jj.shape[0])[:96]
+    rx, ry = sample_pixels(sc.camera, 32, 4)
+    px = np.concatenate([ii[pick], rx])
+    py = np.concatenate([jj[pick], ry])
+    osc = oracle.OracleScene(sc)
+    errs = {}
+    for name in ("plain", "learned"):
+        r = compare(sc, out[name][1], out[name][2], px, py, osc=osc)
+        assert r["fail"] == 0, (name, r)
+        errs[name] = r["max_depth_err_rel"]
+    assert errs["learned"] <= max(2.0 * errs["plain"], 1e-6)
+    for name in out:
+        ms, _, _, stats = out[name]
+        print(f"{name}: {ms:.2f} ms, {sc.camera.width * sc.camera.height / ms / 1e3:.2f} Mrays/s, "
+              f"steps {stats['steps']}, evals {stats['field_evals']}, accepted {stats['learned_accepted']}, "
+              f"rejected {stats['learned_rejected']}")
+    print("depth error (max rel):", errs)
