@@ -110,8 +110,9 @@ def bench_batch(args):
     cams = [sc.camera for sc in scs]
     t0 = time.perf_counter()
     if args.no_autotune:
-        b = st.Batch(handles, cams, tuning=st.default_tuning(tile=args.tile))
-        tuned = "defaults"
+        b = st.Batch(handles, cams, tuning=st.default_tuning(tile=args.tile, max_new=args.max_new,
+                                                             sub_depth=args.sub_depth))
+        tuned = "fixed"
     else:
         b = st.Batch(handles, cams, autotune=True, reps=1)
         tuned = "autotuned"
@@ -163,6 +164,8 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--max-new", type=int, default=64)
+    ap.add_argument("--sub-depth", type=float, default=0.25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=6144)
     ap.add_argument("--no-autotune", action="store_true")
@@ -194,8 +197,8 @@ def main():
     scene = st.Scene(sc)
     flatten_ms = (time.perf_counter() - t0) * 1e3
     if args.no_autotune:
-        tune = st.default_tuning(tile=args.tile)
-        tuned = "defaults"
+        tune = st.default_tuning(tile=args.tile, max_new=args.max_new, sub_depth=args.sub_depth)
+        tuned = "fixed"
     else:
         # set-up, outside the timed region: grid search of tile size, fetch
         # cap and fetch-ahead depth with device timing
