@@ -270,6 +270,9 @@ def main():
         "abuffer_entries": stats["abuffer_entries"],
         "max_overlap": stats["max_overlap"],
         "max_active": stats["max_active"],
+        "subfrustums": stats["subfrustums"],
+        "empty_views": stats["empty_views"],
+        "view_nodes": stats["view_nodes"],
         "wide_tiles": stats["wide_tiles"],
         "roofline": {"bound": "alu", "kernel": "trace (trace_fast_kernel + trace_wide_kernel)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",

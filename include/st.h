@@ -181,6 +181,23 @@ void st_scene_destroy(st_scene *s);
 st_status st_scene_get_info(const st_scene *s, st_scene_info *info);
 
 /*
+ * st_update_primitives -- new parameters for existing primitives without
+ * re-flattening (the paper's point that editing primitive parameters needs
+ * no preprocessing, Sections 1 and 5: ranges of interest and Lipschitz
+ * factors depend on the operators only).
+ *   ids[n] (host): caller node indices of primitives; nodes[n] (host): their
+ *   new values (same kind, left = right = -1, parameters validated as in
+ *   st_flatten_blobtree).
+ * Uploads the parameter blocks, recomputes every volume of interest on the
+ * device and the scene's extent and box on the host, and marks the A-buffer
+ * stale (st_trace returns ST_E_STALE until st_build_abuffer).  Synchronizes
+ * `stream`.  Nothing is changed if any entry is rejected.
+ * Errors: ST_E_INVALID (bad index, not a primitive, kind changed, invalid
+ * parameters), ST_E_TREE (children given), ST_E_DEVICE.
+ */
+st_status st_update_primitives(st_scene *s, const int32_t *ids, const st_node *nodes, int32_t n, void *stream);
+
+/*
  * st_build_abuffer -- per-tile A-buffer of volumes of interest (Section 6.2):
  * for every screen tile, the list of primitives whose volume of interest meets
  * a pixel-centre ray of the tile, with the tile's entry/exit view depth

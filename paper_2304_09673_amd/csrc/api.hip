@@ -242,6 +242,47 @@ st_status st_scene_get_info(const st_scene* s, st_scene_info* info) {
     return ST_OK;
 }
 
+st_status st_update_primitives(st_scene* s, const int32_t* ids, const st_node* nodes, int32_t n, void* stream_v) {
+    if (!s || n < 0 || (n > 0 && (!ids || !nodes))) { set_error("update: bad argument"); return ST_E_INVALID; }
+    if (n == 0) return ST_OK;
+    hipStream_t stream = (hipStream_t)stream_v;
+    // validate everything before touching the scene
+    std::vector<int32_t> slot(static_cast<size_t>(n));
+    for (int i = 0; i < n; i++) {
+        int32_t c = ids[i];
+        if (c < 0 || c >= s->n_nodes) { set_error("update: node index out of range"); return ST_E_INVALID; }
+        int32_t p = s->post_of_caller[size_t(c)];
+        if (!blob_prim(s->h_blob[size_t(p)])) { set_error("update: node is not a primitive"); return ST_E_INVALID; }
+        if (nodes[i].kind != blob_op(s->h_blob[size_t(p)])) { set_error("update: primitive kind changed"); return ST_E_INVALID; }
+        st_status r = validate_primitive(nodes[i], c);
+        if (r != ST_OK) return r;
+        auto it = std::lower_bound(s->h_prims.begin(), s->h_prims.end(), uint32_t(p));
+        slot[size_t(i)] = int32_t(it - s->h_prims.begin());
+    }
+    for (int i = 0; i < n; i++) {
+        int32_t p = s->post_of_caller[size_t(ids[i])];
+        primitive_params(nodes[i], double(s->h_roi[size_t(p)]), s->h_par[size_t(p)], s->h_box[size_t(slot[size_t(i)])]);
+    }
+    scene_bounds(s);
+    hipError_t e = hipSuccess;
+    if (n <= 64) {
+        for (int i = 0; i < n && e == hipSuccess; i++) {
+            size_t p = size_t(s->post_of_caller[size_t(ids[i])]);
+            e = hipMemcpyAsync(s->d_par + p, &s->h_par[p], sizeof(NodePar), hipMemcpyHostToDevice, stream);
+        }
+    } else {
+        e = hipMemcpyAsync(s->d_par, s->h_par.data(), s->h_par.size() * sizeof(NodePar), hipMemcpyHostToDevice, stream);
+    }
+    if (e != hipSuccess) return device_error(e, "update: upload");
+    st_status r = launch_voi(s, stream);
+    if (r != ST_OK) return r;
+    // the host copies are read by the asynchronous uploads
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error(e, "update: sync");
+    s->ab_valid = false;   // the A-buffer must be rebuilt
+    return ST_OK;
+}
+
 st_status st_build_abuffer(st_scene* s, const st_camera* cam, const st_tuning* tin, void* stream_v) {
     if (!s || !cam) { set_error("build: NULL argument"); return ST_E_INVALID; }
     hipStream_t stream = (hipStream_t)stream_v;

@@ -43,6 +43,90 @@ void quat_axes(const float q_in[4], double axes[3][3]) {
 
 }  // namespace
 
+st_status validate_primitive(const st_node& nd, int i) {
+    uint32_t k = nd.kind;
+    if (nd.left != -1 || nd.right != -1) {
+        set_error("primitive " + std::to_string(i) + " has children");
+        return ST_E_TREE;
+    }
+    int cnt = k == ST_SPHERE ? 4 : k == ST_BOX ? 10 : 7;
+    if (!finite_params(nd, cnt)) { set_error("non-finite primitive parameter"); return ST_E_INVALID; }
+    if (k == ST_SPHERE && !(nd.p[3] > 0)) { set_error("sphere radius <= 0"); return ST_E_INVALID; }
+    if (k == ST_BOX) {
+        if (!(nd.p[3] > 0 && nd.p[4] > 0 && nd.p[5] > 0)) { set_error("box extent <= 0"); return ST_E_INVALID; }
+        double qn = 0;
+        for (int j = 6; j < 10; j++) qn += double(nd.p[j]) * nd.p[j];
+        if (!(qn > 1e-20)) { set_error("zero quaternion"); return ST_E_INVALID; }
+    }
+    if (k == ST_CAPSULE && !(nd.p[6] > 0)) { set_error("capsule radius <= 0"); return ST_E_INVALID; }
+    return ST_OK;
+}
+
+void primitive_params(const st_node& nd, double d, NodePar& par, PrimBox& box) {
+    float* q = par.v;
+    for (int j = 0; j < 16; j++) q[j] = 0.f;
+    switch (nd.kind) {
+    case ST_SPHERE: {
+        for (int j = 0; j < 4; j++) q[j] = nd.p[j];
+        for (int j = 0; j < 3; j++) {
+            box.lo[j] = double(nd.p[j]) - nd.p[3];
+            box.hi[j] = double(nd.p[j]) + nd.p[3];
+            box.vlo[j] = box.lo[j] - d;
+            box.vhi[j] = box.hi[j] + d;
+        }
+        break;
+    }
+    case ST_BOX: {
+        double ax[3][3];
+        quat_axes(nd.p + 6, ax);
+        for (int j = 0; j < 3; j++) q[j] = nd.p[j];
+        for (int a = 0; a < 3; a++) {
+            for (int c = 0; c < 3; c++) q[4 + 4 * a + c] = float(ax[a][c]);
+            q[7 + 4 * a] = nd.p[3 + a];
+        }
+        for (int j = 0; j < 3; j++) {
+            double e = 0, ev = 0;
+            for (int a = 0; a < 3; a++) {
+                e += std::fabs(ax[a][j]) * nd.p[3 + a];
+                ev += std::fabs(ax[a][j]) * (nd.p[3 + a] + d);   // VOI box: offset along the box axes
+            }
+            box.lo[j] = nd.p[j] - e; box.hi[j] = nd.p[j] + e;
+            box.vlo[j] = nd.p[j] - ev; box.vhi[j] = nd.p[j] + ev;
+        }
+        break;
+    }
+    default: {   // capsule
+        double ba[3], bb = 0;
+        for (int j = 0; j < 3; j++) { q[j] = nd.p[j]; ba[j] = double(nd.p[3 + j]) - nd.p[j]; q[4 + j] = float(ba[j]); bb += ba[j] * ba[j]; }
+        q[3] = nd.p[6];
+        q[7] = bb > 0 ? float(1.0 / bb) : 0.f;
+        for (int j = 0; j < 3; j++) {
+            box.lo[j] = std::min<double>(nd.p[j], nd.p[3 + j]) - nd.p[6];
+            box.hi[j] = std::max<double>(nd.p[j], nd.p[3 + j]) + nd.p[6];
+            box.vlo[j] = box.lo[j] - d;
+            box.vhi[j] = box.hi[j] + d;
+        }
+    }
+    }
+}
+
+void scene_bounds(st_scene* s) {
+    double ext_lo[3] = {INFINITY, INFINITY, INFINITY}, ext_hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double voi_lo[3] = {INFINITY, INFINITY, INFINITY}, voi_hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (const PrimBox& b : s->h_box)
+        for (int j = 0; j < 3; j++) {
+            ext_lo[j] = std::min(ext_lo[j], b.lo[j]); ext_hi[j] = std::max(ext_hi[j], b.hi[j]);
+            voi_lo[j] = std::min(voi_lo[j], b.vlo[j]); voi_hi[j] = std::max(voi_hi[j], b.vhi[j]);
+        }
+    double e = 0;
+    for (int j = 0; j < 3; j++) {
+        e = std::max(e, ext_hi[j] - ext_lo[j]);
+        s->voi_lo[j] = float(voi_lo[j]);
+        s->voi_hi[j] = float(voi_hi[j]);
+    }
+    s->extent = float(e);
+}
+
 st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* s) {
     if (!nodes || n <= 0 || root < 0 || root >= n) {
         set_error("flatten: NULL nodes, n <= 0 or root out of range");
@@ -57,20 +141,8 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
         const st_node& nd = nodes[i];
         uint32_t k = nd.kind;
         if (is_prim_kind(k)) {
-            if (nd.left != -1 || nd.right != -1) {
-                set_error("flatten: primitive " + std::to_string(i) + " has children");
-                return ST_E_TREE;
-            }
-            int cnt = k == ST_SPHERE ? 4 : k == ST_BOX ? 10 : 7;
-            if (!finite_params(nd, cnt)) { set_error("flatten: non-finite primitive parameter"); return ST_E_INVALID; }
-            if (k == ST_SPHERE && !(nd.p[3] > 0)) { set_error("flatten: sphere radius <= 0"); return ST_E_INVALID; }
-            if (k == ST_BOX) {
-                if (!(nd.p[3] > 0 && nd.p[4] > 0 && nd.p[5] > 0)) { set_error("flatten: box extent <= 0"); return ST_E_INVALID; }
-                double qn = 0;
-                for (int j = 6; j < 10; j++) qn += double(nd.p[j]) * nd.p[j];
-                if (!(qn > 1e-20)) { set_error("flatten: zero quaternion"); return ST_E_INVALID; }
-            }
-            if (k == ST_CAPSULE && !(nd.p[6] > 0)) { set_error("flatten: capsule radius <= 0"); return ST_E_INVALID; }
+            st_status r = validate_primitive(nd, i);
+            if (r != ST_OK) return r;
         } else if (is_op_kind(k)) {
             if (nd.left < 0 || nd.left >= n || nd.right < 0 || nd.right >= n || nd.left == nd.right) {
                 set_error("flatten: operator " + std::to_string(i) + " has invalid children");
@@ -165,95 +237,34 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
     }
 
     // parameters, bounds
-    double ext_lo[3] = {INFINITY, INFINITY, INFINITY}, ext_hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double voi_lo[3] = {INFINITY, INFINITY, INFINITY}, voi_hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double Lmax = 1.0;
     int nprim = 0;
+    s->h_box.clear();
     for (int p = 0; p < n; p++) {
         const st_node& nd = nodes[order[p]];
         float* q = s->h_par[p].v;
-        double d = roi[p];
-        auto grow = [&](const double lo[3], const double hi[3], double off) {
-            for (int j = 0; j < 3; j++) {
-                ext_lo[j] = std::min(ext_lo[j], lo[j]); ext_hi[j] = std::max(ext_hi[j], hi[j]);
-                voi_lo[j] = std::min(voi_lo[j], lo[j] - off); voi_hi[j] = std::max(voi_hi[j], hi[j] + off);
-            }
-        };
-        switch (nd.kind) {
-        case ST_SPHERE: {
-            for (int j = 0; j < 4; j++) q[j] = nd.p[j];
-            double lo[3], hi[3];
-            for (int j = 0; j < 3; j++) { lo[j] = double(nd.p[j]) - nd.p[3]; hi[j] = double(nd.p[j]) + nd.p[3]; }
-            grow(lo, hi, d);
-            break;
-        }
-        case ST_BOX: {
-            double ax[3][3];
-            quat_axes(nd.p + 6, ax);
-            for (int j = 0; j < 3; j++) q[j] = nd.p[j];
-            for (int a = 0; a < 3; a++) {
-                for (int c = 0; c < 3; c++) q[4 + 4 * a + c] = float(ax[a][c]);
-                q[7 + 4 * a] = nd.p[3 + a];
-            }
-            double lo[3], hi[3];
-            for (int j = 0; j < 3; j++) {
-                double e = 0;
-                for (int a = 0; a < 3; a++) e += std::fabs(ax[a][j]) * nd.p[3 + a];
-                lo[j] = nd.p[j] - e; hi[j] = nd.p[j] + e;
-            }
-            grow(lo, hi, 0.0);
-            // VOI box: offset along the box axes
-            double lo2[3], hi2[3];
-            for (int j = 0; j < 3; j++) {
-                double e = 0;
-                for (int a = 0; a < 3; a++) e += std::fabs(ax[a][j]) * (nd.p[3 + a] + d);
-                lo2[j] = nd.p[j] - e; hi2[j] = nd.p[j] + e;
-                voi_lo[j] = std::min(voi_lo[j], lo2[j]); voi_hi[j] = std::max(voi_hi[j], hi2[j]);
-            }
-            break;
-        }
-        case ST_CAPSULE: {
-            double ba[3], bb = 0;
-            for (int j = 0; j < 3; j++) { q[j] = nd.p[j]; ba[j] = double(nd.p[3 + j]) - nd.p[j]; q[4 + j] = float(ba[j]); bb += ba[j] * ba[j]; }
-            q[3] = nd.p[6];
-            q[7] = bb > 0 ? float(1.0 / bb) : 0.f;
-            double lo[3], hi[3];
-            for (int j = 0; j < 3; j++) {
-                lo[j] = std::min<double>(nd.p[j], nd.p[3 + j]) - nd.p[6];
-                hi[j] = std::max<double>(nd.p[j], nd.p[3 + j]) + nd.p[6];
-            }
-            grow(lo, hi, d);
-            break;
-        }
-        default: {
-            if (is_compact_kind(nd.kind)) {
-                double kk = nd.p[0], dd = nd.p[1] > 0 ? nd.p[1] : 7.0 * kk / 6.0;
-                q[0] = float(kk);
-                q[1] = float(1.0 / kk);
-                q[2] = float(6.0 * kk / (6.0 * dd - kk));
-                q[3] = float(dd);
-                q[4] = float(1.0 + kk / (6.0 * dd - kk));
-                q[5] = float(kk / 6.0);
-            } else {
-                q[4] = 1.f;
-            }
-        }
-        }
         if (is_prim_kind(nd.kind)) {
+            PrimBox box;
+            primitive_params(nd, roi[p], s->h_par[p], box);
+            s->h_box.push_back(box);
             s->h_prims.push_back(uint32_t(p));
             nprim++;
             Lmax = std::max(Lmax, lip[p]);
+        } else if (is_compact_kind(nd.kind)) {
+            double kk = nd.p[0], dd = nd.p[1] > 0 ? nd.p[1] : 7.0 * kk / 6.0;
+            q[0] = float(kk);
+            q[1] = float(1.0 / kk);
+            q[2] = float(6.0 * kk / (6.0 * dd - kk));
+            q[3] = float(dd);
+            q[4] = float(1.0 + kk / (6.0 * dd - kk));
+            q[5] = float(kk / 6.0);
+        } else {
+            q[4] = 1.f;
         }
     }
     s->n_prims = nprim;
     s->lipschitz = float(Lmax);
-    double e = 0;
-    for (int j = 0; j < 3; j++) {
-        e = std::max(e, ext_hi[j] - ext_lo[j]);
-        s->voi_lo[j] = float(voi_lo[j]);
-        s->voi_hi[j] = float(voi_hi[j]);
-    }
-    s->extent = float(e);
+    scene_bounds(s);
 
     // sparse table over post-order positions of (depth << 24 | parent)
     int levels = 1;

@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const float* __restrict__
     if (s < n) {
         const float inv_n = 1.0f / float(n);
         float xi[8];
-        for (int k = 0; k < 8; k++) xi[k] = round_half((x[8 * size_t(s) + k] - norm[k]) * norm[8 + k]);
+        for (int k = 0; k < 8; k++) xi[k] = round_half(mlp_feature(x[8 * size_t(s) + k], norm[k], norm[8 + k]));
         float a1[32], h1[32], a2[32], h2[32];
         for (int j = 0; j < 32; j++) {
             float acc = W[kMlpB1 + j];

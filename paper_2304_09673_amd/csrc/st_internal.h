@@ -8,6 +8,11 @@
 #include "st_common.h"
 #include "st_prune.h"
 
+// axis-aligned boxes of a primitive (support) and of its volume of interest
+struct PrimBox {
+    double lo[3], hi[3], vlo[3], vhi[3];
+};
+
 struct st_scene {
     // tree, post-order numbering
     int32_t n_nodes = 0, n_prims = 0, depth = 0, rmq_levels = 0;
@@ -16,6 +21,7 @@ struct st_scene {
     std::vector<uint32_t> h_blob, h_kill, h_rmq, h_prims;
     std::vector<st::NodePar> h_par;
     std::vector<float> h_roi;
+    std::vector<PrimBox> h_box;   // per primitive, in h_prims order
     float extent = 0.f, lipschitz = 1.f;
     float voi_lo[3] = {0, 0, 0}, voi_hi[3] = {0, 0, 0};
 
@@ -101,6 +107,11 @@ st_status debug_eval_device(const st_scene* s, const uint32_t* active_post, int 
 
 // flatten.cpp (host)
 st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* s);
+st_status validate_primitive(const st_node& nd, int i);
+// device parameter block and bounds of a primitive with range of interest d
+void primitive_params(const st_node& nd, double d, NodePar& par, PrimBox& box);
+// scene extent and volume-of-interest box from the primitives' boxes
+void scene_bounds(st_scene* s);
 PruneResult host_prune(const st_scene* s, std::vector<uint32_t> active_post,
                        std::vector<uint32_t>& view);
 

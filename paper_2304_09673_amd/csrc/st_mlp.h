@@ -24,6 +24,7 @@ namespace st {
 constexpr int kMlpParams = 1377;
 constexpr int kMlpW1 = 0, kMlpB1 = 256, kMlpW2 = 288, kMlpB2 = 1312, kMlpW3 = 1344, kMlpB3 = 1376;
 constexpr float kOmegaMax = 4.0f;
+constexpr float kFeatClamp = 8.0f;   // standardised features are clamped to [-8, 8]
 
 // Per-lane operand table, one column per lane (entry k of lane l at k*64+l):
 //  [0,1]   W1 A operand: halves W1[h][4g..4g+3]          (h = l % 32, g = l / 32)
@@ -58,49 +59,52 @@ __device__ __forceinline__ float round_half(float x) { return float((_Float16)x)
 // instructions and cross-lane shuffles).
 __device__ __forceinline__ float tabf(const uint32_t* tab, int k) { return __uint_as_float(tab[k]); }
 
+// standardised feature, clamped so that an input far outside the training
+// range stays finite in binary16
+__device__ __forceinline__ float mlp_feature(float x, float mean, float inv_std) {
+    return fminf(fmaxf((x - mean) * inv_std, -kFeatClamp), kFeatClamp);
+}
+
 __device__ __forceinline__ float mlp_omega(const uint32_t* tab, const float x[8]) {
     const int l = int(threadIdx.x & 63u), g = l >> 5;
     const uint32_t* nrm = tab + kMlpTabRows * 64;
     float xn[8];
 #pragma unroll
-    for (int i = 0; i < 8; i++) xn[i] = (x[i] - tabf(nrm, i)) * tabf(nrm, 8 + i);
+    for (int i = 0; i < 8; i++) xn[i] = mlp_feature(x[i], tabf(nrm, i), tabf(nrm, 8 + i));
     uint32_t lo0 = pack_h2(xn[0], xn[1]), lo1 = pack_h2(xn[2], xn[3]);
     uint32_t hi0 = pack_h2(xn[4], xn[5]), hi1 = pack_h2(xn[6], xn[7]);
     uint32_t slo0 = __shfl_xor(lo0, 32), slo1 = __shfl_xor(lo1, 32);
     uint32_t shi0 = __shfl_xor(hi0, 32), shi1 = __shfl_xor(hi1, 32);
     // B operands: block 0 = rays 0..31, block 1 = rays 32..63; lane l holds
     // features 4g..4g+3 of ray 32b + l%32
-    h4_t B0 = g == 0 ? h4_from(lo0, lo1) : h4_from(shi0, shi1);
-    h4_t B1 = g == 0 ? h4_from(slo0, slo1) : h4_from(hi0, hi1);
-    h4_t A1 = h4_from(tab[0 * 64 + l], tab[1 * 64 + l]);
-    f16_t c;
+    const h4_t B0 = g == 0 ? h4_from(lo0, lo1) : h4_from(shi0, shi1);
+    const h4_t B1 = g == 0 ? h4_from(slo0, slo1) : h4_from(hi0, hi1);
+    float z = 0.f;
+    // the two blocks one after the other: 32 accumulators live, not 64
+#pragma unroll 1
+    for (int blk = 0; blk < 2; blk++) {
+        const h4_t B = blk == 0 ? B0 : B1;
+        f16_t c;
 #pragma unroll
-    for (int a = 0; a < 16; a++) c[a] = tabf(tab, (10 + a) * 64 + l);
-    f16_t d0 = __builtin_amdgcn_mfma_f32_32x32x8f16(A1, B0, c, 0, 0, 0);
-    f16_t d1 = __builtin_amdgcn_mfma_f32_32x32x8f16(A1, B1, c, 0, 0, 0);
+        for (int a = 0; a < 16; a++) c[a] = tabf(tab, (10 + a) * 64 + l);
+        const f16_t d = __builtin_amdgcn_mfma_f32_32x32x8f16(h4_from(tab[l], tab[64 + l]), B, c, 0, 0, 0);
+        f16_t e;
 #pragma unroll
-    for (int a = 0; a < 16; a++) c[a] = tabf(tab, (26 + a) * 64 + l);
-    f16_t e0 = c, e1 = c;
+        for (int a = 0; a < 16; a++) e[a] = tabf(tab, (26 + a) * 64 + l);
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        h4_t A2 = h4_from(tab[(2 + 2 * q) * 64 + l], tab[(3 + 2 * q) * 64 + l]);
-        h4_t b0 = h4_from(pack_h2(fmaxf(d0[4 * q], 0.f), fmaxf(d0[4 * q + 1], 0.f)),
-                          pack_h2(fmaxf(d0[4 * q + 2], 0.f), fmaxf(d0[4 * q + 3], 0.f)));
-        h4_t b1 = h4_from(pack_h2(fmaxf(d1[4 * q], 0.f), fmaxf(d1[4 * q + 1], 0.f)),
-                          pack_h2(fmaxf(d1[4 * q + 2], 0.f), fmaxf(d1[4 * q + 3], 0.f)));
-        e0 = __builtin_amdgcn_mfma_f32_32x32x8f16(A2, b0, e0, 0, 0, 0);
-        e1 = __builtin_amdgcn_mfma_f32_32x32x8f16(A2, b1, e1, 0, 0, 0);
+        for (int q = 0; q < 4; q++) {
+            const h4_t A2 = h4_from(tab[(2 + 2 * q) * 64 + l], tab[(3 + 2 * q) * 64 + l]);
+            const h4_t b = h4_from(pack_h2(fmaxf(d[4 * q], 0.f), fmaxf(d[4 * q + 1], 0.f)),
+                                   pack_h2(fmaxf(d[4 * q + 2], 0.f), fmaxf(d[4 * q + 3], 0.f)));
+            e = __builtin_amdgcn_mfma_f32_32x32x8f16(A2, b, e, 0, 0, 0);
+        }
+        float p = 0.f;
+#pragma unroll
+        for (int a = 0; a < 16; a++) p = fmaf(tabf(tab, (42 + a) * 64 + l), round_half(fmaxf(e[a], 0.f)), p);
+        p += __shfl_xor(p, 32);
+        if (g == blk) z = p;
     }
-    float p0 = 0.f, p1 = 0.f;
-#pragma unroll
-    for (int a = 0; a < 16; a++) {
-        float w = tabf(tab, (42 + a) * 64 + l);
-        p0 = fmaf(w, round_half(fmaxf(e0[a], 0.f)), p0);
-        p1 = fmaf(w, round_half(fmaxf(e1[a], 0.f)), p1);
-    }
-    p0 += __shfl_xor(p0, 32);
-    p1 += __shfl_xor(p1, 32);
-    float z = (l < 32 ? p0 : p1) + tabf(tab, 58 * 64 + l);
+    z += tabf(tab, 58 * 64 + l);
     return 1.0f + (kOmegaMax - 1.0f) / (1.0f + __expf(-z));
 }
 

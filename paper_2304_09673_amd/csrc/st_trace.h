@@ -582,7 +582,10 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                     if (ballot(need) != 0) {
                         float f[8];
                         step_features(f, v, invL, t, tp, vp, tp_ok, steps, n, len);
-                        if constexpr (SM == SM_LEARNED) om = mlp_omega(tab, f);
+                        if constexpr (SM == SM_LEARNED) {
+                            om = mlp_omega(tab, f);
+                            if (!(om >= 1.0f)) om = 1.0f;   // never below the plain step
+                        }
                         else dump_samples<KS>(A, S.view(), len, ray, t, v, invL, t1, need, f);
                     }
                 }

@@ -41,13 +41,9 @@ template <int KS, int SM, bool InLds>
 __global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A, uint32_t* slots, int ma) {
     extern __shared__ uint32_t dyn_slot[];
     WaveGlob S{InLds ? dyn_slot : slots + size_t(blockIdx.x) * 9u * uint32_t(ma), ma};
-    const uint32_t* tab = nullptr;
-    if constexpr (SM == SM_LEARNED) {
-        __shared__ uint32_t mlp_tab[kMlpTabWords];
-        for (int i = int(threadIdx.x); i < kMlpTabWords; i += int(blockDim.x)) mlp_tab[i] = A.mlp[i];
-        __syncthreads();
-        tab = mlp_tab;
-    }
+    // the step-model table is read through the caches here: one wave per
+    // workgroup, and LDS is what limits the number of resident waves
+    const uint32_t* tab = SM == SM_LEARNED ? A.mlp : nullptr;
     uint32_t n_wide = A.wide[0];
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     for (uint32_t job = blockIdx.x; job < n_wide * spt; job += gridDim.x) {

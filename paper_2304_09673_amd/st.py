@@ -24,7 +24,7 @@ EXPORTS = (
     "st_debug_prune_tree",
     "st_debug_abuffer", "st_mlp_pack", "st_mlp_forward", "st_mlp_grad", "st_mlp_adam", "st_set_step_model",
     "st_trace_dump", "st_debug_mfma_probe", "st_batch_create", "st_batch_render", "st_batch_stats",
-    "st_batch_destroy", "st_batch_autotune", "st_trace_batch",
+    "st_batch_destroy", "st_batch_autotune", "st_trace_batch", "st_update_primitives",
 )
 
 MLP_PARAMS = 1377
@@ -123,6 +123,7 @@ def lib():
         L.st_batch_destroy.argtypes = [vp]
         L.st_batch_autotune.argtypes = [C.POINTER(vp), C.POINTER(StCamera), i32, C.POINTER(StTuning), C.POINTER(vp),
                                         C.POINTER(vp), i32, C.POINTER(StTuning), C.POINTER(C.c_float), vp]
+        L.st_update_primitives.argtypes = [vp, vp, C.POINTER(StNode), i32, vp]
         L.st_trace_batch.argtypes = [C.POINTER(vp), C.POINTER(StCamera), i32, C.POINTER(vp), C.POINTER(vp),
                                      C.POINTER(StStats), vp]
         for name in EXPORTS:
@@ -266,6 +267,13 @@ class Scene:
                                          view.ctypes.data_as(C.c_void_p), view.shape[0], C.byref(vlen),
                                          _stream_ptr(stream)))
         return f, g, int(used.value), view[: vlen.value].copy()
+
+    def update_primitives(self, ids, kind, params, stream=None):
+        """st_update_primitives: ids (caller node indices), kind[n], params [n, 16]."""
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        n = ids.shape[0]
+        nodes = nodes_from_arrays(kind, [-1] * n, [-1] * n, params)
+        _check(lib().st_update_primitives(self._h, ids.ctypes.data_as(C.c_void_p), nodes, n, _stream_ptr(stream)))
 
     def set_step_model(self, weights, norm, stream=None):
         """st_set_step_model: weights float32 CUDA [1377], norm float32 CUDA [16]."""

@@ -224,3 +224,31 @@ def test_prune_intersection_with_lone_operand_is_unused():
     a, b = sc.left[sc.root], sc.right[sc.root]
     assert list(_prune(sc, [a])[0]) == [a]
     assert len(_prune(sc, [b])[0]) == 0
+
+
+def test_golden_single_operator_views():
+    """The per-operator behaviour the paper tabulates (ignoreMod codes and the
+    reserved op types), for sharp and compact smooth operators of each class."""
+    from pathlib import Path
+    rows = []
+    for line in (Path(__file__).parent / "golden" / "ignoremod_single_operator.txt").read_text().splitlines():
+        if line.strip() and not line.startswith("#"):
+            parts = line.split()
+            rows.append((parts[0], parts[1], parts[2:]))
+    assert len(rows) == 12
+    kinds = {"union": (sg.UNION, sg.SUNION), "intersection": (sg.INTER, sg.SINTER),
+             "difference": (sg.DIFF, sg.SDIFF)}
+    for cls, active, expect in rows:
+        for k in kinds[cls]:
+            kind = np.array([sg.SPHERE, sg.SPHERE, k], dtype=np.int32)
+            left = np.array([-1, -1, 0], dtype=np.int32)
+            right = np.array([-1, -1, 1], dtype=np.int32)
+            params = np.zeros((3, 16), dtype=np.float32)
+            params[0, :4] = [-0.2, 0, 0, 0.5]
+            params[1, :4] = [0.2, 0, 0, 0.5]
+            params[2, :2] = [0.1, 0.0]
+            act = [] if active == "-" else [{"A": 0, "B": 1}[c] for c in active]
+            view, _ = st.prune_tree(kind, left, right, params, 2, act)
+            names = {0: "A", 1: "B", 2: "op"}
+            got = [names[int(v)] for v in view] or ["-"]
+            assert got == expect, (cls, k, active, got, expect)

@@ -30,7 +30,7 @@ def _random_problem(seed, n, target_spread=True):
     x = rng.normal(0, 1, (n, 8)).astype(np.float32) * np.array([0.1, 1, 0.01, 3, 0.5, 2, 1.5, 2], np.float32) \
         + np.array([0.05, 0.9, 0.01, 4, -0.3, 3, 3.0, 2], np.float32)
     mu = x.mean(axis=0)
-    inv = 1.0 / x.std(axis=0)
+    inv = 1.0 / np.maximum(x.std(axis=0), 1e-3)
     norm = np.concatenate([mu, inv]).astype(np.float32)
     t = rng.uniform(1.0, 4.0, n).astype(np.float32) if target_spread else np.full(n, 2.0, np.float32)
     return w, norm, x, t
@@ -38,8 +38,8 @@ def _random_problem(seed, n, target_spread=True):
 
 def _oracle_inputs(w, norm, x):
     """The device's inputs to the arithmetic: binary16 weights and standardised
-    features computed in FP32, then rounded to binary16."""
-    xs = ((x - norm[:8]) * norm[8:]).astype(np.float32)
+    features computed in FP32, clamped to [-8, 8], then rounded to binary16."""
+    xs = np.clip(((x - norm[:8]) * norm[8:]).astype(np.float32), -8.0, 8.0)
     return oracle.round_half(w.astype(np.float64)), oracle.round_half(xs.astype(np.float64))
 
 
@@ -125,6 +125,23 @@ def test_adam_update():
         vr = b2 * vr + (1 - b2) * g.astype(np.float64) ** 2
         wr = wr - lr * (mr / (1 - b1 ** k)) / (np.sqrt(vr / (1 - b2 ** k)) + eps)
     np.testing.assert_allclose(w.cpu().numpy(), wr, rtol=0, atol=1e-5)
+
+
+def test_forward_clamps_outlying_features():
+    """Features far outside the standardisation range give a finite omega in
+    [1, 4] equal to that of the clamped features."""
+    import torch
+    st = _st()
+    w, norm, x, t = _random_problem(77, 256)
+    x_far = x.copy()
+    x_far[::2, 3] = 1e30
+    x_far[1::2, 6] = -1e30
+    tab = st.mlp_pack(torch.as_tensor(w).cuda(), torch.as_tensor(norm).cuda())
+    om = st.mlp_forward(tab, torch.as_tensor(x_far).cuda()).cpu().numpy().astype(np.float64)
+    assert np.isfinite(om).all() and np.all((om >= 1.0) & (om <= 4.0))
+    wr, xr = _oracle_inputs(w, norm, x_far)
+    _, om_ref, _ = oracle.mlp(wr, xr, t.astype(np.float64), grad=False)
+    assert _rel_l2(om, om_ref) <= 1e-3
 
 
 def test_training_reduces_loss():
