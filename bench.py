@@ -156,6 +156,75 @@ def bench_batch(args):
     b.close()
 
 
+def progress(msg: str):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def learned_vs_plain(args):
+    """16384 primitives of the second workload's laws at 3840x2160: plain,
+    over-relaxed (factor 1.7) and learned step, same tuning.  The step model is
+    trained first (outside the timed region) on dumps of the plain tracer over
+    the first two workloads.  Hit masks must agree; depth differences between
+    the learned and the plain image are reported (the oracle comparison is in
+    the tests)."""
+    import torch
+    import scenegen as sg
+    from paper_2304_09673_amd import st, stepmodel
+
+    t0 = time.perf_counter()
+    train = [sg.config1(seed=s_, width=256, height=256) for s_ in range(10)] + \
+            [sg.config2(seed=s_, width=512, height=512) for s_ in range(5)]
+    progress("learned step: collecting training samples")
+    X, T = stepmodel.collect(train, cap_per_scene=1 << 20)
+    progress(f"learned step: training on {X.shape[0]} samples")
+    w, norm, losses = stepmodel.fit(X, T, epochs=10, batch=8192, lr=3e-3, seed=0)
+    train_s = time.perf_counter() - t0
+    sc = sg.config5()
+    cam = sc.camera
+    kw = {"tile": 16, "max_new": 64, "sub_depth": 0.25}
+    out = {}
+    imgs = {}
+    for name, mode in (("plain", st.ST_STEP_PLAIN), ("overrelax", st.ST_STEP_OVERRELAX),
+                       ("learned", st.ST_STEP_LEARNED)):
+        progress(f"learned step: {name} at {cam.width}x{cam.height}")
+        s = st.Scene(sc)
+        if mode == st.ST_STEP_LEARNED:
+            s.set_step_model(w, norm)
+        tune = st.default_tuning(step_mode=mode, **kw)
+        s.build_abuffer(cam, tune)
+        _, _, stats = s.trace()
+        ts = []
+        for _ in range(args.c5_reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            d, n, _ = s.trace(stats=False)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        ms = float(np.median(ts))
+        rays = cam.width * cam.height
+        imgs[name] = d.cpu().numpy()
+        out[name] = {"trace_ms": round(ms, 2), "mrays_s": round(rays / ms / 1e3, 3),
+                     "field_evals_per_s": stats["field_evals"] / (ms * 1e-3),
+                     "steps_per_ray": stats["steps"] / rays, "evals_per_ray": stats["field_evals"] / rays,
+                     "relaxed_accepted": stats["learned_accepted"], "relaxed_rejected": stats["learned_rejected"],
+                     "unconverged": stats["unconverged"], "hits": stats["hits"]}
+        ext = s.info()["extent"]
+        s.close()
+    hit = np.isfinite(imgs["plain"])
+    for name in ("overrelax", "learned"):
+        same = bool((np.isfinite(imgs[name]) == hit).all())
+        dd = np.abs(imgs[name][hit].astype(np.float64) - imgs["plain"][hit]) / ext if hit.any() else np.zeros(1)
+        out[name]["mask_equal_to_plain"] = same
+        out[name]["depth_diff_vs_plain_rel"] = {"p99": float(np.percentile(dd, 99)), "max": float(dd.max())}
+        out[name]["speedup_vs_plain"] = round(out["plain"]["trace_ms"] / out[name]["trace_ms"], 4)
+    return {"workload": f"{sc.name}: 16384 primitives, depth<=24, {cam.width}x{cam.height}, tile 16, max_new 64, "
+                        f"sub_depth 1/4; median of {args.c5_reps} traces",
+            "train": {"samples": int(X.shape[0]), "epochs": 10, "final_loss": losses[-1], "seconds": round(train_s, 1)},
+            **out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +240,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--n-scenes", type=int, default=64)
+    ap.add_argument("--no-c5", action="store_true", help="skip the learned-vs-plain comparison")
+    ap.add_argument("--c5-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design (screen tiles sharded "
@@ -279,7 +350,21 @@ def main():
                      "frac": achieved / PEAK_FP32, "frac_nonpacked": achieved / PEAK_FP32_NONPACKED,
                      "flops_per_launch": flops, "traffic": measured_traffic()},
     }
+    # binning (HBM-bound by design): algorithmic bytes = VOI reads (2 passes,
+    # 48 B/primitive each), tile count/scan/offsets (12 B/tile), scatter write
+    # (12 B/entry), per-tile sort read + write (24 B/entry)
+    n_tiles = -(-cam.width // tune.tile) * -(-cam.height // tune.tile)
+    e = stats["abuffer_entries"]
+    bin_bytes = 96 * sc.n_prims + 12 * n_tiles + 36 * e
+    line["binning"] = {"bound": "hbm", "algorithmic_bytes": bin_bytes, "ms_wall": round(build_ms, 4),
+                       "achieved_GBps": bin_bytes / (build_ms * 1e-3) / 1e9,
+                       "frac": bin_bytes / (build_ms * 1e-3) / 8e12,
+                       "note": "wall time of st_build_abuffer (includes its two host synchronizations)"}
+    progress(f"frame: {value:.1f} Mrays/s")
+    if not args.no_c5:
+        line["learned_vs_plain"] = learned_vs_plain(args)
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_rays)
     print(json.dumps(line), flush=True)
 

@@ -222,6 +222,14 @@ st_status st_batch_create(st_scene* const* scenes, const st_camera* cams, int32_
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 9 * kMaLds * 4);
     }
     if (e != hipSuccess) { batch_free(b); return device_error(e, "batch: upload"); }
+    // one direct frame first: every kernel of the frame is launched (and its
+    // code object loaded) outside stream capture, and the frame is checked
+    st_status r0 = enqueue_frame(b, stream);
+    if (r0 == ST_OK) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) r0 = device_error(e, "batch: first frame");
+    }
+    if (r0 != ST_OK) { batch_free(b); return r0; }
     // capture one frame into a graph on a stream of the batch's own
     e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);

@@ -11,6 +11,10 @@ import scenegen as sg
 pytestmark = pytest.mark.gpu
 
 
+def _log(*a):
+    print(*a, flush=True)
+
+
 def _scenes(idx, shrink):
     out = []
     for i in idx:
@@ -36,11 +40,15 @@ def test_batch_equals_standalone(tile):
     import torch
     from paper_2304_09673_amd import st
     scs = _scenes(range(6), 4)
+    _log("scenes", [(sc.n_prims, sc.camera.width, sc.camera.height) for sc in scs])
     tune = st.default_tuning(tile=tile, max_new=16)
     ref = [_standalone(sc, tune) for sc in scs]
+    _log("standalone done")
     handles = [st.Scene(sc) for sc in scs]
     b = st.Batch(handles, [sc.camera for sc in scs], tuning=tune)
+    _log("batch created")
     for use_graph in (False, True, True, True):
+        _log("render graph", use_graph)
         for d in b.depths:
             d.fill_(-1.0)
         # eager work between replays

@@ -108,7 +108,7 @@ def test_learned_parity(model, which, seed):
     r = compare(sc, d_l, n_l, px, py)
     assert r["fail"] == 0, r
     np.testing.assert_array_equal(np.isfinite(d_l), np.isfinite(d_p))
-    assert s_l["learned_accepted"] > 0
+    assert s_l["learned_accepted"] > 0, (s_l, s_p)
     assert s_l["unconverged"] == 0
     # fewer stepping evaluations than plain
     assert s_l["steps"] < s_p["steps"], (s_l["steps"], s_p["steps"])
@@ -177,3 +177,27 @@ def test_learned_vs_plain_on_large_scene(model):
               f"steps {stats['steps']}, evals {stats['field_evals']}, accepted {stats['learned_accepted']}, "
               f"rejected {stats['learned_rejected']}")
     print("depth error (max rel):", errs)
+
+
+def test_full_size_large_scene_sampled(model):
+    """The full 3840x2160 frame of 16384 primitives in the launch
+    configuration of the comparison: plain and learned agree on every hit/miss
+    and match the oracle on sampled pixels (hit pixels and random ones)."""
+    st = _st()
+    sc = sg.config5()
+    kw = {"tile": 16, "max_new": 64, "sub_depth": 0.25}
+    d_p, n_p, s_p = _render(sc, st.ST_STEP_PLAIN, tuning_kw=kw)
+    d_l, n_l, s_l = _render(sc, st.ST_STEP_LEARNED, model=model, tuning_kw=kw)
+    assert s_p["unconverged"] == 0 and s_l["unconverged"] == 0
+    assert s_p["stalled"] == 0 and s_l["stalled"] == 0
+    np.testing.assert_array_equal(np.isfinite(d_l), np.isfinite(d_p))
+    jj, ii = np.nonzero(np.isfinite(d_p))
+    rng = np.random.default_rng(11)
+    pick = rng.permutation(jj.shape[0])[:48]
+    rx, ry = sample_pixels(sc.camera, 32, 12)
+    px = np.concatenate([ii[pick], rx])
+    py = np.concatenate([jj[pick], ry])
+    osc = oracle.OracleScene(sc)
+    for name, d, n in (("plain", d_p, n_p), ("learned", d_l, n_l)):
+        r = compare(sc, d, n, px, py, osc=osc)
+        assert r["fail"] == 0, (name, r)
