@@ -91,7 +91,9 @@ typedef struct {
                               run on a wider-capacity path, never fail */
     float sub_depth;       /* fetch-ahead depth d as a fraction of the scene's
                               view-depth span (paper: 1/20) */
-    int32_t max_new;       /* new primitives fetched per subfrustum (paper: 6) */
+    int32_t max_new;       /* new primitives fetched per subfrustum, >= 1 (values
+                              above 4096 act as 4096)
+                              (paper: 6) */
     float eps;             /* minimum step and probing step, scene units */
     int32_t max_steps;     /* field evaluations per ray for stepping */
     int32_t refine_iters;  /* bracket refinement iterations after a crossing */
@@ -244,7 +246,7 @@ st_status st_trace_ex(st_scene *s, const st_camera *cam, float *out_depth, float
 /*
  * st_autotune -- picks, for this scene and camera, the tuning with the
  * shortest A-buffer build + trace time among a grid of A-buffer tile sizes
- * {8, 16, 32}, fetch caps max_new {6, 16, 64} (the paper's 6 first) and
+ * {8, 16, 32}, fetch caps max_new {6, 16, 64, 256} (the paper's 6 first) and
  * fetch-ahead depths sub_depth {1/20, 1/4} (the paper's 1/20 first).  Every
  * candidate is timed on the device with HIP events (median of `reps` runs,
  * reps >= 1) into temporary output buffers; the A-buffer is left built with
@@ -352,7 +354,7 @@ st_status st_batch_stats(const st_batch *b, st_stats *out, int32_t cap, void *st
 void st_batch_destroy(st_batch *b);
 
 /* Picks the batch tuning with the shortest graph frame among the grid of
- * st_autotune (tile {8,16,32}, max_new {6,16,64}, sub_depth {1/20, 1/4}),
+ * st_autotune (tile {8,16,32}, max_new {6,16,64,256}, sub_depth {1/20, 1/4}),
  * timing `reps` replays of each candidate with HIP events (median).  Renders
  * into depths/normals; leaves the scenes' A-buffers built with the last
  * candidate.  Synchronous.  Errors: those of st_batch_create/render. */

@@ -185,6 +185,7 @@ st_status st_flatten_blobtree(const st_node* nodes, int32_t n, int32_t root, con
     struct { void** p; size_t bytes; const void* src; } bufs[] = {
         {(void**)&s->d_blob, N * 4, s->h_blob.data()},
         {(void**)&s->d_kill, N * 4, s->h_kill.data()},
+        {(void**)&s->d_range, N * 8, s->h_range.data()},
         {(void**)&s->d_rmq, s->h_rmq.size() * 4, s->h_rmq.data()},
         {(void**)&s->d_prims, P * 4, s->h_prims.data()},
         {(void**)&s->d_par, N * sizeof(NodePar), s->h_par.data()},
@@ -216,6 +217,7 @@ void st_scene_destroy(st_scene* s) {
     free_abuffer(s, stream);
     dev_free(s, s->d_blob, stream);
     dev_free(s, s->d_kill, stream);
+    dev_free(s, s->d_range, stream);
     dev_free(s, s->d_rmq, stream);
     dev_free(s, s->d_prims, stream);
     dev_free(s, s->d_par, stream);
@@ -399,13 +401,13 @@ st_status st_autotune(st_scene* s, const st_camera* cam, const st_tuning* base, 
     if (he == hipSuccess) he = hipEventCreate(&e1);
     if (he != hipSuccess) { dev_free(s, buf, stream); return device_error(he, "autotune events"); }
     const int tiles[3] = {8, 16, 32};
-    const int news[3] = {6, 16, 64};
+    const int news[4] = {6, 16, 64, 256};
     const float subs[2] = {1.0f / 20.0f, 0.25f};
     float best = INFINITY;
     st_tuning best_t = b;
     st_status r = ST_OK;
     for (int ti = 0; ti < 3 && r == ST_OK; ti++)
-        for (int ni = 0; ni < 3 && r == ST_OK; ni++)
+        for (int ni = 0; ni < 4 && r == ST_OK; ni++)
             for (int si = 0; si < 2 && r == ST_OK; si++) {
                 st_tuning t = b;
                 t.tile = tiles[ti];

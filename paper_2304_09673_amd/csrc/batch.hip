@@ -15,6 +15,21 @@
 
 namespace st {
 
+// Batched rendering is switched off: its creation (first builds, one direct
+// frame, graph capture) did not return on the device, and the cause has not
+// been found.  Every entry point refuses with ST_E_INVALID until it is.
+constexpr bool kBatchEnabled = false;
+
+// Next job index of the wave from the global queue.  Every lane takes part
+// in the atomic (lane 0 adds 1, the others 0) and the index is lane 0's
+// return value, so the fetch has no lane-dependent branch: a persistent loop
+// whose job index is produced under a lane-0-only branch was compiled into a
+// loop that can re-enter its body with the index register reset to 0.
+__device__ __forceinline__ uint32_t next_job(uint32_t* head) {
+    const uint32_t r = atomicAdd(head, lane_id() == 0 ? 1u : 0u);
+    return rdlane(r, 0);
+}
+
 // job: x = scene index, y = tile << 8 | block within the tile
 template <int KS>
 __global__ void __launch_bounds__(256) batch_fast_kernel(const TraceArgs* __restrict__ args,
@@ -22,10 +37,10 @@ __global__ void __launch_bounds__(256) batch_fast_kernel(const TraceArgs* __rest
                                                          uint32_t* __restrict__ head) {
     __shared__ WaveLds<kMaFast> lds[4];
     const int w = threadIdx.x >> 6;
-    for (;;) {
-        uint32_t j = 0;
-        if (lane_id() == 0) j = atomicAdd(head, 1u);
-        j = rdlane(j, 0);
+    // a wave takes at most n_jobs jobs, so the loop ends even if the queue
+    // were corrupted
+    for (uint32_t it = 0; it < n_jobs; it++) {
+        const uint32_t j = next_job(head);
         if (j >= n_jobs) break;
         const uint2 jb = jobs[j];
         const TraceArgs& A = args[jb.x];
@@ -39,10 +54,8 @@ __global__ void __launch_bounds__(64) batch_wide_kernel(const TraceArgs* __restr
                                                         uint32_t* __restrict__ head, uint32_t* slots, int ma) {
     extern __shared__ uint32_t dyn_slot[];
     WaveGlob S{InLds ? dyn_slot : slots + size_t(blockIdx.x) * 9u * uint32_t(ma), ma};
-    for (;;) {
-        uint32_t j = 0;
-        if (lane_id() == 0) j = atomicAdd(head, 1u);
-        j = rdlane(j, 0);
+    for (uint32_t it = 0; it < n_jobs; it++) {
+        const uint32_t j = next_job(head);
         if (j >= n_jobs) break;
         const uint2 jb = jobs[j];
         const TraceArgs& A = args[jb.x];
@@ -143,6 +156,11 @@ st_status st_batch_create(st_scene* const* scenes, const st_camera* cams, int32_
         return ST_E_INVALID;
     }
     *out = nullptr;
+    if (!kBatchEnabled) {
+        set_error("batch: disabled (a batch creation did not return on the device and its cause is not "
+                  "identified); render the scenes one by one with st_trace");
+        return ST_E_INVALID;
+    }
     hipStream_t stream = (hipStream_t)stream_v;
     st_tuning t;
     if (tuning) t = *tuning; else st_default_tuning(&t);
@@ -292,13 +310,13 @@ st_status st_batch_autotune(st_scene* const* scenes, const st_camera* cams, int3
     if (he == hipSuccess) he = hipEventCreate(&e1);
     if (he != hipSuccess) return device_error(he, "batch autotune events");
     const int tiles[3] = {8, 16, 32};
-    const int news[3] = {6, 16, 64};
+    const int news[4] = {6, 16, 64, 256};
     const float subs[2] = {1.0f / 20.0f, 0.25f};
     float best = INFINITY;
     st_tuning best_t = b0;
     st_status r = ST_OK;
     for (int ti = 0; ti < 3 && r == ST_OK; ti++)
-        for (int ni = 0; ni < 3 && r == ST_OK; ni++)
+        for (int ni = 0; ni < 4 && r == ST_OK; ni++)
             for (int si = 0; si < 2 && r == ST_OK; si++) {
                 st_tuning t = b0;
                 t.tile = tiles[ti];

@@ -201,6 +201,19 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
     }
     s->h_blob.assign(n, 0);
     s->h_kill.assign(n, kNoKill);
+    // subtree ranges: a subtree is the post-order range [first, node]; an
+    // operator's right subtree starts at split = (left child) + 1
+    s->h_range.assign(size_t(2) * n, 0u);
+    for (int p = 0; p < n; p++) {
+        const st_node& nd = nodes[order[p]];
+        if (is_prim_kind(nd.kind)) {
+            s->h_range[2 * size_t(p)] = uint32_t(p);
+        } else {
+            uint32_t lp = uint32_t(s->post_of_caller[nd.left]);
+            s->h_range[2 * size_t(p)] = s->h_range[2 * size_t(lp)];
+            s->h_range[2 * size_t(p) + 1] = lp + 1u;
+        }
+    }
     s->h_par.assign(n, NodePar{});
     s->h_roi.assign(n, 0.f);
     s->h_prims.clear();

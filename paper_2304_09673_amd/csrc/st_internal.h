@@ -19,6 +19,7 @@ struct st_scene {
     std::vector<int32_t> post_of_caller;   // caller index -> post-order index
     std::vector<int32_t> caller_of_post;   // post-order index -> caller index
     std::vector<uint32_t> h_blob, h_kill, h_rmq, h_prims;
+    std::vector<uint32_t> h_range;   // per node: first node of the subtree, start of the right subtree
     std::vector<st::NodePar> h_par;
     std::vector<float> h_roi;
     std::vector<PrimBox> h_box;   // per primitive, in h_prims order
@@ -28,6 +29,7 @@ struct st_scene {
     // device copies
     uint32_t* d_blob = nullptr;
     uint32_t* d_kill = nullptr;
+    uint32_t* d_range = nullptr;     // 2 words per node
     uint32_t* d_rmq = nullptr;
     uint32_t* d_prims = nullptr;     // post-order index of each primitive
     st::NodePar* d_par = nullptr;

@@ -83,6 +83,7 @@ struct TraceArgs {
     const uint32_t* blob;
     const NodePar* par;
     const uint32_t* kill;
+    const uint2* range;        // per node: first node of the subtree, start of the right subtree
     const uint32_t* rmq;
     uint32_t n_nodes;
     const uint32_t* tile_off;
@@ -286,14 +287,93 @@ __device__ __forceinline__ int lower_count(const uint32_t* a, int n, uint32_t x)
 }
 
 // Builds the pruned view of the active set S.act(buf)[0..n) into S.view().
+// Drops active primitives that cannot reach the root: a primitive whose
+// nearest killing ancestor K (an intersection, or a difference reached from
+// its right operand) has no active primitive in K's other operand is
+// discarded at K; so is every other active primitive below K (they are all on
+// the same side), and K is unused.  Removing it leaves the pruned view
+// unchanged and shrinks the work of the view build.  act[0..n) sorted;
+// survivors written in order to out; returns their count.
+template <class Mem>
+__device__ int drop_dead(const TraceArgs& A, const uint32_t* act, int n, uint32_t* out) {
+    const int lane = lane_id();
+    int kept = 0;
+    wave_sync();
+    for (int b = 0; b < n; b += 64) {
+        const int s = b + lane;
+        const bool in = s < n;
+        const uint32_t x = in ? act[s] : 0u;
+        bool keep = in;
+        if (in) {
+            const uint32_t K = A.kill[min(x, A.n_nodes - 1u)];
+            if (K < A.n_nodes) {
+                const uint2 r = A.range[K];
+                // K's other operand: [split, K) when x is on the left, else [first, split)
+                const uint32_t lo = x < r.y ? r.y : r.x;
+                const uint32_t hi = x < r.y ? K : r.y;
+                keep = lower_count(act, n, hi) > lower_count(act, n, lo);
+            }
+        }
+        const uint64_t mk = ballot(keep);
+        if (keep) out[kept + int(lanes_below(mk))] = x;
+        kept += __popcll(mk);
+    }
+    wave_sync();
+    return kept;
+}
+
 template <class Mem>
 __device__ PruneResult build_view(const TraceArgs& A, Mem& S, int buf, int n) {
     const uint32_t* act = S.act(buf);
     const int lane = lane_id();
     int m;
+    if (n >= 2) {
+        // two rounds: the second catches primitives whose only partners were
+        // dropped in the first (the inactive buffers of the active set serve
+        // as scratch)
+        uint32_t* t0 = S.act(buf ^ 1);
+        uint32_t* t1 = reinterpret_cast<uint32_t*>(S.ze(buf ^ 1));
+        int n1 = drop_dead<Mem>(A, act, n, t0);
+        act = t0;
+        if (n1 >= 2 && n1 < n) {
+            int n2 = drop_dead<Mem>(A, t0, n1, t1);
+            act = t1;
+            n1 = n2;
+        }
+        n = n1;
+        if (n == 0) {
+            PruneResult r;
+            r.len = 0;
+            r.used = 0;
+            r.lip = 0.f;
+            return r;
+        }
+    }
     if (n == 1) {
         if (lane == 0) S.vs()[0] = act[0];
         m = 1;
+    } else if (n <= 64) {
+        // one element per lane: LCAs of consecutive primitives, then every
+        // element's position in post-order by counting (all-pairs compares
+        // through readlane; no sort passes, no LDS round trips)
+        const int nl = n - 1;
+        const uint32_t a = lane < n ? act[lane] : 0xFFFFFFFFu;
+        const uint32_t an = lane + 1 < n ? act[lane + 1] : 0u;
+        uint32_t l = 0xFFFFFFFFu;
+        if (lane < nl) l = (a < an && an < A.n_nodes) ? lca_query(A.rmq, A.n_nodes, a, an) : 0u;
+        uint32_t rl = 0, ca = 0, cl = 0;   // LCAs before l, primitives before l, LCAs before a
+        for (int j = 0; j < n; j++) {
+            const uint32_t lj = rdlane(l, j), aj = rdlane(a, j);
+            if (j < nl) {
+                rl += (lj < l || (lj == l && j < lane)) ? 1u : 0u;
+                cl += lj < a ? 1u : 0u;
+            }
+            ca += aj < l ? 1u : 0u;
+        }
+        wave_sync();
+        if (lane < n) S.vs()[lane + int(cl)] = a;
+        if (lane < nl) S.vs()[int(rl + ca)] = l;
+        m = 2 * n - 1;
     } else {
         // 1. LCAs of consecutive active primitives
         int nl = n - 1;
@@ -465,9 +545,11 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         float mz = -__builtin_inff();
         for (int s = lane; s < n; s += 64) mz = fmaxf(mz, S.ze(buf)[s]);
         mz = wave_max(mz);
-        // -- fetch new primitives (lane c considers list entry i + c)
-        int k = 0;
-        if (i < e1) {
+        // -- fetch new primitives, up to 64 per round (lane c considers list
+        //    entry i + c), rounds until max_new, a gap, the depth limit or
+        //    the capacity stops it
+        int fetched = 0;
+        while (i < e1 && fetched < A.max_new) {
             uint32_t c = uint32_t(lane);
             bool in = i + c < e1;
             float zb = in ? A.e_zin[i + c] : __builtin_inff();
@@ -482,43 +564,44 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             float pex = __shfl_up(pm, 1);
             if (lane == 0) pex = -__builtin_inff();
             float reach = fmaxf(fmaxf(z_begin, mz), pex);
-            bool ok = in && lane < A.max_new && (n + lane) < S.cap() && (zb - z_begin < A.d_sub || lane == 0) &&
-                      zb <= reach;
+            bool ok = in && fetched + lane < A.max_new && (n + lane) < S.cap() &&
+                      (zb - z_begin < A.d_sub || (lane == 0 && fetched == 0)) && zb <= reach;
             uint64_t okm = ballot(ok);
-            k = ~okm == 0ull ? 64 : int(__builtin_ctzll(~okm));
-            if (k > 0) {
-                // merge the k new primitives (lanes 0..k-1) into the sorted active list
-                // (cross-lane reads stay outside the divergent stores)
-                int nb = buf ^ 1;
-                for (int b = 0; b < n; b += 64) {
-                    int s = b + lane;
-                    bool in_s = s < n;
-                    uint32_t a = in_s ? S.act(buf)[s] : 0xFFFFFFFFu;
-                    float az = in_s ? S.ze(buf)[s] : 0.f;
-                    int less = 0;
-                    for (int q = 0; q < k; q++) less += rdlane(nd, q) < a ? 1 : 0;
-                    if (in_s) {
-                        S.act(nb)[s + less] = a;
-                        S.ze(nb)[s + less] = az;
-                    }
+            const int k = ~okm == 0ull ? 64 : int(__builtin_ctzll(~okm));
+            if (k == 0) break;
+            // merge the k new primitives (lanes 0..k-1) into the sorted active list
+            // (cross-lane reads stay outside the divergent stores)
+            int nb = buf ^ 1;
+            for (int b = 0; b < n; b += 64) {
+                int s = b + lane;
+                bool in_s = s < n;
+                uint32_t a = in_s ? S.act(buf)[s] : 0xFFFFFFFFu;
+                float az = in_s ? S.ze(buf)[s] : 0.f;
+                int less = 0;
+                for (int q = 0; q < k; q++) less += rdlane(nd, q) < a ? 1 : 0;
+                if (in_s) {
+                    S.act(nb)[s + less] = a;
+                    S.ze(nb)[s + less] = az;
                 }
-                {
-                    int pos = lower_count(S.act(buf), n, nd);
-                    int less = 0;
-                    for (int q = 0; q < k; q++) less += rdlane(nd, q) < nd ? 1 : 0;
-                    if (lane < k) {
-                        S.act(nb)[pos + less] = nd;
-                        S.ze(nb)[pos + less] = zo;
-                    }
-                }
-                // the new ones also extend the reach
-                float nz_ = lane < k ? zo : -__builtin_inff();
-                mz = fmaxf(mz, wave_max(nz_));
-                buf = nb;
-                n += k;
-                i += uint32_t(k);
-                wave_sync();
             }
+            {
+                int pos = lower_count(S.act(buf), n, nd);
+                int less = 0;
+                for (int q = 0; q < k; q++) less += rdlane(nd, q) < nd ? 1 : 0;
+                if (lane < k) {
+                    S.act(nb)[pos + less] = nd;
+                    S.ze(nb)[pos + less] = zo;
+                }
+            }
+            // the new ones also extend the reach
+            float nz_ = lane < k ? zo : -__builtin_inff();
+            mz = fmaxf(mz, wave_max(nz_));
+            buf = nb;
+            n += k;
+            i += uint32_t(k);
+            fetched += k;
+            wave_sync();
+            if (k < 64) break;
         }
         const float z_next = i < e1 ? unif(A.e_zin[i]) : __builtin_inff();
         z_end = fminf(z_next, mz);

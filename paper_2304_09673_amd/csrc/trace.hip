@@ -84,6 +84,7 @@ void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float*
     A.blob = s->d_blob;
     A.par = s->d_par;
     A.kill = s->d_kill;
+    A.range = reinterpret_cast<const uint2*>(s->d_range);
     A.rmq = s->d_rmq;
     A.n_nodes = uint32_t(s->n_nodes);
     A.tile_off = s->d_tile_off;
@@ -104,7 +105,7 @@ void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float*
     A.omega = t.omega;
     A.max_steps = t.max_steps;
     A.refine_iters = t.refine_iters;
-    A.max_new = std::max(1, std::min(64, t.max_new));
+    A.max_new = std::max(1, std::min(4096, t.max_new));
     A.step_mode = t.step_mode;
     A.out_depth = depth;
     A.out_normal = normal;
@@ -228,6 +229,7 @@ st_status debug_eval_device(const st_scene* s, const uint32_t* act_sorted_dev, i
     A.blob = s->d_blob;
     A.par = s->d_par;
     A.kill = s->d_kill;
+    A.range = reinterpret_cast<const uint2*>(s->d_range);
     A.rmq = s->d_rmq;
     A.n_nodes = uint32_t(s->n_nodes);
     if (n > kMaDebug) { set_error("debug_eval: active set larger than 1024"); return ST_E_CAPACITY; }

@@ -10,6 +10,10 @@ import scenegen as sg
 
 pytestmark = pytest.mark.gpu
 
+# batched rendering is switched off in the library (st_batch_create refuses)
+DISABLED = pytest.mark.skip(reason="batched rendering is switched off: a batch creation did not return on the "
+                                   "device and the cause is not identified; st_batch_create refuses until it is")
+
 
 def _log(*a):
     print(*a, flush=True)
@@ -35,6 +39,7 @@ def _standalone(sc, tuning):
     return d.cpu().numpy(), n.cpu().numpy()
 
 
+@DISABLED
 @pytest.mark.parametrize("tile", [8, 16, 32])
 def test_batch_equals_standalone(tile):
     import torch
@@ -64,6 +69,7 @@ def test_batch_equals_standalone(tile):
     b.close()
 
 
+@DISABLED
 def test_batch_with_wide_tiles_equals_standalone():
     """A scene whose tiles overlap more than the LDS fast-path capacity."""
     import torch
@@ -83,6 +89,7 @@ def test_batch_with_wide_tiles_equals_standalone():
     b.close()
 
 
+@DISABLED
 def test_batch_stale_after_rebuild():
     from paper_2304_09673_amd import st
     scs = _scenes(range(2), 8)
@@ -95,6 +102,7 @@ def test_batch_stale_after_rebuild():
     b.close()
 
 
+@DISABLED
 def test_batch_rejects_bad_input():
     from paper_2304_09673_amd import st
     sc = sg.config1(seed=0, width=32, height=32)
@@ -103,3 +111,12 @@ def test_batch_rejects_bad_input():
         st.Batch([h, h], [sc.camera, sc.camera])
     with pytest.raises(st.StError):
         st.Batch([h], [sc.camera], tuning=st.default_tuning(step_mode=st.ST_STEP_OVERRELAX))
+
+
+def test_batch_refuses_while_switched_off():
+    """The switched-off batch entry points fail loudly (no silent fallback)."""
+    from paper_2304_09673_amd import st
+    sc = sg.config1(seed=0, width=32, height=32)
+    h = st.Scene(sc)
+    with pytest.raises(st.StError, match="disabled"):
+        st.Batch([h], [sc.camera])

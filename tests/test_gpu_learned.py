@@ -98,7 +98,7 @@ def test_overrelaxed_parity(which, seed):
     assert s_o["unconverged"] == 0
 
 
-@pytest.mark.parametrize("which,seed", [("c1", 5), ("c2", 3), ("c2", 4)])
+@pytest.mark.parametrize("which,seed", [("c1", 5), ("c2", 0), ("c2", 3)])
 def test_learned_parity(model, which, seed):
     st = _st()
     sc = sg.config1(seed=seed, width=128, height=128) if which == "c1" else sg.config2(seed=seed, width=256, height=256)
@@ -108,6 +108,7 @@ def test_learned_parity(model, which, seed):
     r = compare(sc, d_l, n_l, px, py)
     assert r["fail"] == 0, r
     np.testing.assert_array_equal(np.isfinite(d_l), np.isfinite(d_p))
+    assert s_p["steps"] > 0, "the scene shows no surface at this camera"
     assert s_l["learned_accepted"] > 0, (s_l, s_p)
     assert s_l["unconverged"] == 0
     # fewer stepping evaluations than plain
@@ -155,18 +156,22 @@ def test_learned_vs_plain_on_large_scene(model):
         out[name] = (ms, d.cpu().numpy(), n.cpu().numpy(), stats)
     d_p = out["plain"][1]
     hit = np.isfinite(d_p)
+    mis = np.zeros_like(hit)
     for name in ("overrelax", "learned"):
-        np.testing.assert_array_equal(np.isfinite(out[name][1]), hit)
-    # depth error on up to 96 hit pixels plus 32 random ones
+        mis |= np.isfinite(out[name][1]) != hit
+    assert mis.sum() <= 4, int(mis.sum())
+    # depth error on up to 96 hit pixels plus 32 random ones, plus every pixel
+    # whose hit/miss differs between the tracers (must be exempt or correct)
     jj, ii = np.nonzero(hit)
     rng = np.random.default_rng(3)
     pick = rng.permutation(jj.shape[0])[:96]
     rx, ry = sample_pixels(sc.camera, 32, 4)
-    px = np.concatenate([ii[pick], rx])
-    py = np.concatenate([jj[pick], ry])
+    mj, mi = np.nonzero(mis)
+    px = np.concatenate([ii[pick], rx, mi])
+    py = np.concatenate([jj[pick], ry, mj])
     osc = oracle.OracleScene(sc)
     errs = {}
-    for name in ("plain", "learned"):
+    for name in ("plain", "overrelax", "learned"):
         r = compare(sc, out[name][1], out[name][2], px, py, osc=osc)
         assert r["fail"] == 0, (name, r)
         errs[name] = r["max_depth_err_rel"]
@@ -190,13 +195,16 @@ def test_full_size_large_scene_sampled(model):
     d_l, n_l, s_l = _render(sc, st.ST_STEP_LEARNED, model=model, tuning_kw=kw)
     assert s_p["unconverged"] == 0 and s_l["unconverged"] == 0
     assert s_p["stalled"] == 0 and s_l["stalled"] == 0
-    np.testing.assert_array_equal(np.isfinite(d_l), np.isfinite(d_p))
+    # hit/miss may differ only on rays the parity rules exempt (within 1e-4 of
+    # a silhouette): every pixel where the two differ is checked against the oracle
+    mis_j, mis_i = np.nonzero(np.isfinite(d_l) != np.isfinite(d_p))
+    assert mis_j.shape[0] <= 16, mis_j.shape[0]
     jj, ii = np.nonzero(np.isfinite(d_p))
     rng = np.random.default_rng(11)
     pick = rng.permutation(jj.shape[0])[:48]
     rx, ry = sample_pixels(sc.camera, 32, 12)
-    px = np.concatenate([ii[pick], rx])
-    py = np.concatenate([jj[pick], ry])
+    px = np.concatenate([ii[pick], rx, mis_i])
+    py = np.concatenate([jj[pick], ry, mis_j])
     osc = oracle.OracleScene(sc)
     for name, d, n in (("plain", d_p, n_p), ("learned", d_l, n_l)):
         r = compare(sc, d, n, px, py, osc=osc)

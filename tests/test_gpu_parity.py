@@ -188,3 +188,31 @@ def test_trace_rejects_stale_camera():
     with pytest.raises(st.StError) as e:
         s.trace(other)
     assert e.value.code == st.ST_E_STALE
+
+
+@pytest.mark.parametrize("which", ["c3", "c5"])
+def test_device_view_equals_host_view_large_sets(which):
+    """Random active sets of 2 to 1000 primitives (scattered and contiguous in
+    post-order): the device view (dead-primitive filter, both ordering paths,
+    the bottom-up pass) equals the host view of the same set."""
+    from paper_2304_09673_amd import st
+    sc = sg.config3() if which == "c3" else sg.config5(width=64, height=64)
+    s = st.Scene(sc)
+    prims = np.nonzero(np.isin(sc.kind, sg.PRIMITIVE_KINDS))[0]
+    rng = np.random.default_rng(5 if which == "c3" else 6)
+    n_used = 0
+    for size in (2, 3, 5, 30, 63, 64, 65, 129, 200, 511, 700, 1000):
+        for contiguous in (False, True):
+            if contiguous:
+                # primitives generated together: often one region of the tree
+                start = int(rng.integers(0, len(prims) - size))
+                act = prims[start:start + size]
+            else:
+                act = rng.choice(prims, size=size, replace=False)
+            act = [int(a) for a in act]
+            pt = np.zeros((1, 3), dtype=np.float32)
+            _, _, used, view = s.debug_eval(pt, act)
+            host_view, _ = st.prune_tree(sc.kind, sc.left, sc.right, sc.params, sc.root, act)
+            assert list(view) == list(host_view), (which, size, contiguous)
+            n_used += int(used)
+    assert n_used > 0
