@@ -237,7 +237,7 @@ def main():
     ap.add_argument("--max-new", type=int, default=64)
     ap.add_argument("--sub-depth", type=float, default=0.25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=6144)
+    ap.add_argument("--cpu-rays", type=int, default=24576)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--n-scenes", type=int, default=64)

@@ -513,6 +513,10 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
     // every turn fetches, drops or closes a subfrustum that the next turn
     // drops from; the bound only guards against a stalled capacity
     uint32_t guard = 4u * (e1 - e0) + 8u;
+    // entry depth of list entry i, when known from the last fetch round
+    // (saves a dependent global load per turn)
+    float zin_i = 0.f;
+    bool zin_ok = false;
 
     while (true) {
         if (ballot(!done) == 0) break;
@@ -540,7 +544,7 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             wave_sync();
         }
         if (i >= e1 && n == 0) break;
-        const float z_begin = n > 0 ? z_end : unif(A.e_zin[i]);
+        const float z_begin = n > 0 ? z_end : (zin_ok ? zin_i : unif(A.e_zin[i]));
         // max exit depth of the remaining active set
         float mz = -__builtin_inff();
         for (int s = lane; s < n; s += 64) mz = fmaxf(mz, S.ze(buf)[s]);
@@ -568,6 +572,9 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                       (zb - z_begin < A.d_sub || (lane == 0 && fetched == 0)) && zb <= reach;
             uint64_t okm = ballot(ok);
             const int k = ~okm == 0ull ? 64 : int(__builtin_ctzll(~okm));
+            // entry i + k is in this round's window unless all 64 were taken
+            zin_ok = k < 64;
+            if (k < 64) zin_i = rdlanef(zb, k);   // +inf past the end of the list
             if (k == 0) break;
             // merge the k new primitives (lanes 0..k-1) into the sorted active list
             // (cross-lane reads stay outside the divergent stores)
@@ -603,7 +610,13 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             wave_sync();
             if (k < 64) break;
         }
-        const float z_next = i < e1 ? unif(A.e_zin[i]) : __builtin_inff();
+        if (i >= e1) {
+            zin_i = __builtin_inff();
+            zin_ok = true;
+        }
+        const float z_next = zin_ok ? zin_i : unif(A.e_zin[i]);
+        zin_i = z_next;
+        zin_ok = true;
         z_end = fminf(z_next, mz);
         max_act = max(max_act, uint32_t(n));
         if (!(z_end > z_begin)) continue;

