@@ -266,7 +266,7 @@ st_status st_autotune(st_scene *s, const st_camera *cam, const st_tuning *base, 
  * plain step f/L, f/f_prev, the previous step, log2(1 + step index), the secant
  * slope of f along the ray divided by L, log2(1 + active primitives), t, and
  * log2(1 + pruned-view length); the model standardises them with norm[16] =
- * means[8], inverse standard deviations[8].  Arithmetic: binary16 inputs,
+ * means[8], inverse standard deviations[8], and clamps them to [-3, 3].  Arithmetic: binary16 inputs,
  * weights and hidden activations, FP32 accumulation (matrix cores).
  * All array arguments of the st_mlp_* calls are device memory owned by the
  * caller; the calls are asynchronous on `stream`.

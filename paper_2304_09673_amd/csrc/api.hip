@@ -41,6 +41,8 @@ static void free_abuffer(st_scene* s, hipStream_t stream) {
     dev_free(s, s->d_e_node, stream); s->d_e_node = nullptr;
     dev_free(s, s->d_e_zin, stream); s->d_e_zin = nullptr;
     dev_free(s, s->d_e_zout, stream); s->d_e_zout = nullptr;
+    dev_free(s, s->d_e_lo, stream); s->d_e_lo = nullptr;
+    dev_free(s, s->d_e_hi, stream); s->d_e_hi = nullptr;
     dev_free(s, s->d_wide, stream); s->d_wide = nullptr;
     dev_free(s, s->d_scratch, stream); s->d_scratch = nullptr;
     dev_free(s, s->d_slots, stream); s->d_slots = nullptr;

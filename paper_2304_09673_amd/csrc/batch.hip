@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(64) batch_wide_kernel(const TraceArgs* __restr
                                                         const uint2* __restrict__ jobs, uint32_t n_jobs,
                                                         uint32_t* __restrict__ head, uint32_t* slots, int ma) {
     extern __shared__ uint32_t dyn_slot[];
-    WaveGlob S{InLds ? dyn_slot : slots + size_t(blockIdx.x) * 9u * uint32_t(ma), ma};
+    WaveGlob S{InLds ? dyn_slot : slots + size_t(blockIdx.x) * slot_words(ma), ma};
     for (uint32_t it = 0; it < n_jobs; it++) {
         const uint32_t j = next_job(head);
         if (j >= n_jobs) break;
@@ -77,7 +77,7 @@ struct st_batch {
     uint2* d_jobs = nullptr;          // fast jobs, then wide jobs
     uint32_t n_fast = 0, n_wide = 0;
     uint32_t* d_heads = nullptr;      // [0] fast queue, [1] wide queue
-    uint32_t* d_slots = nullptr;      // wide path in global memory (ma > kMaLds)
+    uint32_t* d_slots = nullptr;      // wide path in global memory (slots above the LDS size)
     int ma = 0;
     bool deep = false;                // evaluation stack 32 (some tree deeper than 16)
     uint32_t grid_fast = 0, grid_wide = 0;
@@ -110,8 +110,8 @@ st_status enqueue_frame(st_batch* b, hipStream_t stream) {
     }
     if (b->n_wide) {
         const uint2* wj = b->d_jobs + b->n_fast;
-        if (b->ma <= kMaLds) {
-            size_t shm = size_t(9) * size_t(b->ma) * 4u;
+        if (slot_words(b->ma) * 4u <= kSlotLdsBytes) {
+            size_t shm = slot_words(b->ma) * 4u;
             if (b->deep)
                 hipLaunchKernelGGL((batch_wide_kernel<32, true>), dim3(b->grid_wide), dim3(64), shm, stream, b->d_args,
                                    wj, b->n_wide, b->d_heads + 1, b->d_slots, b->ma);
@@ -222,9 +222,10 @@ st_status st_batch_create(st_scene* const* scenes, const st_camera* cams, int32_
     b->d_args = (TraceArgs*)dev_alloc(b->owner, sizeof(TraceArgs) * size_t(n), stream);
     b->d_jobs = (uint2*)dev_alloc(b->owner, sizeof(uint2) * std::max<size_t>(hj.size(), 1), stream);
     b->d_heads = (uint32_t*)dev_alloc(b->owner, 64, stream);
-    if (b->n_wide && ma > kMaLds)
-        b->d_slots = (uint32_t*)dev_alloc(b->owner, size_t(b->grid_wide) * 9u * size_t(ma) * 4u, stream);
-    if (!b->d_args || !b->d_jobs || !b->d_heads || (b->n_wide && ma > kMaLds && !b->d_slots)) {
+    const bool wide_lds = slot_words(ma) * 4u <= kSlotLdsBytes;
+    if (b->n_wide && !wide_lds)
+        b->d_slots = (uint32_t*)dev_alloc(b->owner, size_t(b->grid_wide) * slot_words(ma) * 4u, stream);
+    if (!b->d_args || !b->d_jobs || !b->d_heads || (b->n_wide && !wide_lds && !b->d_slots)) {
         batch_free(b);
         set_error("batch: allocation failed");
         return ST_E_NOMEM;
@@ -233,11 +234,11 @@ st_status st_batch_create(st_scene* const* scenes, const st_camera* cams, int32_
     if (e == hipSuccess && !hj.empty())
         e = hipMemcpyAsync(b->d_jobs, hj.data(), sizeof(uint2) * hj.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e == hipSuccess && b->n_wide && ma <= kMaLds) {
+    if (e == hipSuccess && b->n_wide && wide_lds) {
         if (b->deep) e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_wide_kernel<32, true>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, 9 * kMaLds * 4);
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(kSlotLdsBytes));
         else e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_wide_kernel<16, true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 9 * kMaLds * 4);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(kSlotLdsBytes));
     }
     if (e != hipSuccess) { batch_free(b); return device_error(e, "batch: upload"); }
     // one direct frame first: every kernel of the frame is launched (and its

@@ -344,6 +344,22 @@ __global__ void scatter_kernel(const Voi* __restrict__ voi, const uint32_t* __re
     e_zout[pos] = z.y;
 }
 
+// partner range of every entry's primitive (kill_partner_range), read by the
+// tracer with the entry so that its dead-primitive test needs no table lookups
+__global__ void entry_range_kernel(const uint32_t* __restrict__ e_node, uint32_t n_ent,
+                                   const uint32_t* __restrict__ kill, const uint2* __restrict__ range,
+                                   uint32_t n_nodes, uint32_t* __restrict__ e_lo, uint32_t* __restrict__ e_hi) {
+    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_ent) return;
+    const uint32_t x = e_node[e];
+    const uint32_t K = kill[min(x, n_nodes - 1u)];
+    const uint2 r = K < n_nodes ? range[K] : make_uint2(0u, 0u);
+    uint32_t lo, hi;
+    kill_partner_range(x, K, r.x, r.y, n_nodes, lo, hi);
+    e_lo[e] = lo;
+    e_hi[e] = hi;
+}
+
 // ---------------------------------------------------------------------------
 // per-tile sort by (z_in, node) and largest depth overlap
 __device__ __forceinline__ uint32_t f2key(float f) {
@@ -606,11 +622,15 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         dev_free(s, s->d_e_node, stream);
         dev_free(s, s->d_e_zin, stream);
         dev_free(s, s->d_e_zout, stream);
+        dev_free(s, s->d_e_lo, stream);
+        dev_free(s, s->d_e_hi, stream);
         int64_t cap = std::max<int64_t>(int64_t(n_ent) + int64_t(n_ent) / 4, 1024);
         s->d_e_node = (uint32_t*)dev_alloc(s, size_t(cap) * 4, stream);
         s->d_e_zin = (float*)dev_alloc(s, size_t(cap) * 4, stream);
         s->d_e_zout = (float*)dev_alloc(s, size_t(cap) * 4, stream);
-        if (!s->d_e_node || !s->d_e_zin || !s->d_e_zout) {
+        s->d_e_lo = (uint32_t*)dev_alloc(s, size_t(cap) * 4, stream);
+        s->d_e_hi = (uint32_t*)dev_alloc(s, size_t(cap) * 4, stream);
+        if (!s->d_e_node || !s->d_e_zin || !s->d_e_zout || !s->d_e_lo || !s->d_e_hi) {
             set_error("build: A-buffer allocation failed");
             s->ab_cap = 0;
             return ST_E_NOMEM;
@@ -639,6 +659,10 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipLaunchKernelGGL(tile_sort_long_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream,
                        s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, sk, sv, sz,
                        uint32_t(s->ab_ma_fast), s->d_wide);
+    if (n_ent)
+        hipLaunchKernelGGL(entry_range_kernel, dim3((n_ent + 255) / 256), dim3(256), 0, stream, s->d_e_node, n_ent,
+                           s->d_kill, reinterpret_cast<const uint2*>(s->d_range), uint32_t(s->n_nodes), s->d_e_lo,
+                           s->d_e_hi);
     if (replay) {
         e = hipGetLastError();
         return e == hipSuccess ? ST_OK : device_error(e, "binning kernels");

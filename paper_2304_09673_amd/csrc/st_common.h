@@ -99,4 +99,21 @@ HD Ray pixel_ray(const DevCam& c, int i, int j) {
     return r;
 }
 
+// The operand of x's nearest killing ancestor K (an intersection, or a
+// difference reached from its right operand) that x does not belong to, as a
+// post-order node range [lo, hi): x's branch survives K only if an active
+// primitive lies in it.  (first, split) are K's subtree start and the start
+// of K's right subtree.  Without a killing ancestor the range is [0, 2^32-1),
+// which always holds x itself.
+HD void kill_partner_range(uint32_t x, uint32_t K, uint32_t first, uint32_t split, uint32_t n_nodes,
+                           uint32_t& lo, uint32_t& hi) {
+    if (K < n_nodes) {
+        lo = x < split ? split : first;
+        hi = x < split ? K : split;
+    } else {
+        lo = 0u;
+        hi = 0xFFFFFFFFu;
+    }
+}
+
 }  // namespace st

@@ -49,6 +49,8 @@ struct st_scene {
     uint32_t* d_e_node = nullptr;     // entries, SoA, sorted per tile
     float* d_e_zin = nullptr;
     float* d_e_zout = nullptr;
+    uint32_t* d_e_lo = nullptr;   // partner range of the entry's primitive
+    uint32_t* d_e_hi = nullptr;
     uint32_t* d_wide = nullptr;       // list of tiles that need the wide path, [0] = count
     uint32_t* d_misc = nullptr;       // small device counters
     int64_t n_entries = 0, ab_cap = 0;

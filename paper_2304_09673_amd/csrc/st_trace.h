@@ -88,6 +88,8 @@ struct TraceArgs {
     uint32_t n_nodes;
     const uint32_t* tile_off;
     const uint32_t* e_node;
+    const uint32_t* e_lo;      // per entry: partner range of the primitive (kill_partner_range)
+    const uint32_t* e_hi;
     const float* e_zin;
     const float* e_zout;
     const uint32_t* tile_ovl;
@@ -111,10 +113,20 @@ struct TraceArgs {
 // step modes (template parameter of the tracer)
 enum { SM_PLAIN = 0, SM_OVER = 1, SM_LEARNED = 2, SM_DUMP = 3 };
 
-// active-set capacity of the LDS fast path (per wave), and the largest
-// wide-path capacity held in LDS: 9 * 2048 words = 72 KiB per workgroup
+// active-set capacity of the LDS fast path (per wave)
 constexpr int kMaFast = 256;
-constexpr int kMaLds = 2048;
+// wide-path slots up to this size are held in LDS (one wave per workgroup)
+constexpr size_t kSlotLdsBytes = 80 * 1024;
+
+__host__ __device__ inline uint32_t pow2_at_least(uint32_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+// 32-bit words of a wide-path slot of capacity ma: active set (node, exit
+// depth, partner range lo/hi; two buffers each), vs and view (2 ma each), and
+// the LCA sort array (a power of two at least ma)
+__host__ __device__ inline size_t slot_words(int ma) { return 12 * size_t(ma) + pow2_at_least(uint32_t(ma)); }
 
 // kernel arguments of one scene (trace.hip)
 void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
@@ -137,26 +149,32 @@ template <int MA>
 struct WaveLds {
     uint32_t act_[2][MA];
     float ze_[2][MA];
+    uint32_t lo_[2][MA];
+    uint32_t hi_[2][MA];
     uint32_t lca_[MA];
     uint32_t vs_[2 * MA];
     uint32_t view_[2 * MA];
     __device__ __forceinline__ uint32_t* act(int b) { return act_[b]; }
     __device__ __forceinline__ float* ze(int b) { return ze_[b]; }
+    __device__ __forceinline__ uint32_t* olo(int b) { return lo_[b]; }
+    __device__ __forceinline__ uint32_t* ohi(int b) { return hi_[b]; }
     __device__ __forceinline__ uint32_t* lca() { return lca_; }
     __device__ __forceinline__ uint32_t* vs() { return vs_; }
     __device__ __forceinline__ uint32_t* view() { return view_; }
     __device__ __forceinline__ int cap() const { return MA; }
 };
 
-// 9 * ma 32-bit words per slot: act 2ma, ze 2ma, lca ma, vs 2ma, view 2ma
+// slot_words(ma) 32-bit words per slot (layout in that order)
 struct WaveGlob {
     uint32_t* base;
     int ma;
     __device__ __forceinline__ uint32_t* act(int b) { return base + b * ma; }
-    __device__ __forceinline__ float* ze(int b) { return reinterpret_cast<float*>(base + 2 * ma + b * ma); }
-    __device__ __forceinline__ uint32_t* lca() { return base + 4 * ma; }
-    __device__ __forceinline__ uint32_t* vs() { return base + 5 * ma; }
-    __device__ __forceinline__ uint32_t* view() { return base + 7 * ma; }
+    __device__ __forceinline__ float* ze(int b) { return reinterpret_cast<float*>(base + (2 + b) * ma); }
+    __device__ __forceinline__ uint32_t* olo(int b) { return base + (4 + b) * ma; }
+    __device__ __forceinline__ uint32_t* ohi(int b) { return base + (6 + b) * ma; }
+    __device__ __forceinline__ uint32_t* vs() { return base + 8 * ma; }
+    __device__ __forceinline__ uint32_t* view() { return base + 10 * ma; }
+    __device__ __forceinline__ uint32_t* lca() { return base + 12 * ma; }
     __device__ __forceinline__ int cap() const { return ma; }
 };
 
@@ -294,8 +312,10 @@ __device__ __forceinline__ int lower_count(const uint32_t* a, int n, uint32_t x)
 // the same side), and K is unused.  Removing it leaves the pruned view
 // unchanged and shrinks the work of the view build.  act[0..n) sorted;
 // survivors written in order to out; returns their count.
-template <class Mem>
-__device__ int drop_dead(const TraceArgs& A, const uint32_t* act, int n, uint32_t* out) {
+// act, plo, phi: primitives (sorted) and their partner ranges; survivors go
+// to out (and their ranges to out_lo/out_hi when those are given).
+__device__ int drop_dead(const uint32_t* act, const uint32_t* plo, const uint32_t* phi, int n, uint32_t* out,
+                         uint32_t* out_lo, uint32_t* out_hi) {
     const int lane = lane_id();
     int kept = 0;
     wave_sync();
@@ -303,19 +323,15 @@ __device__ int drop_dead(const TraceArgs& A, const uint32_t* act, int n, uint32_
         const int s = b + lane;
         const bool in = s < n;
         const uint32_t x = in ? act[s] : 0u;
-        bool keep = in;
-        if (in) {
-            const uint32_t K = A.kill[min(x, A.n_nodes - 1u)];
-            if (K < A.n_nodes) {
-                const uint2 r = A.range[K];
-                // K's other operand: [split, K) when x is on the left, else [first, split)
-                const uint32_t lo = x < r.y ? r.y : r.x;
-                const uint32_t hi = x < r.y ? K : r.y;
-                keep = lower_count(act, n, hi) > lower_count(act, n, lo);
-            }
-        }
+        const uint32_t lo = in ? plo[s] : 0u, hi = in ? phi[s] : 0u;
+        // an active primitive in [lo, hi)
+        const bool keep = in && lower_count(act, n, hi) > lower_count(act, n, lo);
         const uint64_t mk = ballot(keep);
-        if (keep) out[kept + int(lanes_below(mk))] = x;
+        const int dst = kept + int(lanes_below(mk));
+        if (keep) {
+            out[dst] = x;
+            if (out_lo) { out_lo[dst] = lo; out_hi[dst] = hi; }
+        }
         kept += __popcll(mk);
     }
     wave_sync();
@@ -333,10 +349,10 @@ __device__ PruneResult build_view(const TraceArgs& A, Mem& S, int buf, int n) {
         // as scratch)
         uint32_t* t0 = S.act(buf ^ 1);
         uint32_t* t1 = reinterpret_cast<uint32_t*>(S.ze(buf ^ 1));
-        int n1 = drop_dead<Mem>(A, act, n, t0);
+        int n1 = drop_dead(act, S.olo(buf), S.ohi(buf), n, t0, S.olo(buf ^ 1), S.ohi(buf ^ 1));
         act = t0;
         if (n1 >= 2 && n1 < n) {
-            int n2 = drop_dead<Mem>(A, t0, n1, t1);
+            int n2 = drop_dead(t0, S.olo(buf ^ 1), S.ohi(buf ^ 1), n1, t1, nullptr, nullptr);
             act = t1;
             n1 = n2;
         }
@@ -533,11 +549,12 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                 bool in = s < n;
                 uint32_t a = in ? S.act(buf)[s] : 0u;
                 float z = in ? S.ze(buf)[s] : 0.f;
+                uint32_t plo = in ? S.olo(buf)[s] : 0u, phi = in ? S.ohi(buf)[s] : 0u;
                 bool keep = in && z > z_end;
                 uint64_t mk = ballot(keep);
                 int dst = kept + int(lanes_below(mk));
                 wave_sync();
-                if (keep) { S.act(buf)[dst] = a; S.ze(buf)[dst] = z; }
+                if (keep) { S.act(buf)[dst] = a; S.ze(buf)[dst] = z; S.olo(buf)[dst] = plo; S.ohi(buf)[dst] = phi; }
                 kept += __popcll(mk);
             }
             n = kept;
@@ -559,6 +576,7 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             float zb = in ? A.e_zin[i + c] : __builtin_inff();
             float zo = in ? A.e_zout[i + c] : -__builtin_inff();
             uint32_t nd = in ? A.e_node[i + c] : 0u;
+            const uint32_t nlo = in ? A.e_lo[i + c] : 0u, nhi = in ? A.e_hi[i + c] : 0u;
             // exclusive prefix max of exit depths of earlier candidates
             float pm = zo;
             for (int o = 1; o < 64; o <<= 1) {
@@ -584,11 +602,14 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                 bool in_s = s < n;
                 uint32_t a = in_s ? S.act(buf)[s] : 0xFFFFFFFFu;
                 float az = in_s ? S.ze(buf)[s] : 0.f;
+                uint32_t alo = in_s ? S.olo(buf)[s] : 0u, ahi = in_s ? S.ohi(buf)[s] : 0u;
                 int less = 0;
                 for (int q = 0; q < k; q++) less += rdlane(nd, q) < a ? 1 : 0;
                 if (in_s) {
                     S.act(nb)[s + less] = a;
                     S.ze(nb)[s + less] = az;
+                    S.olo(nb)[s + less] = alo;
+                    S.ohi(nb)[s + less] = ahi;
                 }
             }
             {
@@ -598,6 +619,8 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                 if (lane < k) {
                     S.act(nb)[pos + less] = nd;
                     S.ze(nb)[pos + less] = zo;
+                    S.olo(nb)[pos + less] = nlo;
+                    S.ohi(nb)[pos + less] = nhi;
                 }
             }
             // the new ones also extend the reach

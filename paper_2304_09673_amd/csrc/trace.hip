@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) trace_fast_kernel(TraceArgs A, uint32_t n
 template <int KS, int SM, bool InLds>
 __global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A, uint32_t* slots, int ma) {
     extern __shared__ uint32_t dyn_slot[];
-    WaveGlob S{InLds ? dyn_slot : slots + size_t(blockIdx.x) * 9u * uint32_t(ma), ma};
+    WaveGlob S{InLds ? dyn_slot : slots + size_t(blockIdx.x) * slot_words(ma), ma};
     // the step-model table is read through the caches here: one wave per
     // workgroup, and LDS is what limits the number of resident waves
     const uint32_t* tab = SM == SM_LEARNED ? A.mlp : nullptr;
@@ -62,12 +62,12 @@ static hipError_t launch_trace(const TraceArgs& A, uint32_t nwg, uint32_t n_jobs
     hipLaunchKernelGGL((trace_fast_kernel<kMaFast, KS, SM>), dim3(nwg), dim3(256), 0, stream, A, n_jobs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || wide_grid == 0) return e;
-    if (ma <= kMaLds) {
-        const size_t shm = size_t(9) * size_t(ma) * 4u;
+    const size_t shm = slot_words(ma) * 4u;
+    if (shm <= kSlotLdsBytes) {
         static bool attr_set = false;   // per process; same value every call
         if (!attr_set) {
             e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_wide_kernel<KS, SM, true>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(9 * kMaLds * 4));
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(kSlotLdsBytes));
             if (e != hipSuccess) return e;
             attr_set = true;
         }
@@ -89,6 +89,8 @@ void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float*
     A.n_nodes = uint32_t(s->n_nodes);
     A.tile_off = s->d_tile_off;
     A.e_node = s->d_e_node;
+    A.e_lo = s->d_e_lo;
+    A.e_hi = s->d_e_hi;
     A.e_zin = s->d_e_zin;
     A.e_zout = s->d_e_zout;
     A.tile_ovl = s->d_tile_ovl;
@@ -114,11 +116,10 @@ void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float*
 }
 
 int wide_capacity(const st_scene* s) {
-    // a power of two above the largest depth overlap, so the active set can
+    // a multiple of 64 above the largest depth overlap, so the active set can
     // always advance
-    int ma = 512;
-    while (uint32_t(ma) <= s->max_overlap) ma <<= 1;
-    return ma;
+    const uint32_t need = s->max_overlap + 1u;
+    return int(std::max<uint32_t>(512u, (need + 63u) / 64u * 64u));
 }
 
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
@@ -149,8 +150,9 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
     if (s->n_wide > 0) {
         ma = wide_capacity(s);
         uint32_t jobs = s->n_wide * spt;
-        grid = std::min<uint32_t>(jobs, ma <= kMaLds ? 16384u : 3072u);
-        size_t need = ma <= kMaLds ? 0 : size_t(grid) * 9u * size_t(ma) * 4u;
+        const bool in_lds = slot_words(ma) * 4u <= kSlotLdsBytes;
+        grid = std::min<uint32_t>(jobs, in_lds ? 16384u : 3072u);
+        size_t need = in_lds ? 0 : size_t(grid) * slot_words(ma) * 4u;
         if (need > s->slots_bytes) {
             dev_free(s, s->d_slots, stream);
             s->d_slots = dev_alloc(s, need, stream);
@@ -189,7 +191,18 @@ __global__ void __launch_bounds__(64) debug_eval_kernel(TraceArgs A, const uint3
     extern __shared__ char dyn[];
     WaveLds<MA>& S = *reinterpret_cast<WaveLds<MA>*>(dyn);
     const int lane = lane_id();
-    for (int s = lane; s < n; s += 64) { S.act(0)[s] = act_sorted[s]; S.ze(0)[s] = 0.f; }
+    for (int s = lane; s < n; s += 64) {
+        const uint32_t x = act_sorted[s];
+        const uint32_t xc = min(x, A.n_nodes - 1u);
+        const uint32_t K = A.kill[xc];
+        const uint2 r = K < A.n_nodes ? A.range[K] : make_uint2(0u, 0u);
+        uint32_t lo, hi;
+        kill_partner_range(x, K, r.x, r.y, A.n_nodes, lo, hi);
+        S.act(0)[s] = x;
+        S.ze(0)[s] = 0.f;
+        S.olo(0)[s] = lo;
+        S.ohi(0)[s] = hi;
+    }
     wave_sync();
     PruneResult pr = build_view(A, S, 0, n);
     if (lane == 0) {

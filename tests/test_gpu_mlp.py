@@ -38,8 +38,8 @@ def _random_problem(seed, n, target_spread=True):
 
 def _oracle_inputs(w, norm, x):
     """The device's inputs to the arithmetic: binary16 weights and standardised
-    features computed in FP32, clamped to [-8, 8], then rounded to binary16."""
-    xs = np.clip(((x - norm[:8]) * norm[8:]).astype(np.float32), -8.0, 8.0)
+    features computed in FP32, clamped to [-3, 3], then rounded to binary16."""
+    xs = np.clip(((x - norm[:8]) * norm[8:]).astype(np.float32), -3.0, 3.0)
     return oracle.round_half(w.astype(np.float64)), oracle.round_half(xs.astype(np.float64))
 
 
