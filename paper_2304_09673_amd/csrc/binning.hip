@@ -271,55 +271,53 @@ static void exclusive_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* s
 }
 
 // ---------------------------------------------------------------------------
-// candidate (primitive, tile) test against the tile's pixel-centre rays: one
-// wave per candidate (the volume's kind and parameters are wave-uniform), each
-// lane tests ts*ts/64 rays, then a wave min/max of the entry and exit depths
+// candidate (primitive, tile) tests against the tiles' pixel-centre rays: one
+// workgroup per primitive (its volume of interest is workgroup-uniform and
+// read once), one wave per candidate tile in turn, each lane testing
+// ts*ts/64 rays, then a wave min/max of the entry and exit depths
 __global__ void __launch_bounds__(256) test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
-                                                   const uint32_t* __restrict__ cand_off, int P, uint32_t n_cand,
-                                                   DevCam cam, int ts, int tiles_x, float2* __restrict__ cz,
+                                                   const uint32_t* __restrict__ cand_off, int P, DevCam cam,
+                                                   int ts, int tiles_x, float2* __restrict__ cz,
                                                    uint32_t* __restrict__ ctile, uint32_t* __restrict__ tile_count) {
-    const uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6);
-    const int lane = int(threadIdx.x & 63u);
-    if (c >= n_cand) return;   // uniform per wave
-    // primitive owning candidate c: last p with cand_off[p] <= c
-    int lo = 0, hi = P - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (cand_off[mid] <= c) lo = mid; else hi = mid - 1;
-    }
-    const int p = lo;
+    const int p = int(blockIdx.x);
+    if (p >= P) return;
+    const int lane = int(threadIdx.x & 63u), w = int(threadIdx.x >> 6);
+    const uint32_t c0 = cand_off[p], cnt = cand_off[p + 1] - c0;
     const int4 rc = rect[p];
-    const uint32_t l = c - cand_off[p];
-    const int w = rc.z - rc.x + 1;
-    const int tx = rc.x + int(l % uint32_t(w)), ty = rc.y + int(l / uint32_t(w));
+    const int wr = rc.z - rc.x + 1;
     const Voi v = voi[p];
-    float zmin = __builtin_inff(), zmax = -__builtin_inff();
-    const int i0 = tx * ts, j0 = ty * ts;
-    for (int k = lane; k < ts * ts; k += 64) {
-        const int i = i0 + k % ts, j = j0 + k / ts;
-        if (i >= cam.w || j >= cam.h) continue;
-        Ray r = pixel_ray(cam, i, j);
-        float t0, t1;
-        if (ray_voi(v, r.o, r.d, t0, t1) && t1 >= 0.f) {
-            t0 = fmaxf(t0, 0.f);
-            zmin = fminf(zmin, t0 * r.cosv);
-            zmax = fmaxf(zmax, t1 * r.cosv);
+    for (uint32_t l = uint32_t(w); l < cnt; l += 4u) {
+        const int tx = rc.x + int(l % uint32_t(wr)), ty = rc.y + int(l / uint32_t(wr));
+        float zmin = __builtin_inff(), zmax = -__builtin_inff();
+        const int i0 = tx * ts, j0 = ty * ts;
+        for (int k = lane; k < ts * ts; k += 64) {
+            const int i = i0 + k % ts, j = j0 + k / ts;
+            if (i >= cam.w || j >= cam.h) continue;
+            Ray r = pixel_ray(cam, i, j);
+            float t0, t1;
+            if (ray_voi(v, r.o, r.d, t0, t1) && t1 >= 0.f) {
+                t0 = fmaxf(t0, 0.f);
+                zmin = fminf(zmin, t0 * r.cosv);
+                zmax = fmaxf(zmax, t1 * r.cosv);
+            }
         }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        zmin = fminf(zmin, __shfl_xor(zmin, o));
-        zmax = fmaxf(zmax, __shfl_xor(zmax, o));
-    }
-    if (lane != 0) return;
-    const uint32_t tile = uint32_t(ty * tiles_x + tx);
-    if (zmin <= zmax) {
-        // conservative padding for FP32 rounding of the intervals
-        float pad = 2e-5f * fmaxf(fabsf(zmax), 1.0f);
-        cz[c] = make_float2(fmaxf(zmin - pad, 0.f), zmax + pad);
-        ctile[c] = tile;
-        atomicAdd(tile_count + tile, 1u);
-    } else {
-        ctile[c] = 0xFFFFFFFFu;
+        for (int o = 32; o > 0; o >>= 1) {
+            zmin = fminf(zmin, __shfl_xor(zmin, o));
+            zmax = fmaxf(zmax, __shfl_xor(zmax, o));
+        }
+        if (lane == 0) {
+            const uint32_t c = c0 + l;
+            const uint32_t tile = uint32_t(ty * tiles_x + tx);
+            if (zmin <= zmax) {
+                // conservative padding for FP32 rounding of the intervals
+                float pad = 2e-5f * fmaxf(fabsf(zmax), 1.0f);
+                cz[c] = make_float2(fmaxf(zmin - pad, 0.f), zmax + pad);
+                ctile[c] = tile;
+                atomicAdd(tile_count + tile, 1u);
+            } else {
+                ctile[c] = 0xFFFFFFFFu;
+            }
+        }
     }
 }
 
@@ -607,8 +605,8 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
     ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
     if (n_cand)
-        hipLaunchKernelGGL(test_kernel, dim3((n_cand + 3) / 4), dim3(256), 0, stream, s->d_voi, rect, coff, P,
-                           n_cand, s->dcam, ts, s->tiles_x, cz, ctile, tcnt);
+        hipLaunchKernelGGL(test_kernel, dim3(P), dim3(256), 0, stream, s->d_voi, rect, coff, P, s->dcam, ts,
+                           s->tiles_x, cz, ctile, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_ent = replay ? uint32_t(s->n_entries) : 0u;
     if (!replay) {

@@ -343,20 +343,25 @@ __device__ PruneResult build_view(const TraceArgs& A, Mem& S, int buf, int n) {
     const uint32_t* act = S.act(buf);
     const int lane = lane_id();
     int m;
-    if (n >= 2) {
-        // two rounds: the second catches primitives whose only partners were
-        // dropped in the first (the inactive buffers of the active set serve
-        // as scratch)
-        uint32_t* t0 = S.act(buf ^ 1);
-        uint32_t* t1 = reinterpret_cast<uint32_t*>(S.ze(buf ^ 1));
-        int n1 = drop_dead(act, S.olo(buf), S.ohi(buf), n, t0, S.olo(buf ^ 1), S.ohi(buf ^ 1));
-        act = t0;
-        if (n1 >= 2 && n1 < n) {
-            int n2 = drop_dead(t0, S.olo(buf ^ 1), S.ohi(buf ^ 1), n1, t1, nullptr, nullptr);
-            act = t1;
-            n1 = n2;
+    {
+        // rounds until nothing more drops: a primitive whose only partners
+        // were dropped goes in the next round (the inactive buffers of the
+        // active set and the not yet used vs array serve as scratch)
+        const uint32_t* plo = S.olo(buf);
+        const uint32_t* phi = S.ohi(buf);
+        uint32_t* bx[2] = {S.act(buf ^ 1), reinterpret_cast<uint32_t*>(S.ze(buf ^ 1))};
+        uint32_t* blo[2] = {S.olo(buf ^ 1), S.vs()};
+        uint32_t* bhi[2] = {S.ohi(buf ^ 1), S.vs() + S.cap()};
+        for (int round = 0; round < 8 && n > 0; round++) {
+            const int t = round & 1;
+            const int kept = drop_dead(act, plo, phi, n, bx[t], blo[t], bhi[t]);
+            act = bx[t];
+            plo = blo[t];
+            phi = bhi[t];
+            const bool changed = kept < n;
+            n = kept;
+            if (!changed) break;
         }
-        n = n1;
         if (n == 0) {
             PruneResult r;
             r.len = 0;
@@ -594,34 +599,46 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             zin_ok = k < 64;
             if (k < 64) zin_i = rdlanef(zb, k);   // +inf past the end of the list
             if (k == 0) break;
-            // merge the k new primitives (lanes 0..k-1) into the sorted active list
-            // (cross-lane reads stay outside the divergent stores)
+            // merge the k new primitives (lanes 0..k-1) into the sorted active
+            // list: insertion point of each new one in the old list, its rank
+            // among the new ones, and for each old element the number of new
+            // ones inserted at or before it (histogram of insertion points,
+            // then a prefix sum).  Cross-lane reads stay in converged code.
             int nb = buf ^ 1;
+            const int ins = lane < k ? lower_count(S.act(buf), n, nd) : n;
+            int rk = 0;
+            for (int q = 0; q < k; q++) rk += rdlane(nd, q) < nd ? 1 : 0;
+            uint32_t* hist = S.lca();   // n + 1 <= capacity words of scratch
+            for (int b = lane; b <= n; b += 64) hist[b] = 0u;
+            wave_sync();
+            if (lane < k) atomicAdd(hist + ins, 1u);
+            wave_sync();
+            uint32_t carry = 0u;
             for (int b = 0; b < n; b += 64) {
                 int s = b + lane;
                 bool in_s = s < n;
-                uint32_t a = in_s ? S.act(buf)[s] : 0xFFFFFFFFu;
+                uint32_t a = in_s ? S.act(buf)[s] : 0u;
                 float az = in_s ? S.ze(buf)[s] : 0.f;
                 uint32_t alo = in_s ? S.olo(buf)[s] : 0u, ahi = in_s ? S.ohi(buf)[s] : 0u;
-                int less = 0;
-                for (int q = 0; q < k; q++) less += rdlane(nd, q) < a ? 1 : 0;
+                uint32_t h = in_s ? hist[s] : 0u;
+                for (int o = 1; o < 64; o <<= 1) {   // inclusive prefix sum over the chunk
+                    uint32_t y = __shfl_up(h, o);
+                    if (lane >= o) h += y;
+                }
+                const uint32_t shift = carry + h;
+                carry = rdlane(shift, 63);
                 if (in_s) {
-                    S.act(nb)[s + less] = a;
-                    S.ze(nb)[s + less] = az;
-                    S.olo(nb)[s + less] = alo;
-                    S.ohi(nb)[s + less] = ahi;
+                    S.act(nb)[s + int(shift)] = a;
+                    S.ze(nb)[s + int(shift)] = az;
+                    S.olo(nb)[s + int(shift)] = alo;
+                    S.ohi(nb)[s + int(shift)] = ahi;
                 }
             }
-            {
-                int pos = lower_count(S.act(buf), n, nd);
-                int less = 0;
-                for (int q = 0; q < k; q++) less += rdlane(nd, q) < nd ? 1 : 0;
-                if (lane < k) {
-                    S.act(nb)[pos + less] = nd;
-                    S.ze(nb)[pos + less] = zo;
-                    S.olo(nb)[pos + less] = nlo;
-                    S.ohi(nb)[pos + less] = nhi;
-                }
+            if (lane < k) {
+                S.act(nb)[ins + rk] = nd;
+                S.ze(nb)[ins + rk] = zo;
+                S.olo(nb)[ins + rk] = nlo;
+                S.ohi(nb)[ins + rk] = nhi;
             }
             // the new ones also extend the reach
             float nz_ = lane < k ? zo : -__builtin_inff();
