@@ -284,13 +284,13 @@ st_status st_mlp_pack(const float *weights, const float *norm, uint32_t *table, 
  * ST_E_DEVICE. */
 st_status st_mlp_forward(const uint32_t *table, const float *x, int32_t n, float *omega, void *stream);
 
-/* Loss sum_i w_i (omega_i - target_i)^2 / n with w_i = 4 where omega_i >
- * target_i (an over-long proposal costs a rejected evaluation), and its
- * gradient with respect to weights (the binary16 roundings of the forward
- * pass are passed through).  grad[ST_MLP_PARAMS] and loss[1] are
- * overwritten.  Errors: ST_E_INVALID, ST_E_DEVICE. */
+/* Loss sum_i w_i (omega_i - target_i)^2 / n with w_i = over_weight (> 0)
+ * where omega_i > target_i (an over-long proposal costs a rejected
+ * evaluation), else 1, and its gradient with respect to weights (the binary16
+ * roundings of the forward pass are passed through).  grad[ST_MLP_PARAMS] and
+ * loss[1] are overwritten.  Errors: ST_E_INVALID, ST_E_DEVICE. */
 st_status st_mlp_grad(const float *weights, const float *norm, const float *x, const float *target, int32_t n,
-                      float *grad, float *loss, void *stream);
+                      float over_weight, float *grad, float *loss, void *stream);
 
 /* One Adam update of w[n] with moments m[n], v[n] (updated in place), bias
  * corrections for update number step >= 1.  Errors: ST_E_INVALID, ST_E_DEVICE. */

@@ -70,7 +70,7 @@ def lib():
         L.or_round_half.restype = C.c_double
         L.or_round_half.argtypes = [C.c_double]
         L.or_mlp.restype = C.c_double
-        L.or_mlp.argtypes = [_dp, _dp, _dp, C.c_int, C.c_double, C.c_int, C.c_void_p, C.c_void_p]
+        L.or_mlp.argtypes = [_dp, _dp, _dp, C.c_int, C.c_double, C.c_int, C.c_double, C.c_void_p, C.c_void_p]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -189,7 +189,7 @@ def round_half(x):
     return np.vectorize(f, otypes=[np.float64])(np.asarray(x, dtype=np.float64))
 
 
-def mlp(weights, X, T, omega_max: float = 4.0, grad: bool = True, exact: bool = False):
+def mlp(weights, X, T, omega_max: float = 4.0, grad: bool = True, exact: bool = False, over_weight: float = 4.0):
     """FP64 step-predictor MLP: returns (loss, omega[B], grad[1377] or None).
     exact=True skips the internal binary16 roundings."""
     W = np.ascontiguousarray(weights, dtype=np.float64)
@@ -198,7 +198,8 @@ def mlp(weights, X, T, omega_max: float = 4.0, grad: bool = True, exact: bool = 
     B = X.shape[0]
     om = np.empty(B)
     g = np.empty(1377) if grad else None
-    loss = lib().or_mlp(W, X.ravel(), T, B, float(omega_max), int(bool(exact)), om.ctypes.data_as(C.c_void_p),
+    loss = lib().or_mlp(W, X.ravel(), T, B, float(omega_max), int(bool(exact)), float(over_weight),
+                        om.ctypes.data_as(C.c_void_p),
                         g.ctypes.data_as(C.c_void_p) if grad else None)
     return loss, om, g
 

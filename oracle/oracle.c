@@ -706,7 +706,8 @@ double or_prim(const or_scene *s, int i, const double x[3]) {
 /* ------------------------------------------------------------------------ */
 /* Step-predictor MLP (not part of the paper): 8 -> 32 -> 32 -> 1 with ReLU,
  * output omega = 1 + (omega_max - 1) * sigmoid(z), loss
- * mean_i w_i (omega_i - target_i)^2 with w_i = 4 when omega_i > target_i
+ * mean_i w_i (omega_i - target_i)^2 with w_i = over_weight (4 by default) when
+ * omega_i > target_i
  * (overshooting costs a rejected step), else 1.
  * Rounding points follow the GPU kernels: inputs and weights arrive already
  * rounded to binary16; the hidden activations are rounded to binary16 before
@@ -740,7 +741,7 @@ static double relu(double x) { return x > 0 ? x : 0; }
  * out_omega: B (may be NULL), out_grad: 1377 (may be NULL).
  * Returns the loss. */
 double or_mlp(const double *Wt, const double *X, const double *T, int B, double omega_max,
-              int exact, double *out_omega, double *out_grad) {
+              int exact, double over_weight, double *out_omega, double *out_grad) {
     const double *W1 = Wt, *b1 = Wt + 256, *W2 = Wt + 288, *b2 = Wt + 1312, *w3 = Wt + 1344,
                  *b3 = Wt + 1376;
     double loss = 0;
@@ -763,7 +764,7 @@ double or_mlp(const double *Wt, const double *X, const double *T, int B, double 
         double sg = 1.0 / (1.0 + exp(-z));
         double om = 1.0 + (omega_max - 1.0) * sg;
         if (out_omega) out_omega[s] = om;
-        double wgt = om > T[s] ? 4.0 : 1.0;
+        double wgt = om > T[s] ? over_weight : 1.0;
         double diff = om - T[s];
         loss += wgt * diff * diff / B;
         if (!out_grad) continue;

@@ -59,14 +59,15 @@ __global__ void mfma_probe_kernel(const float* __restrict__ A, const float* __re
 }
 
 // ---------------------------------------------------------------------------
-// training: loss mean_i w_i (omega_i - target_i)^2, w_i = 4 when omega_i > target_i.
+// training: loss mean_i w_i (omega_i - target_i)^2, w_i = over_weight when omega_i > target_i.
 // One thread per sample; forward and backward in FP32 with the inference's
 // binary16 rounding points (inputs, weights, hidden activations; error signals
 // that feed a product); gradients summed per block in LDS, then one global
 // atomic per parameter per block.
 __global__ void __launch_bounds__(256) mlp_grad_kernel(const float* __restrict__ wm, const float* __restrict__ norm,
                                                        const float* __restrict__ x, const float* __restrict__ tgt, int n,
-                                                       float* __restrict__ grad, float* __restrict__ loss) {
+                                                       float over_weight, float* __restrict__ grad,
+                                                       float* __restrict__ loss) {
     __shared__ float W[kMlpParams];
     __shared__ float G[kMlpParams];
     __shared__ float L;
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const float* __restrict__
         float sg = 1.0f / (1.0f + expf(-z));
         float om = 1.0f + (kOmegaMax - 1.0f) * sg;
         float diff = om - tgt[s];
-        float wgt = om > tgt[s] ? 4.0f : 1.0f;
+        float wgt = om > tgt[s] ? over_weight : 1.0f;
         atomicAdd(&L, wgt * diff * diff * inv_n);
         float dz = 2.0f * wgt * diff * inv_n * (kOmegaMax - 1.0f) * sg * (1.0f - sg);
         atomicAdd(&G[kMlpB3], dz);
@@ -165,9 +166,9 @@ st_status st_mlp_forward(const uint32_t* tab, const float* x, int32_t n, float* 
     return e == hipSuccess ? ST_OK : device_error(e, "mlp_forward_kernel");
 }
 
-st_status st_mlp_grad(const float* w, const float* norm, const float* x, const float* target, int32_t n, float* grad,
-                      float* loss, void* stream) {
-    if (!w || !norm || !grad || !loss || n < 0 || (n > 0 && (!x || !target))) {
+st_status st_mlp_grad(const float* w, const float* norm, const float* x, const float* target, int32_t n,
+                      float over_weight, float* grad, float* loss, void* stream) {
+    if (!w || !norm || !grad || !loss || n < 0 || (n > 0 && (!x || !target)) || !(over_weight > 0.f)) {
         set_error("mlp_grad: bad argument");
         return ST_E_INVALID;
     }
@@ -176,7 +177,8 @@ st_status st_mlp_grad(const float* w, const float* norm, const float* x, const f
     if (e == hipSuccess) e = hipMemsetAsync(loss, 0, 4, st);
     if (e != hipSuccess) return device_error(e, "mlp_grad memset");
     if (n == 0) return ST_OK;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w, norm, x, target, n, grad, loss);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w, norm, x, target, n, over_weight,
+                       grad, loss);
     e = hipGetLastError();
     return e == hipSuccess ? ST_OK : device_error(e, "mlp_grad_kernel");
 }

@@ -110,7 +110,7 @@ def lib():
         L.st_debug_abuffer.argtypes = [vp, vp, sz, vp, sz, C.POINTER(i32), C.POINTER(i64), vp]
         L.st_mlp_pack.argtypes = [vp, vp, vp, vp]
         L.st_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
-        L.st_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+        L.st_mlp_grad.argtypes = [vp, vp, vp, vp, i32, C.c_float, vp, vp, vp]
         L.st_mlp_adam.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.st_set_step_model.argtypes = [vp, vp, vp, vp]
         L.st_trace_dump.argtypes = [vp, C.POINTER(StCamera), vp, vp, vp, vp, i64, C.POINTER(i64), vp]
@@ -347,7 +347,7 @@ def mlp_forward(table, x, out=None, stream=None):
     return out
 
 
-def mlp_grad(weights, norm, x, target, grad=None, loss=None, stream=None):
+def mlp_grad(weights, norm, x, target, grad=None, loss=None, over_weight=4.0, stream=None):
     """st_mlp_grad -> (grad [1377], loss [1]) CUDA tensors."""
     import torch
     n = target.numel()
@@ -359,7 +359,7 @@ def mlp_grad(weights, norm, x, target, grad=None, loss=None, stream=None):
         grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
     if loss is None:
         loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    _check(lib().st_mlp_grad(_ptr(weights), _ptr(norm), _ptr(x), _ptr(target), n, _ptr(grad), _ptr(loss),
+    _check(lib().st_mlp_grad(_ptr(weights), _ptr(norm), _ptr(x), _ptr(target), n, float(over_weight), _ptr(grad), _ptr(loss),
                              _stream_ptr(stream)))
     return grad, loss
 

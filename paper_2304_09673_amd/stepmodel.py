@@ -51,7 +51,8 @@ def standardisation(X: np.ndarray) -> np.ndarray:
     return np.concatenate([mu, 1.0 / sd]).astype(np.float32)
 
 
-def fit(X, T, epochs: int = 8, batch: int = 8192, lr: float = 3e-3, seed: int = 0, log=None):
+def fit(X, T, epochs: int = 8, batch: int = 8192, lr: float = 3e-3, seed: int = 0, log=None,
+        over_weight: float = 4.0):
     """Adam on the weighted squared error; returns (weights [1377], norm [16], losses per epoch)."""
     import torch
     rng = np.random.default_rng(seed)
@@ -72,7 +73,7 @@ def fit(X, T, epochs: int = 8, batch: int = 8192, lr: float = 3e-3, seed: int = 
         acc = torch.zeros(1, dtype=torch.float64)
         for b in range(nb):
             lo, hi = b * batch, min(n, (b + 1) * batch)
-            st.mlp_grad(w, norm, Xd[lo:hi], Td[lo:hi], grad=grad, loss=loss)
+            st.mlp_grad(w, norm, Xd[lo:hi], Td[lo:hi], grad=grad, loss=loss, over_weight=over_weight)
             step += 1
             st.mlp_adam(w, m, v, grad, step, lr=lr)
             acc += loss.cpu().double() if b % 16 == 0 else 0.0

@@ -75,16 +75,16 @@ def test_forward_matches_oracle(n):
     assert np.max(np.abs(om - om_ref)) <= 1e-2
 
 
-@pytest.mark.parametrize("n", [256, 5000])
-def test_gradients_match_oracle(n):
+@pytest.mark.parametrize("n,over", [(256, 4.0), (5000, 4.0), (5000, 16.0)])
+def test_gradients_match_oracle(n, over):
     import torch
     st = _st()
     w, norm, x, t = _random_problem(101 + n, n)
     g, loss = st.mlp_grad(torch.as_tensor(w).cuda(), torch.as_tensor(norm).cuda(), torch.as_tensor(x).cuda(),
-                          torch.as_tensor(t).cuda())
+                          torch.as_tensor(t).cuda(), over_weight=over)
     g = g.cpu().numpy().astype(np.float64)
     wr, xr = _oracle_inputs(w, norm, x)
-    loss_ref, _, g_ref = oracle.mlp(wr, xr, t.astype(np.float64), grad=True)
+    loss_ref, _, g_ref = oracle.mlp(wr, xr, t.astype(np.float64), grad=True, over_weight=over)
     assert abs(float(loss.cpu()) - loss_ref) <= 1e-4 * abs(loss_ref)
     for name, off, size in TENSORS:
         e = _rel_l2(g[off:off + size], g_ref[off:off + size])

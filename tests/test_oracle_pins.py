@@ -495,14 +495,15 @@ def test_mlp_backward_matches_finite_differences():
     W = rng.normal(scale=0.4, size=1377)
     X = rng.normal(size=(16, 8))
     T = rng.uniform(1, 4, size=16)
-    loss, om, g = oracle.mlp(W, X, T, exact=True)
-    assert om.min() >= 1 and om.max() <= 4
-    for j in rng.choice(1377, 400, replace=False):
-        e = np.zeros(1377)
-        e[j] = 1e-6
-        fd = (oracle.mlp(W + e, X, T, grad=False, exact=True)[0]
-              - oracle.mlp(W - e, X, T, grad=False, exact=True)[0]) / 2e-6
-        assert abs(fd - g[j]) <= 1e-7 * max(1.0, abs(g[j])), j
+    for over in (4.0, 16.0):
+        loss, om, g = oracle.mlp(W, X, T, exact=True, over_weight=over)
+        assert om.min() >= 1 and om.max() <= 4
+        for j in rng.choice(1377, 200, replace=False):
+            e = np.zeros(1377)
+            e[j] = 1e-6
+            fd = (oracle.mlp(W + e, X, T, grad=False, exact=True, over_weight=over)[0]
+                  - oracle.mlp(W - e, X, T, grad=False, exact=True, over_weight=over)[0]) / 2e-6
+            assert abs(fd - g[j]) <= 1e-7 * max(1.0, abs(g[j])), (over, j)
 
 
 def test_mlp_rounding_points_are_small_perturbations():
@@ -525,3 +526,6 @@ def test_mlp_forward_hand_example():
     assert np.allclose(om, 2.5)
     # loss = mean(w (omega - t)^2): (0 + 4 * 0.25 + 1 * 0.25) / 3
     assert loss == pytest.approx((0 + 4 * 0.25 + 0.25) / 3, rel=1e-15)
+    # the over-prediction weight scales only the terms with omega > t
+    loss16, _, _ = oracle.mlp(W, np.ones((3, 8)), np.array([2.5, 2.0, 3.0]), over_weight=16.0)
+    assert loss16 == pytest.approx((0 + 16 * 0.25 + 0.25) / 3, rel=1e-15)
