@@ -538,6 +538,11 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
     // (saves a dependent global load per turn)
     float zin_i = 0.f;
     bool zin_ok = false;
+    // the next fetch window (entries pf_i + lane), loaded at the end of the
+    // previous turn's fetch so that its latency overlaps the view build and
+    // the stepping
+    uint32_t pf_i = 0xFFFFFFFFu, pf_nd = 0u, pf_lo = 0u, pf_hi = 0u;
+    float pf_zb = 0.f, pf_zo = 0.f;
 
     while (true) {
         if (ballot(!done) == 0) break;
@@ -546,31 +551,35 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             if (lane == 0) atomicAdd(cnt + S_STALL, 1ull);
             break;
         }
-        // -- drop exited primitives (z_e <= z_end), compact in place
+        // -- drop exited primitives (z_e <= z_end), compact in place; the
+        //    remaining ones give the largest exit depth mz.  Elements move only
+        //    once something before them has been dropped.
+        float mz;
         {
             int kept = 0;
+            float mzl = -__builtin_inff();
             for (int b = 0; b < n; b += 64) {
                 int s = b + lane;
                 bool in = s < n;
-                uint32_t a = in ? S.act(buf)[s] : 0u;
                 float z = in ? S.ze(buf)[s] : 0.f;
-                uint32_t plo = in ? S.olo(buf)[s] : 0u, phi = in ? S.ohi(buf)[s] : 0u;
                 bool keep = in && z > z_end;
-                uint64_t mk = ballot(keep);
-                int dst = kept + int(lanes_below(mk));
-                wave_sync();
-                if (keep) { S.act(buf)[dst] = a; S.ze(buf)[dst] = z; S.olo(buf)[dst] = plo; S.ohi(buf)[dst] = phi; }
+                if (keep) mzl = fmaxf(mzl, z);
+                const uint64_t mk = ballot(keep);
+                if (mk != ballot(in) || kept != b) {
+                    uint32_t a = in ? S.act(buf)[s] : 0u;
+                    uint32_t plo = in ? S.olo(buf)[s] : 0u, phi = in ? S.ohi(buf)[s] : 0u;
+                    int dst = kept + int(lanes_below(mk));
+                    wave_sync();
+                    if (keep) { S.act(buf)[dst] = a; S.ze(buf)[dst] = z; S.olo(buf)[dst] = plo; S.ohi(buf)[dst] = phi; }
+                }
                 kept += __popcll(mk);
             }
             n = kept;
+            mz = wave_max(mzl);
             wave_sync();
         }
         if (i >= e1 && n == 0) break;
         const float z_begin = n > 0 ? z_end : (zin_ok ? zin_i : unif(A.e_zin[i]));
-        // max exit depth of the remaining active set
-        float mz = -__builtin_inff();
-        for (int s = lane; s < n; s += 64) mz = fmaxf(mz, S.ze(buf)[s]);
-        mz = wave_max(mz);
         // -- fetch new primitives, up to 64 per round (lane c considers list
         //    entry i + c), rounds until max_new, a gap, the depth limit or
         //    the capacity stops it
@@ -578,10 +587,17 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         while (i < e1 && fetched < A.max_new) {
             uint32_t c = uint32_t(lane);
             bool in = i + c < e1;
-            float zb = in ? A.e_zin[i + c] : __builtin_inff();
-            float zo = in ? A.e_zout[i + c] : -__builtin_inff();
-            uint32_t nd = in ? A.e_node[i + c] : 0u;
-            const uint32_t nlo = in ? A.e_lo[i + c] : 0u, nhi = in ? A.e_hi[i + c] : 0u;
+            float zb, zo;
+            uint32_t nd, nlo, nhi;
+            if (pf_i == i) {
+                zb = pf_zb; zo = pf_zo; nd = pf_nd; nlo = pf_lo; nhi = pf_hi;
+            } else {
+                zb = in ? A.e_zin[i + c] : __builtin_inff();
+                zo = in ? A.e_zout[i + c] : -__builtin_inff();
+                nd = in ? A.e_node[i + c] : 0u;
+                nlo = in ? A.e_lo[i + c] : 0u;
+                nhi = in ? A.e_hi[i + c] : 0u;
+            }
             // exclusive prefix max of exit depths of earlier candidates
             float pm = zo;
             for (int o = 1; o < 64; o <<= 1) {
@@ -657,6 +673,16 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         const float z_next = zin_ok ? zin_i : unif(A.e_zin[i]);
         zin_i = z_next;
         zin_ok = true;
+        if (i < e1 && pf_i != i) {
+            const uint32_t c = uint32_t(lane);
+            const bool in = i + c < e1;
+            pf_zb = in ? A.e_zin[i + c] : __builtin_inff();
+            pf_zo = in ? A.e_zout[i + c] : -__builtin_inff();
+            pf_nd = in ? A.e_node[i + c] : 0u;
+            pf_lo = in ? A.e_lo[i + c] : 0u;
+            pf_hi = in ? A.e_hi[i + c] : 0u;
+            pf_i = i;
+        }
         z_end = fminf(z_next, mz);
         max_act = max(max_act, uint32_t(n));
         if (!(z_end > z_begin)) continue;
