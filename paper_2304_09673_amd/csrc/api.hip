@@ -38,6 +38,7 @@ void dev_free(st_scene* s, void* p, hipStream_t stream) {
 static void free_abuffer(st_scene* s, hipStream_t stream) {
     dev_free(s, s->d_tile_off, stream); s->d_tile_off = nullptr;
     dev_free(s, s->d_tile_ovl, stream); s->d_tile_ovl = nullptr;
+    dev_free(s, s->d_tile_order, stream); s->d_tile_order = nullptr;
     dev_free(s, s->d_e_node, stream); s->d_e_node = nullptr;
     dev_free(s, s->d_e_zin, stream); s->d_e_zin = nullptr;
     dev_free(s, s->d_e_zout, stream); s->d_e_zout = nullptr;
@@ -306,10 +307,14 @@ st_status st_build_abuffer(st_scene* s, const st_camera* cam, const st_tuning* t
     if (T != s->n_tiles || !s->d_tile_off) {
         dev_free(s, s->d_tile_off, stream);
         dev_free(s, s->d_tile_ovl, stream);
+        dev_free(s, s->d_tile_order, stream);
         s->d_tile_off = (uint32_t*)dev_alloc(s, size_t(T + 1) * 4, stream);
         s->d_tile_ovl = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
-        if (!s->d_wide) s->d_wide = nullptr;
-        if (!s->d_tile_off || !s->d_tile_ovl) { set_error("build: tile arrays allocation failed"); return ST_E_NOMEM; }
+        s->d_tile_order = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
+        if (!s->d_tile_off || !s->d_tile_ovl || !s->d_tile_order) {
+            set_error("build: tile arrays allocation failed");
+            return ST_E_NOMEM;
+        }
     }
     dev_free(s, s->d_wide, stream);
     s->d_wide = (uint32_t*)dev_alloc(s, size_t(T + 1) * 4, stream);

@@ -516,6 +516,47 @@ __global__ void __launch_bounds__(kSortThreads) tile_sort_long_kernel(
     }
 }
 
+// Dispatch order of the tiles: decreasing A-buffer list length.  The work of
+// a tile's blocks grows with the number of depth intervals its rays cross,
+// and a frame is set by its slowest blocks, so the heavy tiles are started
+// first and the light ones fill the machine behind them.  One workgroup,
+// counting sort over kOrderBuckets length buckets (lengths beyond the last
+// bucket share it); the order within a bucket is whatever the LDS atomics
+// give, which changes only the schedule, not any result.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 4 * kOrderThreads;
+
+__global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_t* __restrict__ tile_off,
+                                                                    int n_tiles, uint32_t* __restrict__ order) {
+    __shared__ uint32_t cnt[kOrderBuckets];
+    __shared__ uint32_t part[kOrderThreads];
+    const int tid = int(threadIdx.x);
+    auto bucket = [&](int t) {   // longest first
+        uint32_t len = tile_off[t + 1] - tile_off[t];
+        return uint32_t(kOrderBuckets - 1) - min(len, uint32_t(kOrderBuckets - 1));
+    };
+    for (int b = tid; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
+    __syncthreads();
+    for (int t = tid; t < n_tiles; t += kOrderThreads) atomicAdd(&cnt[bucket(t)], 1u);
+    __syncthreads();
+    // exclusive scan: four buckets per thread, then an inclusive scan of the
+    // per-thread sums
+    uint32_t c[4], sum = 0;
+    for (int j = 0; j < 4; j++) { c[j] = cnt[4 * tid + j]; sum += c[j]; }
+    part[tid] = sum;
+    __syncthreads();
+    for (int d = 1; d < kOrderThreads; d <<= 1) {
+        uint32_t v = tid >= d ? part[tid - d] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - sum;
+    for (int j = 0; j < 4; j++) { cnt[4 * tid + j] = run; run += c[j]; }
+    __syncthreads();
+    for (int t = tid; t < n_tiles; t += kOrderThreads) order[atomicAdd(&cnt[bucket(t)], 1u)] = uint32_t(t);
+}
+
 // ---------------------------------------------------------------------------
 st_status launch_voi(st_scene* s, hipStream_t stream) {
     int P = s->n_prims;
@@ -657,6 +698,8 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipLaunchKernelGGL(tile_sort_long_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream,
                        s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, sk, sv, sz,
                        uint32_t(s->ab_ma_fast), s->d_wide);
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_off, T,
+                       s->d_tile_order);
     if (n_ent)
         hipLaunchKernelGGL(entry_range_kernel, dim3((n_ent + 255) / 256), dim3(256), 0, stream, s->d_e_node, n_ent,
                            s->d_kill, reinterpret_cast<const uint2*>(s->d_range), uint32_t(s->n_nodes), s->d_e_lo,

@@ -46,6 +46,7 @@ struct st_scene {
     float z_min = 0.f, z_max = 0.f;   // view-depth span of the VOI box
     uint32_t* d_tile_off = nullptr;   // n_tiles + 1
     uint32_t* d_tile_ovl = nullptr;   // per tile max depth overlap
+    uint32_t* d_tile_order = nullptr; // tiles by decreasing list length (dispatch order)
     uint32_t* d_e_node = nullptr;     // entries, SoA, sorted per tile
     float* d_e_zin = nullptr;
     float* d_e_zout = nullptr;

@@ -93,6 +93,7 @@ struct TraceArgs {
     const float* e_zin;
     const float* e_zout;
     const uint32_t* tile_ovl;
+    const uint32_t* tile_order;   // dispatch order of the tiles (fast path)
     const uint32_t* wide;      // [0] count, [1..] tiles
     DevCam cam;
     int ts, tiles_x, tiles_y, sub_x;   // sub_x = ts / 8

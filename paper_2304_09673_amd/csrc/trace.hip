@@ -20,16 +20,13 @@ __global__ void __launch_bounds__(256) trace_fast_kernel(TraceArgs A, uint32_t n
         __syncthreads();
         tab = mlp_tab;
     }
-    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
-    // so workgroup g runs on XCD g % 8; give each XCD a contiguous range of
-    // jobs (neighbouring tiles share primitives and their L2 lines).
-    uint32_t nwg = gridDim.x, g = blockIdx.x;
-    uint32_t x = g % 8u, idx = g / 8u, q = nwg / 8u, r = nwg % 8u;
-    uint32_t gg = x * q + min(x, r) + idx;
-    uint32_t job = gg * 4 + uint32_t(w);
+    // Workgroups are dispatched in index order, round-robin over the 8 XCDs:
+    // job k is a block of the k-th tile of the longest-first order, so the
+    // heaviest tiles start first and spread evenly over the XCDs.
+    uint32_t job = blockIdx.x * 4u + uint32_t(w);
     if (job >= n_jobs) return;
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
-    uint32_t tile = job / spt, sub = job % spt;
+    uint32_t tile = A.tile_order[job / spt], sub = job % spt;
     if (A.tile_ovl[tile] > A.ma_fast) return;   // wide path
     trace_block<WaveLds<MA>, KS, SM>(A, lds[w], tile, sub, A.stats, tab);
 }
@@ -94,6 +91,7 @@ void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float*
     A.e_zin = s->d_e_zin;
     A.e_zout = s->d_e_zout;
     A.tile_ovl = s->d_tile_ovl;
+    A.tile_order = s->d_tile_order;
     A.wide = s->d_wide;
     A.cam = s->dcam;
     A.ts = t.tile;

@@ -90,6 +90,11 @@ def lib():
         if not LIB_PATH.exists():
             raise ImportError(f"{LIB_PATH} is not built; run paper_2304_09673_amd/build.py "
                               "(there is no CPU fallback)")
+        # torch first: its HIP runtime is then the one the library binds to
+        # (same soname).  Loaded the other way round, the process would hold
+        # two HIP runtimes, and torch's streams and buffers would be foreign
+        # to the library's.
+        import torch  # noqa: F401
         L = C.CDLL(str(LIB_PATH))
         vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
         L.st_status_str.restype = C.c_char_p

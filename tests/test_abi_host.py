@@ -1,6 +1,7 @@
 """CPU-side checks of the C ABI library: it loads without a GPU, exports every
 function include/st.h declares, and its host logic (flatten validation, the
 pruned tree view) follows the paper's rules."""
+import ast
 import ctypes as C
 import itertools
 import re
@@ -29,6 +30,20 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
         assert n in st.EXPORTS, n
     assert set(st.EXPORTS) == set(names)
+
+
+def test_binding_loads_one_hip_runtime():
+    """Loading the library through the binding in a fresh process maps a
+    single HIP runtime (torch's): the library binds to the runtime torch
+    already loaded instead of bringing a second one."""
+    import subprocess
+    import sys
+    code = ("from paper_2304_09673_amd import st; st.lib(); "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=str(Path(__file__).resolve().parents[1]), check=True).stdout
+    paths = ast.literal_eval(out.strip().splitlines()[-1])
+    assert len(paths) == 1, paths
 
 
 def test_status_strings_and_default_tuning():
