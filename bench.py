@@ -344,6 +344,7 @@ def main():
         "hits": stats["hits"],
         "unconverged": stats["unconverged"],
         "abuffer_entries": stats["abuffer_entries"],
+        "abuffer_binned": stats["abuffer_binned"],
         "max_overlap": stats["max_overlap"],
         "max_active": stats["max_active"],
         "subfrustums": stats["subfrustums"],
@@ -357,10 +358,13 @@ def main():
     }
     # binning (HBM-bound by design): algorithmic bytes = VOI reads (2 passes,
     # 48 B/primitive each), tile count/scan/offsets (12 B/tile), scatter write
-    # (12 B/entry), per-tile sort read + write (24 B/entry)
+    # (12 B per binned entry), tile pruning read (12 B per binned entry) and
+    # write (12 B per kept entry), per-tile sort read + write (24 B per kept
+    # entry)
     n_tiles = -(-cam.width // tune.tile) * -(-cam.height // tune.tile)
     e = stats["abuffer_entries"]
-    bin_bytes = 96 * sc.n_prims + 12 * n_tiles + 36 * e
+    eb = stats["abuffer_binned"]
+    bin_bytes = 96 * sc.n_prims + 12 * n_tiles + 24 * eb + 36 * e
     line["binning"] = {"bound": "hbm", "algorithmic_bytes": bin_bytes, "ms_wall": round(build_ms, 4),
                        "achieved_GBps": bin_bytes / (build_ms * 1e-3) / 1e9,
                        "frac": bin_bytes / (build_ms * 1e-3) / 8e12,

@@ -107,7 +107,12 @@ typedef struct {
                               [1, 4] (paper: 1.7) */
     float lipschitz;       /* 0: proven bound of each pruned view; > 0: this
                               fixed global bound (paper: 1.45, not proven) */
-    int32_t reserved[6];
+    int32_t keep_all_entries; /* 0 (default): drop, at binning, the entries
+                              of primitives that cannot reach the root for any
+                              subset of their tile's list (every subfrustum
+                              view stays the same; not in the paper);
+                              1: keep every entry */
+    int32_t reserved[5];
 } st_tuning;
 
 /* Counters of one st_trace call (all 64-bit). */
@@ -123,13 +128,15 @@ typedef struct {
     uint64_t subfrustums;     /* (wave, subfrustum) pairs processed */
     uint64_t empty_views;     /* subfrustums whose pruned root is unused (no surface) */
     uint64_t view_nodes;      /* sum of pruned-view sizes over subfrustums */
-    uint64_t abuffer_entries; /* A-buffer entries of the scene */
+    uint64_t abuffer_entries; /* A-buffer entries the tracer reads (kept by
+                                 the tile-level pruning) */
     uint64_t max_list;        /* longest tile list */
     uint64_t max_overlap;     /* largest depth overlap of volumes of interest in a tile */
     uint64_t max_active;      /* largest active set used by the tracer */
     uint64_t wide_tiles;      /* tiles traced on the wide-capacity path */
     uint64_t learned_accepted, learned_rejected;   /* relaxed steps (OVERRELAX, LEARNED) */
-    uint64_t reserved[8];
+    uint64_t abuffer_binned;  /* A-buffer entries before the tile-level pruning */
+    uint64_t reserved[7];
 } st_stats;
 
 /* Device memory allocator used for the scene's buffers (e.g. a framework's
@@ -409,11 +416,13 @@ st_status st_debug_prune_tree(const st_node *nodes, int32_t n, int32_t root, con
                               float *out_lip);
 
 /*
- * st_debug_abuffer -- test hook: copies the current A-buffer to host memory.
- *   tile_off (host, uint32[n_tiles+1]), entries (host, 3 x uint32 per entry:
- *   caller node index of the primitive, z_in bits, z_out bits), capacities in
- *   elements; *n_tiles and *n_entries receive the sizes.  Pass NULL arrays to
- *   query sizes.  Synchronous.
+ * st_debug_abuffer -- test hook: copies the current A-buffer, as the tracer
+ *   reads it (the entries kept by the tile-level pruning, each tile's list
+ *   sorted by entry depth), to host memory: tile_off (host,
+ *   uint32[n_tiles+1], offsets of the packed lists), entries (host, 3 x uint32
+ *   per entry: caller node index of the primitive, z_in bits, z_out bits),
+ *   capacities in elements; *n_tiles and *n_entries receive the sizes.  Pass
+ *   NULL arrays to query sizes.  Synchronous.
  */
 st_status st_debug_abuffer(const st_scene *s, uint32_t *tile_off, size_t tile_cap,
                            uint32_t *entries, size_t entry_cap, int32_t *n_tiles,

@@ -39,15 +39,16 @@ static void free_abuffer(st_scene* s, hipStream_t stream) {
     dev_free(s, s->d_tile_off, stream); s->d_tile_off = nullptr;
     dev_free(s, s->d_tile_ovl, stream); s->d_tile_ovl = nullptr;
     dev_free(s, s->d_tile_order, stream); s->d_tile_order = nullptr;
+    dev_free(s, s->d_tile_cnt, stream); s->d_tile_cnt = nullptr;
     dev_free(s, s->d_e_node, stream); s->d_e_node = nullptr;
     dev_free(s, s->d_e_zin, stream); s->d_e_zin = nullptr;
     dev_free(s, s->d_e_zout, stream); s->d_e_zout = nullptr;
-    dev_free(s, s->d_e_lo, stream); s->d_e_lo = nullptr;
-    dev_free(s, s->d_e_hi, stream); s->d_e_hi = nullptr;
     dev_free(s, s->d_wide, stream); s->d_wide = nullptr;
     dev_free(s, s->d_scratch, stream); s->d_scratch = nullptr;
     dev_free(s, s->d_slots, stream); s->d_slots = nullptr;
     s->slots_bytes = 0;
+    dev_free(s, s->d_wrec, stream); s->d_wrec = nullptr;
+    s->wrec_bytes = 0;
     s->scratch_bytes = 0;
     s->ab_cap = 0;
     s->n_tiles = 0;
@@ -109,7 +110,8 @@ void stats_from_counters(const st_scene* s, const unsigned long long* h, st_stat
     out->learned_rejected = h[20];
     out->reserved[0] = h[21];   // stalled blocks (must be 0)
     out->reserved[1] = h[22];   // compact operators evaluated on their smooth branch
-    out->abuffer_entries = uint64_t(s->n_entries);
+    out->abuffer_entries = uint64_t(s->n_live);
+    out->abuffer_binned = uint64_t(s->n_entries);
     out->max_list = s->max_list;
     out->max_overlap = s->max_overlap;
 }
@@ -124,6 +126,7 @@ static st_status check_tuning(const st_tuning& t) {
     if (t.step_mode < ST_STEP_PLAIN || t.step_mode > ST_STEP_LEARNED) { set_error("tuning: step_mode"); return ST_E_INVALID; }
     if (!(t.omega >= 1.f) || !(t.omega <= 4.f)) { set_error("tuning: omega outside [1, 4]"); return ST_E_INVALID; }
     if (!(t.lipschitz >= 0.f) || !std::isfinite(t.lipschitz)) { set_error("tuning: lipschitz < 0"); return ST_E_INVALID; }
+    if (t.keep_all_entries != 0 && t.keep_all_entries != 1) { set_error("tuning: keep_all_entries must be 0 or 1"); return ST_E_INVALID; }
     return ST_OK;
 }
 
@@ -188,7 +191,7 @@ st_status st_flatten_blobtree(const st_node* nodes, int32_t n, int32_t root, con
     struct { void** p; size_t bytes; const void* src; } bufs[] = {
         {(void**)&s->d_blob, N * 4, s->h_blob.data()},
         {(void**)&s->d_kill, N * 4, s->h_kill.data()},
-        {(void**)&s->d_range, N * 8, s->h_range.data()},
+        {(void**)&s->d_kslot, N * 32, s->h_kslot.data()},
         {(void**)&s->d_rmq, s->h_rmq.size() * 4, s->h_rmq.data()},
         {(void**)&s->d_prims, P * 4, s->h_prims.data()},
         {(void**)&s->d_par, N * sizeof(NodePar), s->h_par.data()},
@@ -220,7 +223,7 @@ void st_scene_destroy(st_scene* s) {
     free_abuffer(s, stream);
     dev_free(s, s->d_blob, stream);
     dev_free(s, s->d_kill, stream);
-    dev_free(s, s->d_range, stream);
+    dev_free(s, s->d_kslot, stream);
     dev_free(s, s->d_rmq, stream);
     dev_free(s, s->d_prims, stream);
     dev_free(s, s->d_par, stream);
@@ -308,10 +311,12 @@ st_status st_build_abuffer(st_scene* s, const st_camera* cam, const st_tuning* t
         dev_free(s, s->d_tile_off, stream);
         dev_free(s, s->d_tile_ovl, stream);
         dev_free(s, s->d_tile_order, stream);
+        dev_free(s, s->d_tile_cnt, stream);
         s->d_tile_off = (uint32_t*)dev_alloc(s, size_t(T + 1) * 4, stream);
         s->d_tile_ovl = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
         s->d_tile_order = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
-        if (!s->d_tile_off || !s->d_tile_ovl || !s->d_tile_order) {
+        s->d_tile_cnt = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
+        if (!s->d_tile_off || !s->d_tile_ovl || !s->d_tile_order || !s->d_tile_cnt) {
             set_error("build: tile arrays allocation failed");
             return ST_E_NOMEM;
         }
@@ -360,7 +365,7 @@ st_status st_trace_ex(st_scene* s, const st_camera* cam, float* out_depth, float
         set_error("trace: the A-buffer was not built for this camera");
         return ST_E_STALE;
     }
-    st_status r = trace_device(s, s->ab_tune, out_depth, out_normal, out_info, stream);
+    st_status r = trace_device(s, s->ab_tune, out_depth, out_normal, out_info, stream, nullptr, out_stats != nullptr);
     if (r != ST_OK) return r;
     if (out_stats) {
         unsigned long long h[kStatCount];
@@ -528,27 +533,33 @@ st_status st_debug_abuffer(const st_scene* s, uint32_t* tile_off, size_t tile_ca
     if (!s->ab_valid) { set_error("abuffer: not built"); return ST_E_STALE; }
     hipStream_t stream = (hipStream_t)stream_v;
     if (n_tiles) *n_tiles = s->n_tiles;
-    if (n_entries) *n_entries = s->n_entries;
-    hipError_t e = hipSuccess;
-    if (tile_off) {
-        if (tile_cap < size_t(s->n_tiles + 1)) { set_error("abuffer: tile capacity"); return ST_E_CAPACITY; }
-        e = hipMemcpyAsync(tile_off, s->d_tile_off, size_t(s->n_tiles + 1) * 4, hipMemcpyDeviceToHost, stream);
+    if (n_entries) *n_entries = s->n_live;
+    if (!tile_off && !entries) return ST_OK;
+    if (tile_off && tile_cap < size_t(s->n_tiles + 1)) { set_error("abuffer: tile capacity"); return ST_E_CAPACITY; }
+    if (entries && entry_cap < 3 * size_t(s->n_live)) { set_error("abuffer: entry capacity"); return ST_E_CAPACITY; }
+    // the kept segment of every tile: [tile_off[t], tile_off[t] + tile_cnt[t])
+    const size_t T = size_t(s->n_tiles), E = size_t(s->n_entries);
+    std::vector<uint32_t> off(T + 1), cnt(T), a(E), b(E), c(E);
+    hipError_t e = hipMemcpyAsync(off.data(), s->d_tile_off, (T + 1) * 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt.data(), s->d_tile_cnt, T * 4, hipMemcpyDeviceToHost, stream);
+    if (E && entries) {
+        if (e == hipSuccess) e = hipMemcpyAsync(a.data(), s->d_e_node, E * 4, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.data(), s->d_e_zin, E * 4, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c.data(), s->d_e_zout, E * 4, hipMemcpyDeviceToHost, stream);
     }
-    if (entries && e == hipSuccess) {
-        size_t E = size_t(s->n_entries);
-        if (entry_cap < 3 * E) { set_error("abuffer: entry capacity"); return ST_E_CAPACITY; }
-        std::vector<uint32_t> a(E), b(E), c(E);
-        if (E) {
-            e = hipMemcpyAsync(a.data(), s->d_e_node, E * 4, hipMemcpyDeviceToHost, stream);
-            if (e == hipSuccess) e = hipMemcpyAsync(b.data(), s->d_e_zin, E * 4, hipMemcpyDeviceToHost, stream);
-            if (e == hipSuccess) e = hipMemcpyAsync(c.data(), s->d_e_zout, E * 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) {
+        size_t k = 0;
+        for (size_t t = 0; t < T; t++) {
+            if (tile_off) tile_off[t] = uint32_t(k);
+            for (uint32_t i = off[t]; i < off[t] + cnt[t] && i < E; i++, k++) {
+                if (!entries) continue;
+                entries[3 * k] = uint32_t(s->caller_of_post[a[i]]);
+                entries[3 * k + 1] = b[i];
+                entries[3 * k + 2] = c[i];
+            }
         }
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        for (size_t i = 0; i < E && e == hipSuccess; i++) {
-            entries[3 * i] = uint32_t(s->caller_of_post[a[i]]);
-            entries[3 * i + 1] = b[i];
-            entries[3 * i + 2] = c[i];
-        }
+        if (tile_off) tile_off[T] = uint32_t(k);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return device_error(e, "abuffer copy");

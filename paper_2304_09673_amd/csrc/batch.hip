@@ -59,7 +59,6 @@ __global__ void __launch_bounds__(64) batch_wide_kernel(const TraceArgs* __restr
         if (j >= n_jobs) break;
         const uint2 jb = jobs[j];
         const TraceArgs& A = args[jb.x];
-        if (lane_id() == 0) atomicAdd(A.stats + S_WIDE, 1ull);
         trace_block<WaveGlob, KS, SM_PLAIN>(A, S, jb.y >> 8, jb.y & 255u, A.stats, nullptr);
     }
 }
@@ -188,8 +187,8 @@ st_status st_batch_create(st_scene* const* scenes, const st_camera* cams, int32_
         b->gens.push_back(s->ab_gen);
         b->deep = b->deep || s->depth > 16;
         fill_trace_args(s, t, depths[i], normals[i], nullptr, args[size_t(i)]);
-        std::vector<uint32_t> off(size_t(s->n_tiles) + 1), ovl(size_t(s->n_tiles));
-        hipError_t e = hipMemcpyAsync(off.data(), s->d_tile_off, off.size() * 4, hipMemcpyDeviceToHost, stream);
+        std::vector<uint32_t> cnt(size_t(s->n_tiles)), ovl(size_t(s->n_tiles));
+        hipError_t e = hipMemcpyAsync(cnt.data(), s->d_tile_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(ovl.data(), s->d_tile_ovl, ovl.size() * 4, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) { batch_free(b); return device_error(e, "batch: tile sizes"); }
@@ -198,7 +197,7 @@ st_status st_batch_create(st_scene* const* scenes, const st_camera* cams, int32_
             bool wide = ovl[size_t(tile)] > uint32_t(s->ab_ma_fast);
             any_wide = any_wide || wide;
             for (uint32_t k = 0; k < spt; k++)
-                jobs.push_back({off[size_t(tile) + 1] - off[size_t(tile)], uint32_t(i), (uint32_t(tile) << 8) | k, wide});
+                jobs.push_back({cnt[size_t(tile)], uint32_t(i), (uint32_t(tile) << 8) | k, wide});
         }
         if (any_wide) ma = std::max(ma, wide_capacity(s));
     }

@@ -16,11 +16,15 @@
 //              the tile's count incremented when some ray hits;
 //   scan     : tile offsets (CSR);
 //   scatter  : entries written to their tile's segment;
+//   prune    : per tile, entries whose primitive cannot reach the root for
+//              any subset of the tile's list are dropped (not in the paper;
+//              see tile_prune below);
 //   sort     : per tile, entries sorted by (z_in, primitive) in LDS (bitonic),
 //              and the tile's largest depth overlap of intervals computed.
 #include <algorithm>
 
 #include "st_internal.h"
+#include "st_prune.h"
 
 namespace st {
 
@@ -342,22 +346,6 @@ __global__ void scatter_kernel(const Voi* __restrict__ voi, const uint32_t* __re
     e_zout[pos] = z.y;
 }
 
-// partner range of every entry's primitive (kill_partner_range), read by the
-// tracer with the entry so that its dead-primitive test needs no table lookups
-__global__ void entry_range_kernel(const uint32_t* __restrict__ e_node, uint32_t n_ent,
-                                   const uint32_t* __restrict__ kill, const uint2* __restrict__ range,
-                                   uint32_t n_nodes, uint32_t* __restrict__ e_lo, uint32_t* __restrict__ e_hi) {
-    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_ent) return;
-    const uint32_t x = e_node[e];
-    const uint32_t K = kill[min(x, n_nodes - 1u)];
-    const uint2 r = K < n_nodes ? range[K] : make_uint2(0u, 0u);
-    uint32_t lo, hi;
-    kill_partner_range(x, K, r.x, r.y, n_nodes, lo, hi);
-    e_lo[e] = lo;
-    e_hi[e] = hi;
-}
-
 // ---------------------------------------------------------------------------
 // per-tile sort by (z_in, node) and largest depth overlap
 __device__ __forceinline__ uint32_t f2key(float f) {
@@ -458,10 +446,172 @@ __device__ void sort_segment(uint64_t* keys, uint32_t* vals, uint32_t* zo_keys, 
     if (threadIdx.x == 0) *ovl_out = red;
 }
 
+// ---------------------------------------------------------------------------
+// Tile-level pruning (not in the paper).  Every active set the tracer builds
+// for a block of the tile is a subset of the tile's list, and a primitive that
+// cannot reach the root for the whole list cannot for any subset of it: the
+// set of primitives surviving the dead-primitive rule (a killing ancestor with
+// no primitive of the set on its other side; repeated until nothing drops)
+// only shrinks with the set, and removing a dead primitive leaves the pruned
+// view unchanged.  So the entries of dead primitives are dropped once here and
+// every subfrustum view stays what it was.  Per tile: the distinct primitives
+// sorted by index, then rounds of (LCAs of consecutive primitives into a hash
+// set, chain test, compaction), then a stable in-place compaction of the
+// entries.  One workgroup per tile; lists up to kPruneLdsCap in LDS, longer
+// ones in global scratch (7 words per entry).
+constexpr int kPruneThreads = 256;
+constexpr int kPruneLdsCap = 2048;
+
+__device__ __forceinline__ uint32_t lanes_below_mask(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+// exclusive rank of this thread among the workgroup's threads with keep set,
+// in thread order; *total gets their count
+__device__ int block_rank(bool keep, int* total) {
+    __shared__ int wsum[kPruneThreads / 64];
+    const int lane = int(threadIdx.x) & 63, w = int(threadIdx.x) >> 6;
+    const uint64_t mk = __ballot(keep);
+    if (lane == 0) wsum[w] = __popcll(mk);
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int k = 0; k < kPruneThreads / 64; k++) {
+        before += k < w ? wsum[k] : 0;
+        all += wsum[k];
+    }
+    __syncthreads();
+    *total = all;
+    return before + int(lanes_below_mask(mk));
+}
+
+// Prunes the list [e0, e0 + n) in place; a (2^ceil(log2 n) words), b (n
+// words) and tab (2^bits words, 2^bits >= 2n) are scratch.  Returns the
+// number of entries kept.
+__device__ int prune_tile(uint32_t e0, int n, uint32_t* e_node, float* e_zin, float* e_zout, uint32_t* a,
+                          uint32_t* b, uint32_t* tab, int bits, const uint32_t* __restrict__ rmq,
+                          const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes) {
+    const int tid = int(threadIdx.x);
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int i = tid; i < np2; i += kPruneThreads) a[i] = i < n ? e_node[e0 + i] : 0xFFFFFFFFu;
+    __threadfence_block();
+    __syncthreads();
+    bitonic_wg(a, (uint32_t*)nullptr, np2);
+    uint32_t* cur = a;
+    uint32_t* nxt = b;
+    int m = n;   // primitives are distinct within a tile's list
+    for (int round = 0; round < 32 && m > 0; round++) {
+        for (int i = tid; i < (1 << bits); i += kPruneThreads) tab[i] = kNoKill;
+        __threadfence_block();
+        __syncthreads();
+        for (int i = tid; i < m - 1; i += kPruneThreads) {
+            const uint32_t x = cur[i], y = cur[i + 1];
+            const uint32_t l = (x < y && y < n_nodes) ? lca_query(rmq, n_nodes, x, y) : 0u;
+            hinsert(tab, bits, l);
+        }
+        __threadfence_block();
+        __syncthreads();
+        int kept = 0;
+        for (int c = 0; c < m; c += kPruneThreads) {
+            const int i = c + tid;
+            const uint32_t x = i < m ? cur[i] : 0u;
+            const bool keep = i < m && chain_alive(x, kslot, kill, n_nodes, tab, bits);
+            int tot;
+            const int r = block_rank(keep, &tot);
+            if (keep) nxt[kept + r] = x;
+            kept += tot;
+        }
+        __threadfence_block();
+        __syncthreads();
+        const bool changed = kept < m;
+        uint32_t* t = cur;
+        cur = nxt;
+        nxt = t;
+        m = kept;
+        if (!changed) break;
+    }
+    // the survivors, as a hash set; then the entries, compacted in place in
+    // their order (each chunk is read whole before any of it is written)
+    for (int i = tid; i < (1 << bits); i += kPruneThreads) tab[i] = kNoKill;
+    __threadfence_block();
+    __syncthreads();
+    for (int i = tid; i < m; i += kPruneThreads) hinsert(tab, bits, cur[i]);
+    __threadfence_block();
+    __syncthreads();
+    int kept = 0;
+    for (int c = 0; c < n; c += kPruneThreads) {
+        const int i = c + tid;
+        const bool in = i < n;
+        const uint32_t x = in ? e_node[e0 + i] : 0u;
+        const float zi = in ? e_zin[e0 + i] : 0.f, zo = in ? e_zout[e0 + i] : 0.f;
+        const bool keep = in && m > 0 && hfind(tab, bits, x, tab[hslot(x, bits)]);
+        int tot;
+        const int r = block_rank(keep, &tot);   // its barriers separate the reads from the writes
+        if (keep) {
+            e_node[e0 + kept + r] = x;
+            e_zin[e0 + kept + r] = zi;
+            e_zout[e0 + kept + r] = zo;
+        }
+        kept += tot;
+        __threadfence_block();
+        __syncthreads();
+    }
+    return kept;
+}
+
+__device__ __forceinline__ int prune_bits(int n) {   // 2^bits >= 2n, and > 2(n - 1)
+    int bits = 1;
+    while ((1 << bits) < 2 * n) bits++;
+    return bits;
+}
+
+__global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
+        const uint32_t* __restrict__ tile_off, int n_tiles, uint32_t* e_node, float* e_zin, float* e_zout,
+        uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
+        const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
+        uint32_t n_nodes, int keep_all) {
+    __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
+    const int tile = int(blockIdx.x);
+    if (tile >= n_tiles) return;
+    const uint32_t e0 = tile_off[tile];
+    const int n = int(tile_off[tile + 1] - e0);
+    if (keep_all || n == 0) {
+        if (threadIdx.x == 0) tile_cnt[tile] = uint32_t(n);
+        return;
+    }
+    if (n > kPruneLdsCap) {
+        if (threadIdx.x == 0) long_list[atomicAdd(misc + 5, 1u)] = uint32_t(tile);
+        return;
+    }
+    const int kept = prune_tile(e0, n, e_node, e_zin, e_zout, a, b, tab, prune_bits(n), rmq, kslot, kill, n_nodes);
+    if (threadIdx.x == 0) tile_cnt[tile] = uint32_t(kept);
+}
+
+// long lists: scratch in global memory, 7 words per entry of the segment
+// (a: 2n >= 2^ceil(log2 n), b: n, tab: 4n >= 2^bits)
+__global__ void __launch_bounds__(kPruneThreads) tile_prune_long_kernel(
+        const uint32_t* __restrict__ tile_off, uint32_t* e_node, float* e_zin, float* e_zout,
+        uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ long_list, const uint32_t* __restrict__ misc,
+        uint32_t* scratch, const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot,
+        const uint32_t* __restrict__ kill, uint32_t n_nodes) {
+    const uint32_t n_long = misc[5];
+    for (uint32_t idx = blockIdx.x; idx < n_long; idx += gridDim.x) {
+        const uint32_t tile = long_list[idx];
+        const uint32_t e0 = tile_off[tile];
+        const int n = int(tile_off[tile + 1] - e0);
+        uint32_t* base = scratch + size_t(7) * e0;
+        const int kept = prune_tile(e0, n, e_node, e_zin, e_zout, base, base + 2 * n, base + 3 * n, prune_bits(n),
+                                    rmq, kslot, kill, n_nodes);
+        if (threadIdx.x == 0) tile_cnt[tile] = uint32_t(kept);
+        __syncthreads();
+    }
+}
+
 constexpr int kSortLdsCap = 4096;
 
 __global__ void __launch_bounds__(kSortThreads) tile_sort_kernel(
-        const uint32_t* __restrict__ tile_off, int n_tiles, uint32_t* e_node, float* e_zin, float* e_zout,
+        const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_cnt, int n_tiles, uint32_t* e_node,
+        float* e_zin, float* e_zout,
         uint32_t* __restrict__ tile_ovl, uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
         uint32_t ma_fast, uint32_t* __restrict__ wide) {
     __shared__ uint64_t keys[kSortLdsCap];
@@ -469,8 +619,9 @@ __global__ void __launch_bounds__(kSortThreads) tile_sort_kernel(
     __shared__ uint32_t zo[kSortLdsCap];
     int tile = blockIdx.x;
     if (tile >= n_tiles) return;
-    uint32_t e0 = tile_off[tile], e1 = tile_off[tile + 1];
+    uint32_t e0 = tile_off[tile], e1 = e0 + tile_cnt[tile];
     uint32_t n = e1 - e0;
+    if (threadIdx.x == 0 && n) atomicAdd(misc + 3, n);   // entries the tracer reads
     if (n > kSortLdsCap) {
         if (threadIdx.x == 0) long_list[atomicAdd(misc + 0, 1u)] = uint32_t(tile);
         return;
@@ -491,7 +642,8 @@ __global__ void __launch_bounds__(kSortThreads) tile_sort_kernel(
 
 // long lists: bitonic sort in global scratch (one workgroup per long tile)
 __global__ void __launch_bounds__(kSortThreads) tile_sort_long_kernel(
-        const uint32_t* __restrict__ tile_off, uint32_t* e_node, float* e_zin, float* e_zout,
+        const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_cnt, uint32_t* e_node, float* e_zin,
+        float* e_zout,
         uint32_t* __restrict__ tile_ovl, const uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
         uint64_t* scratch_keys, uint32_t* scratch_vals, uint32_t* scratch_zo, uint32_t ma_fast,
         uint32_t* __restrict__ wide) {
@@ -499,7 +651,7 @@ __global__ void __launch_bounds__(kSortThreads) tile_sort_long_kernel(
     __shared__ uint32_t ov;
     for (uint32_t idx = blockIdx.x; idx < n_long; idx += gridDim.x) {
         uint32_t tile = long_list[idx];
-        uint32_t e0 = tile_off[tile], e1 = tile_off[tile + 1];
+        uint32_t e0 = tile_off[tile], e1 = e0 + tile_cnt[tile];
         // scratch segment: entries of this tile padded to a power of two fit
         // in [2*e0, 2*e0 + 2n) since np2 < 2n
         uint64_t* k = scratch_keys + 2 * size_t(e0);
@@ -516,7 +668,7 @@ __global__ void __launch_bounds__(kSortThreads) tile_sort_long_kernel(
     }
 }
 
-// Dispatch order of the tiles: decreasing A-buffer list length.  The work of
+// Dispatch order of the tiles: decreasing A-buffer list length (after pruning).  The work of
 // a tile's blocks grows with the number of depth intervals its rays cross,
 // and a frame is set by its slowest blocks, so the heavy tiles are started
 // first and the light ones fill the machine behind them.  One workgroup,
@@ -526,13 +678,13 @@ __global__ void __launch_bounds__(kSortThreads) tile_sort_long_kernel(
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4 * kOrderThreads;
 
-__global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_t* __restrict__ tile_off,
+__global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_t* __restrict__ tile_cnt,
                                                                     int n_tiles, uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[kOrderBuckets];
     __shared__ uint32_t part[kOrderThreads];
     const int tid = int(threadIdx.x);
     auto bucket = [&](int t) {   // longest first
-        uint32_t len = tile_off[t + 1] - tile_off[t];
+        const uint32_t len = tile_cnt[t];
         return uint32_t(kOrderBuckets - 1) - min(len, uint32_t(kOrderBuckets - 1));
     };
     for (int b = tid; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
@@ -661,15 +813,11 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         dev_free(s, s->d_e_node, stream);
         dev_free(s, s->d_e_zin, stream);
         dev_free(s, s->d_e_zout, stream);
-        dev_free(s, s->d_e_lo, stream);
-        dev_free(s, s->d_e_hi, stream);
         int64_t cap = std::max<int64_t>(int64_t(n_ent) + int64_t(n_ent) / 4, 1024);
         s->d_e_node = (uint32_t*)dev_alloc(s, size_t(cap) * 4, stream);
         s->d_e_zin = (float*)dev_alloc(s, size_t(cap) * 4, stream);
         s->d_e_zout = (float*)dev_alloc(s, size_t(cap) * 4, stream);
-        s->d_e_lo = (uint32_t*)dev_alloc(s, size_t(cap) * 4, stream);
-        s->d_e_hi = (uint32_t*)dev_alloc(s, size_t(cap) * 4, stream);
-        if (!s->d_e_node || !s->d_e_zin || !s->d_e_zout || !s->d_e_lo || !s->d_e_hi) {
+        if (!s->d_e_node || !s->d_e_zin || !s->d_e_zout) {
             set_error("build: A-buffer allocation failed");
             s->ab_cap = 0;
             return ST_E_NOMEM;
@@ -680,10 +828,8 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     if (n_cand)
         hipLaunchKernelGGL(scatter_kernel, dim3((n_cand + 255) / 256), dim3(256), 0, stream, s->d_voi, coff, P,
                            n_cand, cz, ctile, s->d_tile_off, cur, s->d_e_node, s->d_e_zin, s->d_e_zout);
-    ST_CHECK(fill_u32(s->d_wide, 1u, 0u, stream), "clear wide list");
-    hipLaunchKernelGGL(tile_sort_kernel, dim3(T), dim3(kSortThreads), 0, stream, s->d_tile_off, T, s->d_e_node,
-                       s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, uint32_t(s->ab_ma_fast), s->d_wide);
-    // long tiles, if any (the kernel reads their count on the device)
+    // scratch of the long lists (pruning: 7 words per entry; sorting: 2
+    // padded copies of key, value and exit depth, 16 bytes per entry each)
     size_t long_bytes = size_t(2) * n_ent * (8 + 4 + 4) + 64;
     if (long_bytes > s->long_bytes) {
         dev_free(s, s->d_long, stream);
@@ -692,18 +838,28 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         if (!s->d_long) { set_error("build: sort scratch allocation failed"); return ST_E_NOMEM; }
     }
     char* lbuf = (char*)s->d_long;
+    // tile-level pruning (long lists: the kernel reads their count on the device)
+    hipLaunchKernelGGL(tile_prune_kernel, dim3(T), dim3(kPruneThreads), 0, stream, s->d_tile_off, T, s->d_e_node,
+                       s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc, s->d_rmq,
+                       reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
+                       t.keep_all_entries);
+    hipLaunchKernelGGL(tile_prune_long_kernel, dim3(std::min(T, 512)), dim3(kPruneThreads), 0, stream,
+                       s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc,
+                       reinterpret_cast<uint32_t*>(lbuf), s->d_rmq, reinterpret_cast<const uint4*>(s->d_kslot),
+                       s->d_kill, uint32_t(s->n_nodes));
+    ST_CHECK(fill_u32(s->d_wide, 1u, 0u, stream), "clear wide list");
+    hipLaunchKernelGGL(tile_sort_kernel, dim3(T), dim3(kSortThreads), 0, stream, s->d_tile_off, s->d_tile_cnt, T,
+                       s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, uint32_t(s->ab_ma_fast),
+                       s->d_wide);
+    // long tiles, if any (the kernel reads their count on the device)
     uint64_t* sk = (uint64_t*)lbuf;
     uint32_t* sv = (uint32_t*)(lbuf + size_t(2) * n_ent * 8);
     uint32_t* sz = (uint32_t*)(lbuf + size_t(2) * n_ent * 12);
     hipLaunchKernelGGL(tile_sort_long_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream,
-                       s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, sk, sv, sz,
-                       uint32_t(s->ab_ma_fast), s->d_wide);
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_off, T,
+                       s->d_tile_off, s->d_tile_cnt, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl,
+                       misc, sk, sv, sz, uint32_t(s->ab_ma_fast), s->d_wide);
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_cnt, T,
                        s->d_tile_order);
-    if (n_ent)
-        hipLaunchKernelGGL(entry_range_kernel, dim3((n_ent + 255) / 256), dim3(256), 0, stream, s->d_e_node, n_ent,
-                           s->d_kill, reinterpret_cast<const uint2*>(s->d_range), uint32_t(s->n_nodes), s->d_e_lo,
-                           s->d_e_hi);
     if (replay) {
         e = hipGetLastError();
         return e == hipSuccess ? ST_OK : device_error(e, "binning kernels");
@@ -716,6 +872,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     ST_CHECK(hipStreamSynchronize(stream), "sync (build)");
     s->max_overlap = h_misc[1];
     s->max_list = h_misc[2];
+    s->n_live = h_misc[3];
     s->n_wide = h_wide;
 #undef ST_CHECK
     return ST_OK;

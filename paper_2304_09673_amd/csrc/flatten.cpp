@@ -201,19 +201,6 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
     }
     s->h_blob.assign(n, 0);
     s->h_kill.assign(n, kNoKill);
-    // subtree ranges: a subtree is the post-order range [first, node]; an
-    // operator's right subtree starts at split = (left child) + 1
-    s->h_range.assign(size_t(2) * n, 0u);
-    for (int p = 0; p < n; p++) {
-        const st_node& nd = nodes[order[p]];
-        if (is_prim_kind(nd.kind)) {
-            s->h_range[2 * size_t(p)] = uint32_t(p);
-        } else {
-            uint32_t lp = uint32_t(s->post_of_caller[nd.left]);
-            s->h_range[2 * size_t(p)] = s->h_range[2 * size_t(lp)];
-            s->h_range[2 * size_t(p) + 1] = lp + 1u;
-        }
-    }
     s->h_par.assign(n, NodePar{});
     s->h_roi.assign(n, 0.f);
     s->h_prims.clear();
@@ -247,6 +234,19 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
             s->h_kill[p] = kills ? pp : s->h_kill[pp];
         }
         s->h_roi[p] = float(roi[p]);
+    }
+    // chain rows: a node's first kKillLevels killing ancestors, nearest first
+    // (following the kill pointers from node to node visits every killing
+    // ancestor on the path to the root), padded with kNoKill, then their count
+    s->h_kslot.assign(size_t(8) * n, kNoKill);
+    for (int p = 0; p < n; p++) {
+        uint32_t* row = &s->h_kslot[8 * size_t(p)];
+        uint32_t v = uint32_t(p), lev = 0;
+        while (lev < uint32_t(kKillLevels) && s->h_kill[v] < uint32_t(n)) {
+            v = s->h_kill[v];
+            row[lev++] = v;
+        }
+        row[7] = lev;
     }
 
     // parameters, bounds

@@ -17,6 +17,9 @@ namespace st {
 // post-order, so the ancestor field holds a node index (the parent here).
 constexpr uint32_t kNoNode = 0x7FFFFFu;      // "invalid" 23-bit ancestor
 constexpr uint32_t kNoKill = 0xFFFFFFFFu;    // no killing ancestor
+// killing ancestors a node's chain row holds (8 words: the first kKillLevels
+// killing ancestors, nearest first, padded with kNoKill, then their count)
+constexpr int kKillLevels = 7;
 constexpr int kMaxDepth = 31;                // evaluation stack bound
 constexpr int kStack = 32;
 
@@ -97,23 +100,6 @@ HD Ray pixel_ray(const DevCam& c, int i, int j) {
     r.d[0] = d0 * inv; r.d[1] = d1 * inv; r.d[2] = d2 * inv;
     r.cosv = fmaf(r.d[0], c.fwd[0], fmaf(r.d[1], c.fwd[1], r.d[2] * c.fwd[2]));
     return r;
-}
-
-// The operand of x's nearest killing ancestor K (an intersection, or a
-// difference reached from its right operand) that x does not belong to, as a
-// post-order node range [lo, hi): x's branch survives K only if an active
-// primitive lies in it.  (first, split) are K's subtree start and the start
-// of K's right subtree.  Without a killing ancestor the range is [0, 2^32-1),
-// which always holds x itself.
-HD void kill_partner_range(uint32_t x, uint32_t K, uint32_t first, uint32_t split, uint32_t n_nodes,
-                           uint32_t& lo, uint32_t& hi) {
-    if (K < n_nodes) {
-        lo = x < split ? split : first;
-        hi = x < split ? K : split;
-    } else {
-        lo = 0u;
-        hi = 0xFFFFFFFFu;
-    }
 }
 
 }  // namespace st

@@ -19,7 +19,7 @@ struct st_scene {
     std::vector<int32_t> post_of_caller;   // caller index -> post-order index
     std::vector<int32_t> caller_of_post;   // post-order index -> caller index
     std::vector<uint32_t> h_blob, h_kill, h_rmq, h_prims;
-    std::vector<uint32_t> h_range;   // per node: first node of the subtree, start of the right subtree
+    std::vector<uint32_t> h_kslot;   // per node: chain row (8 words, see kKillLevels)
     std::vector<st::NodePar> h_par;
     std::vector<float> h_roi;
     std::vector<PrimBox> h_box;   // per primitive, in h_prims order
@@ -29,7 +29,7 @@ struct st_scene {
     // device copies
     uint32_t* d_blob = nullptr;
     uint32_t* d_kill = nullptr;
-    uint32_t* d_range = nullptr;     // 2 words per node
+    uint32_t* d_kslot = nullptr;     // 8 words per node
     uint32_t* d_rmq = nullptr;
     uint32_t* d_prims = nullptr;     // post-order index of each primitive
     st::NodePar* d_par = nullptr;
@@ -47,14 +47,14 @@ struct st_scene {
     uint32_t* d_tile_off = nullptr;   // n_tiles + 1
     uint32_t* d_tile_ovl = nullptr;   // per tile max depth overlap
     uint32_t* d_tile_order = nullptr; // tiles by decreasing list length (dispatch order)
+    uint32_t* d_tile_cnt = nullptr;   // per tile: entries kept by the tile-level pruning
     uint32_t* d_e_node = nullptr;     // entries, SoA, sorted per tile
     float* d_e_zin = nullptr;
     float* d_e_zout = nullptr;
-    uint32_t* d_e_lo = nullptr;   // partner range of the entry's primitive
-    uint32_t* d_e_hi = nullptr;
     uint32_t* d_wide = nullptr;       // list of tiles that need the wide path, [0] = count
     uint32_t* d_misc = nullptr;       // small device counters
-    int64_t n_entries = 0, ab_cap = 0;
+    int64_t n_entries = 0, ab_cap = 0;   // entries binned, capacity
+    int64_t n_live = 0;                  // entries kept by the tile-level pruning
     uint32_t n_cand = 0;        // (primitive, tile) candidates of the last build
     uint64_t ab_gen = 0;        // bumped by every st_build_abuffer
     uint32_t max_list = 0, max_overlap = 0, n_wide = 0;
@@ -63,6 +63,8 @@ struct st_scene {
     // wide-path per-workgroup slots (trace)
     void* d_slots = nullptr;
     size_t slots_bytes = 0;
+    void* d_wrec = nullptr;           // per-block counter records of the last trace
+    size_t wrec_bytes = 0;
 
     // scratch kept between builds
     void* d_scratch = nullptr;
@@ -104,8 +106,9 @@ struct DumpTarget {
     unsigned long long* n;     // samples produced (may exceed cap)
     unsigned long long cap;
 };
+// want_stats: sum the blocks' counter records into d_stats after the trace
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
-                       hipStream_t stream, const DumpTarget* dump = nullptr);
+                       hipStream_t stream, const DumpTarget* dump = nullptr, bool want_stats = false);
 st_status debug_eval_device(const st_scene* s, const uint32_t* active_post, int n_active,
                             const float* pts, int n_pts, float* out_f, float* out_grad,
                             int* root_used, hipStream_t stream);

@@ -45,6 +45,61 @@ HD uint32_t lca_query(const uint32_t* rmq, uint32_t n_nodes, uint32_t a, uint32_
     return (x < y ? x : y) & 0xFFFFFFu;
 }
 
+// Hash set of node indices in LDS or global memory: open addressing, linear
+// probing, kNoKill marks an empty slot.  The table has 2^bits slots and is
+// filled to less than half, so every probe sequence reaches an empty slot.
+__device__ __forceinline__ uint32_t hslot(uint32_t k, int bits) { return (k * 2654435761u) >> (32 - bits); }
+
+__device__ __forceinline__ void hinsert(uint32_t* tab, int bits, uint32_t k) {
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t h = hslot(k, bits);
+    while (true) {
+        const uint32_t old = atomicCAS(tab + h, kNoKill, k);
+        if (old == kNoKill || old == k) return;
+        h = (h + 1u) & mask;
+    }
+}
+
+// membership of k, given the content t of its home slot (read in advance)
+__device__ __forceinline__ bool hfind(const uint32_t* tab, int bits, uint32_t k, uint32_t t) {
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t h = hslot(k, bits);
+    while (t != k && t != kNoKill) {
+        h = (h + 1u) & mask;
+        t = tab[h];
+    }
+    return t == k;
+}
+
+// Whether primitive x survives every killing ancestor on its path, given the
+// hash set of the nodes with active primitives on both sides (the LCAs of
+// consecutive active primitives): its chain row lists the first kKillLevels
+// killing ancestors (kNoKill padding), the kill pointers continue a longer
+// chain (ancestors are later in post-order, so the walk ends).  The home
+// slots of the row's ancestors are read together.
+__device__ __forceinline__ bool chain_alive(uint32_t x, const uint4* __restrict__ kslot,
+                                            const uint32_t* __restrict__ kill, uint32_t n_nodes,
+                                            const uint32_t* tab, int bits) {
+    const uint4* row = kslot + size_t(min(x, n_nodes - 1u)) * 2u;
+    const uint4 r0 = row[0], r1 = row[1];
+    const uint32_t K[kKillLevels] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z};
+    uint32_t t[kKillLevels];
+#pragma unroll
+    for (int j = 0; j < kKillLevels; j++) t[j] = K[j] != kNoKill ? tab[hslot(K[j], bits)] : kNoKill;
+    bool keep = true;
+#pragma unroll
+    for (int j = 0; j < kKillLevels; j++)
+        if (K[j] != kNoKill) keep = keep && hfind(tab, bits, K[j], t[j]);
+    uint32_t v = keep && r1.w == uint32_t(kKillLevels) ? K[kKillLevels - 1] : kNoKill;
+    while (v < n_nodes) {
+        const uint32_t u = kill[v];
+        if (!(u < n_nodes && u > v)) break;
+        if (!hfind(tab, bits, u, tab[hslot(u, bits)])) { keep = false; break; }
+        v = u;
+    }
+    return keep;
+}
+
 struct PruneResult {
     int len;     // number of view entries (0 when the root is unused)
     int used;    // 1 when the pruned root is used

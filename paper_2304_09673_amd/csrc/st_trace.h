@@ -83,16 +83,15 @@ struct TraceArgs {
     const uint32_t* blob;
     const NodePar* par;
     const uint32_t* kill;
-    const uint2* range;        // per node: first node of the subtree, start of the right subtree
     const uint32_t* rmq;
     uint32_t n_nodes;
     const uint32_t* tile_off;
+    const uint32_t* tile_cnt;   // per tile: entries kept (the list is [tile_off, tile_off + tile_cnt))
     const uint32_t* e_node;
-    const uint32_t* e_lo;      // per entry: partner range of the primitive (kill_partner_range)
-    const uint32_t* e_hi;
     const float* e_zin;
     const float* e_zout;
     const uint32_t* tile_ovl;
+    const uint4* kslot;        // per node: chain row, 2 x uint4 (killing ancestors, count)
     const uint32_t* tile_order;   // dispatch order of the tiles (fast path)
     const uint32_t* wide;      // [0] count, [1..] tiles
     DevCam cam;
@@ -104,6 +103,8 @@ struct TraceArgs {
     float* out_normal;
     uint32_t* out_info;
     unsigned long long* stats;
+    unsigned long long* wrec;      // per block (job = tile * sub_x^2 + sub): kWaveStats counters,
+                                   // or null: atomics into stats
     const uint32_t* mlp;           // packed step model (learned mode)
     float* dump_x;                 // dump mode: features [cap][8], targets [cap]
     float* dump_t;
@@ -125,9 +126,9 @@ __host__ __device__ inline uint32_t pow2_at_least(uint32_t x) {
     return p;
 }
 // 32-bit words of a wide-path slot of capacity ma: active set (node, exit
-// depth, partner range lo/hi; two buffers each), vs and view (2 ma each), and
-// the LCA sort array (a power of two at least ma)
-__host__ __device__ inline size_t slot_words(int ma) { return 12 * size_t(ma) + pow2_at_least(uint32_t(ma)); }
+// depth; two buffers each), vs and view (2 ma each), and the LCA sort array
+// (a power of two at least ma)
+__host__ __device__ inline size_t slot_words(int ma) { return 8 * size_t(ma) + pow2_at_least(uint32_t(ma)); }
 
 // kernel arguments of one scene (trace.hip)
 void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
@@ -137,8 +138,11 @@ int wide_capacity(const st_scene* s);
 
 enum StatIdx {
     S_RAYS = 0, S_HITS, S_UNCONV, S_EVALS, S_GEVALS, S_NODE = 5, S_GNODE = 9, S_STEPS = 13, S_SUBF, S_EMPTY,
-    S_VIEWN, S_MAXACT, S_WIDE, S_ACC, S_REJ, S_STALL, S_SMOOTH
+    S_VIEWN, S_MAXACT, S_WIDE, S_ACC, S_REJ, S_STALL, S_SMOOTH, S_COUNT
 };
+// words of a block's counter record (S_COUNT rounded up)
+constexpr int kWaveStats = 24;
+static_assert(S_COUNT <= kWaveStats, "counter record too small");
 
 // Per-wave storage of the active set and the view.  Two layouts share the
 // tracing code through accessors: LDS arrays of compile-time capacity MA
@@ -150,15 +154,11 @@ template <int MA>
 struct WaveLds {
     uint32_t act_[2][MA];
     float ze_[2][MA];
-    uint32_t lo_[2][MA];
-    uint32_t hi_[2][MA];
     uint32_t lca_[MA];
     uint32_t vs_[2 * MA];
     uint32_t view_[2 * MA];
     __device__ __forceinline__ uint32_t* act(int b) { return act_[b]; }
     __device__ __forceinline__ float* ze(int b) { return ze_[b]; }
-    __device__ __forceinline__ uint32_t* olo(int b) { return lo_[b]; }
-    __device__ __forceinline__ uint32_t* ohi(int b) { return hi_[b]; }
     __device__ __forceinline__ uint32_t* lca() { return lca_; }
     __device__ __forceinline__ uint32_t* vs() { return vs_; }
     __device__ __forceinline__ uint32_t* view() { return view_; }
@@ -171,11 +171,9 @@ struct WaveGlob {
     int ma;
     __device__ __forceinline__ uint32_t* act(int b) { return base + b * ma; }
     __device__ __forceinline__ float* ze(int b) { return reinterpret_cast<float*>(base + (2 + b) * ma); }
-    __device__ __forceinline__ uint32_t* olo(int b) { return base + (4 + b) * ma; }
-    __device__ __forceinline__ uint32_t* ohi(int b) { return base + (6 + b) * ma; }
-    __device__ __forceinline__ uint32_t* vs() { return base + 8 * ma; }
-    __device__ __forceinline__ uint32_t* view() { return base + 10 * ma; }
-    __device__ __forceinline__ uint32_t* lca() { return base + 12 * ma; }
+    __device__ __forceinline__ uint32_t* vs() { return base + 4 * ma; }
+    __device__ __forceinline__ uint32_t* view() { return base + 6 * ma; }
+    __device__ __forceinline__ uint32_t* lca() { return base + 8 * ma; }
     __device__ __forceinline__ int cap() const { return ma; }
 };
 
@@ -305,63 +303,67 @@ __device__ __forceinline__ int lower_count(const uint32_t* a, int n, uint32_t x)
     return lo;
 }
 
-// Builds the pruned view of the active set S.act(buf)[0..n) into S.view().
-// Drops active primitives that cannot reach the root: a primitive whose
-// nearest killing ancestor K (an intersection, or a difference reached from
-// its right operand) has no active primitive in K's other operand is
-// discarded at K; so is every other active primitive below K (they are all on
-// the same side), and K is unused.  Removing it leaves the pruned view
-// unchanged and shrinks the work of the view build.  act[0..n) sorted;
-// survivors written in order to out; returns their count.
-// act, plo, phi: primitives (sorted) and their partner ranges; survivors go
-// to out (and their ranges to out_lo/out_hi when those are given).
-__device__ int drop_dead(const uint32_t* act, const uint32_t* plo, const uint32_t* phi, int n, uint32_t* out,
-                         uint32_t* out_lo, uint32_t* out_hi) {
+// Lowest common ancestors of the consecutive pairs of act[0..n) into
+// lca[0..n-1), and into the hash set tab (cleared first).
+__device__ void pair_lcas(const TraceArgs& A, const uint32_t* act, int n, uint32_t* lca, uint32_t* tab, int bits) {
     const int lane = lane_id();
-    int kept = 0;
+    for (int i = lane; i < (1 << bits); i += 64) tab[i] = kNoKill;
     wave_sync();
-    for (int b = 0; b < n; b += 64) {
-        const int s = b + lane;
-        const bool in = s < n;
-        const uint32_t x = in ? act[s] : 0u;
-        const uint32_t lo = in ? plo[s] : 0u, hi = in ? phi[s] : 0u;
-        // an active primitive in [lo, hi)
-        const bool keep = in && lower_count(act, n, hi) > lower_count(act, n, lo);
-        const uint64_t mk = ballot(keep);
-        const int dst = kept + int(lanes_below(mk));
-        if (keep) {
-            out[dst] = x;
-            if (out_lo) { out_lo[dst] = lo; out_hi[dst] = hi; }
-        }
-        kept += __popcll(mk);
+    for (int i = lane; i < n - 1; i += 64) {
+        // a < b always holds for a duplicate-free sorted set; the guard keeps
+        // a corrupted set from reading outside the table
+        const uint32_t a = act[i], b = act[i + 1];
+        const uint32_t l = (a < b && b < A.n_nodes) ? lca_query(A.rmq, A.n_nodes, a, b) : 0u;
+        lca[i] = l;
+        hinsert(tab, bits, l);
     }
     wave_sync();
-    return kept;
 }
 
+// Builds the pruned view of the active set S.act(buf)[0..n) into S.view().
+//
+// First it drops active primitives that cannot reach the root: a primitive
+// with a killing ancestor K on its path (an intersection, or a difference
+// reached from its right operand) whose other operand holds no active
+// primitive is discarded at K, and so is everything below K on that side.
+// K has active primitives on both sides exactly when it is the lowest common
+// ancestor of two consecutive active primitives (post-order sorted), so the
+// test is a lookup of each killing ancestor (chain row: the first
+// kKillLevels, then the kill pointers) in the hash set of those LCAs.
+// Removing dead primitives leaves the view unchanged; rounds repeat until
+// nothing drops, since a drop can leave another killing ancestor one-sided.
+// The LCAs of the last round are those of the survivors, which the view
+// build needs next.
 template <class Mem>
 __device__ PruneResult build_view(const TraceArgs& A, Mem& S, int buf, int n) {
     const uint32_t* act = S.act(buf);
     const int lane = lane_id();
+    // hash table over vs and view (contiguous, 4 * capacity words, unused
+    // until the merge), more than twice the number of LCAs
+    uint32_t* tab = S.vs();
+    const int bits = 31 - __builtin_clz(uint32_t(4 * S.cap()));
     int m;
     {
-        // rounds until nothing more drops: a primitive whose only partners
-        // were dropped goes in the next round (the inactive buffers of the
-        // active set and the not yet used vs array serve as scratch)
-        const uint32_t* plo = S.olo(buf);
-        const uint32_t* phi = S.ohi(buf);
         uint32_t* bx[2] = {S.act(buf ^ 1), reinterpret_cast<uint32_t*>(S.ze(buf ^ 1))};
-        uint32_t* blo[2] = {S.olo(buf ^ 1), S.vs()};
-        uint32_t* bhi[2] = {S.ohi(buf ^ 1), S.vs() + S.cap()};
-        for (int round = 0; round < 8 && n > 0; round++) {
-            const int t = round & 1;
-            const int kept = drop_dead(act, plo, phi, n, bx[t], blo[t], bhi[t]);
-            act = bx[t];
-            plo = blo[t];
-            phi = bhi[t];
-            const bool changed = kept < n;
+        bool lca_ok = false;
+        for (int round = 0; round < 8; round++) {
+            pair_lcas(A, act, n, S.lca(), tab, bits);
+            uint32_t* out = bx[round & 1];
+            int kept = 0;
+            for (int b = 0; b < n; b += 64) {
+                const int s = b + lane;
+                const bool in = s < n;
+                const uint32_t x = in ? act[s] : 0u;
+                const bool keep = in && chain_alive(x, A.kslot, A.kill, A.n_nodes, tab, bits);
+                const uint64_t mk = ballot(keep);
+                if (keep) out[kept + int(lanes_below(mk))] = x;
+                kept += __popcll(mk);
+            }
+            wave_sync();
+            if (kept == n) { lca_ok = true; break; }
+            act = out;
             n = kept;
-            if (!changed) break;
+            if (n == 0) break;
         }
         if (n == 0) {
             PruneResult r;
@@ -370,19 +372,17 @@ __device__ PruneResult build_view(const TraceArgs& A, Mem& S, int buf, int n) {
             r.lip = 0.f;
             return r;
         }
+        if (!lca_ok) pair_lcas(A, act, n, S.lca(), tab, bits);
     }
     if (n == 1) {
         if (lane == 0) S.vs()[0] = act[0];
         m = 1;
     } else if (n <= 64) {
-        // one element per lane: LCAs of consecutive primitives, then every
-        // element's position in post-order by counting (all-pairs compares
-        // through readlane; no sort passes, no LDS round trips)
+        // one element per lane: every element's position in post-order by
+        // counting (all-pairs compares through readlane; no sort passes)
         const int nl = n - 1;
         const uint32_t a = lane < n ? act[lane] : 0xFFFFFFFFu;
-        const uint32_t an = lane + 1 < n ? act[lane + 1] : 0u;
-        uint32_t l = 0xFFFFFFFFu;
-        if (lane < nl) l = (a < an && an < A.n_nodes) ? lca_query(A.rmq, A.n_nodes, a, an) : 0u;
+        const uint32_t l = lane < nl ? S.lca()[lane] : 0xFFFFFFFFu;
         uint32_t rl = 0, ca = 0, cl = 0;   // LCAs before l, primitives before l, LCAs before a
         for (int j = 0; j < n; j++) {
             const uint32_t lj = rdlane(l, j), aj = rdlane(a, j);
@@ -397,20 +397,12 @@ __device__ PruneResult build_view(const TraceArgs& A, Mem& S, int buf, int n) {
         if (lane < nl) S.vs()[int(rl + ca)] = l;
         m = 2 * n - 1;
     } else {
-        // 1. LCAs of consecutive active primitives
+        // 1. the LCAs of consecutive active primitives (S.lca()), padded to
+        //    a power of two
         int nl = n - 1;
         int np2 = 1;
         while (np2 < nl) np2 <<= 1;
-        for (int i = lane; i < np2; i += 64) {
-            uint32_t x = 0xFFFFFFFFu;
-            if (i < nl) {
-                // a < b always holds for a duplicate-free sorted set; the
-                // guard keeps a corrupted set from reading outside the table
-                uint32_t a = act[i], b = act[i + 1];
-                x = (a < b && b < A.n_nodes) ? lca_query(A.rmq, A.n_nodes, a, b) : 0u;
-            }
-            S.lca()[i] = x;
-        }
+        for (int i = nl + lane; i < np2; i += 64) S.lca()[i] = 0xFFFFFFFFu;
         // 2. sort them
         wave_bitonic(S.lca(), np2);
         // 3. merge with the (sorted) primitives into post-order
@@ -492,6 +484,27 @@ __device__ void dump_samples(const TraceArgs& A, const uint32_t* view, int len, 
 }
 
 // ---------------------------------------------------------------------------
+// Counters of one block.  With a record array, lane c stores counter c of
+// the block's record (one coalesced write, no atomics: thousands of blocks
+// adding into the same few words serialise in the L2 and were the largest
+// cost of a frame); the records are summed by a separate kernel when the
+// caller asks for statistics.  Without one, lane 0 adds them atomically.
+__device__ void block_counters(const TraceArgs& A, unsigned long long* cnt, uint32_t job,
+                               const unsigned long long (&v)[kWaveStats]) {
+    const int lane = lane_id();
+    if (A.wrec) {
+        unsigned long long mine = 0;
+#pragma unroll
+        for (int c = 0; c < kWaveStats; c++) mine = lane == c ? v[c] : mine;
+        if (lane < kWaveStats) A.wrec[size_t(job) * kWaveStats + size_t(lane)] = mine;
+    } else if (lane == 0) {
+        for (int c = 0; c < S_COUNT; c++) {
+            if (c == S_MAXACT) atomicMax(cnt + c, v[c]);
+            else if (v[c]) atomicAdd(cnt + c, v[c]);
+        }
+    }
+}
+
 // Lane modes inside a subfrustum
 enum { M_IDLE = 0, M_TRACE = 1, M_REFINE = 2, M_GRAD = 3 };
 
@@ -505,7 +518,12 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
     const int px = tx * A.ts + sx * 8 + (lane & 7);
     const int py = ty * A.ts + sy * 8 + (lane >> 3);
     const bool valid = px < A.cam.w && py < A.cam.h;
-    if (ballot(valid) == 0) return;
+    const uint32_t job = tile * uint32_t(A.sub_x * A.sub_x) + sub;
+    if (ballot(valid) == 0) {
+        const unsigned long long zero[kWaveStats] = {};
+        block_counters(A, cnt, job, zero);
+        return;
+    }
     Ray ray = pixel_ray(A.cam, px, py);
     const float inv_cos = 1.0f / ray.cosv;
 
@@ -525,12 +543,12 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
     uint32_t n_acc = 0, n_rej = 0;
 
     // wave state (uniform)
-    const uint32_t e0 = uni(A.tile_off[tile]), e1 = uni(A.tile_off[tile + 1]);
+    const uint32_t e0 = uni(A.tile_off[tile]), e1 = e0 + uni(A.tile_cnt[tile]);
     uint32_t i = e0;
     int n = 0, buf = 0;
     float z_end = -__builtin_inff();
     uint64_t node_cnt[4] = {0, 0, 0, 0}, gnode_cnt[4] = {0, 0, 0, 0};
-    uint32_t n_subf = 0, n_empty = 0, max_act = 0;
+    uint32_t n_subf = 0, n_empty = 0, max_act = 0, n_stall = 0;
     uint64_t view_nodes = 0;
     // every turn fetches, drops or closes a subfrustum that the next turn
     // drops from; the bound only guards against a stalled capacity
@@ -542,14 +560,14 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
     // the next fetch window (entries pf_i + lane), loaded at the end of the
     // previous turn's fetch so that its latency overlaps the view build and
     // the stepping
-    uint32_t pf_i = 0xFFFFFFFFu, pf_nd = 0u, pf_lo = 0u, pf_hi = 0u;
+    uint32_t pf_i = 0xFFFFFFFFu, pf_nd = 0u;
     float pf_zb = 0.f, pf_zo = 0.f;
 
     while (true) {
         if (ballot(!done) == 0) break;
         if (i >= e1 && n == 0) break;
         if (guard-- == 0u) {
-            if (lane == 0) atomicAdd(cnt + S_STALL, 1ull);
+            n_stall = 1;
             break;
         }
         // -- drop exited primitives (z_e <= z_end), compact in place; the
@@ -568,10 +586,9 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                 const uint64_t mk = ballot(keep);
                 if (mk != ballot(in) || kept != b) {
                     uint32_t a = in ? S.act(buf)[s] : 0u;
-                    uint32_t plo = in ? S.olo(buf)[s] : 0u, phi = in ? S.ohi(buf)[s] : 0u;
                     int dst = kept + int(lanes_below(mk));
                     wave_sync();
-                    if (keep) { S.act(buf)[dst] = a; S.ze(buf)[dst] = z; S.olo(buf)[dst] = plo; S.ohi(buf)[dst] = phi; }
+                    if (keep) { S.act(buf)[dst] = a; S.ze(buf)[dst] = z; }
                 }
                 kept += __popcll(mk);
             }
@@ -589,15 +606,13 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             uint32_t c = uint32_t(lane);
             bool in = i + c < e1;
             float zb, zo;
-            uint32_t nd, nlo, nhi;
+            uint32_t nd;
             if (pf_i == i) {
-                zb = pf_zb; zo = pf_zo; nd = pf_nd; nlo = pf_lo; nhi = pf_hi;
+                zb = pf_zb; zo = pf_zo; nd = pf_nd;
             } else {
                 zb = in ? A.e_zin[i + c] : __builtin_inff();
                 zo = in ? A.e_zout[i + c] : -__builtin_inff();
                 nd = in ? A.e_node[i + c] : 0u;
-                nlo = in ? A.e_lo[i + c] : 0u;
-                nhi = in ? A.e_hi[i + c] : 0u;
             }
             // exclusive prefix max of exit depths of earlier candidates
             float pm = zo;
@@ -636,7 +651,6 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                 bool in_s = s < n;
                 uint32_t a = in_s ? S.act(buf)[s] : 0u;
                 float az = in_s ? S.ze(buf)[s] : 0.f;
-                uint32_t alo = in_s ? S.olo(buf)[s] : 0u, ahi = in_s ? S.ohi(buf)[s] : 0u;
                 uint32_t h = in_s ? hist[s] : 0u;
                 for (int o = 1; o < 64; o <<= 1) {   // inclusive prefix sum over the chunk
                     uint32_t y = __shfl_up(h, o);
@@ -647,15 +661,11 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                 if (in_s) {
                     S.act(nb)[s + int(shift)] = a;
                     S.ze(nb)[s + int(shift)] = az;
-                    S.olo(nb)[s + int(shift)] = alo;
-                    S.ohi(nb)[s + int(shift)] = ahi;
                 }
             }
             if (lane < k) {
                 S.act(nb)[ins + rk] = nd;
                 S.ze(nb)[ins + rk] = zo;
-                S.olo(nb)[ins + rk] = nlo;
-                S.ohi(nb)[ins + rk] = nhi;
             }
             // the new ones also extend the reach
             float nz_ = lane < k ? zo : -__builtin_inff();
@@ -680,8 +690,6 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             pf_zb = in ? A.e_zin[i + c] : __builtin_inff();
             pf_zo = in ? A.e_zout[i + c] : -__builtin_inff();
             pf_nd = in ? A.e_node[i + c] : 0u;
-            pf_lo = in ? A.e_lo[i + c] : 0u;
-            pf_hi = in ? A.e_hi[i + c] : 0u;
             pf_i = i;
         }
         z_end = fminf(z_next, mz);
@@ -909,25 +917,28 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         nacc = wave_sum(n_acc);
         nrej = wave_sum(n_rej);
     }
-    if (lane == 0) {
-        atomicAdd(cnt + S_RAYS, (unsigned long long)rays);
-        atomicAdd(cnt + S_HITS, (unsigned long long)hits);
-        atomicAdd(cnt + S_UNCONV, (unsigned long long)unc);
-        atomicAdd(cnt + S_EVALS, (unsigned long long)ev);
-        atomicAdd(cnt + S_GEVALS, (unsigned long long)gev);
-        atomicAdd(cnt + S_STEPS, (unsigned long long)st);
-        for (int q = 0; q < 4; q++) atomicAdd(cnt + S_NODE + q, (unsigned long long)node_cnt[q]);
-        for (int q = 0; q < 4; q++) atomicAdd(cnt + S_GNODE + q, (unsigned long long)gnode_cnt[q]);
-        atomicAdd(cnt + S_SUBF, (unsigned long long)n_subf);
-        atomicAdd(cnt + S_EMPTY, (unsigned long long)n_empty);
-        atomicAdd(cnt + S_VIEWN, (unsigned long long)view_nodes);
-        atomicMax(cnt + S_MAXACT, (unsigned long long)max_act);
-        atomicAdd(cnt + S_SMOOTH, (unsigned long long)smt);
-        if constexpr (kRelax) {
-            atomicAdd(cnt + S_ACC, (unsigned long long)nacc);
-            atomicAdd(cnt + S_REJ, (unsigned long long)nrej);
-        }
+    unsigned long long v[kWaveStats] = {};
+    v[S_RAYS] = rays;
+    v[S_HITS] = hits;
+    v[S_UNCONV] = unc;
+    v[S_EVALS] = ev;
+    v[S_GEVALS] = gev;
+    v[S_STEPS] = st;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        v[S_NODE + q] = node_cnt[q];
+        v[S_GNODE + q] = gnode_cnt[q];
     }
+    v[S_SUBF] = n_subf;
+    v[S_EMPTY] = n_empty;
+    v[S_VIEWN] = view_nodes;
+    v[S_MAXACT] = max_act;
+    v[S_WIDE] = A.tile_ovl[tile] > A.ma_fast ? 1u : 0u;
+    v[S_ACC] = nacc;
+    v[S_REJ] = nrej;
+    v[S_STALL] = n_stall;
+    v[S_SMOOTH] = smt;
+    block_counters(A, cnt, job, v);
 }
 
 

@@ -45,12 +45,34 @@ __global__ void __launch_bounds__(64) trace_wide_kernel(TraceArgs A, uint32_t* s
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     for (uint32_t job = blockIdx.x; job < n_wide * spt; job += gridDim.x) {
         uint32_t tile = A.wide[1 + job / spt], sub = job % spt;
-        if (lane_id() == 0) atomicAdd(A.stats + S_WIDE, 1ull);
         trace_block<WaveGlob, KS, SM>(A, S, tile, sub, A.stats, tab);
     }
 }
 
 constexpr int kMaDebug = 1024;
+
+// Sums the blocks' counter records into stats[0..S_COUNT) (S_MAXACT: the
+// maximum); one workgroup per counter.
+__global__ void __launch_bounds__(256) reduce_counters_kernel(const unsigned long long* __restrict__ wrec,
+                                                              uint32_t n_jobs, unsigned long long* __restrict__ stats) {
+    __shared__ unsigned long long part[256];
+    const int c = int(blockIdx.x);
+    unsigned long long acc = 0;
+    for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x) {
+        const unsigned long long x = wrec[size_t(j) * kWaveStats + size_t(c)];
+        acc = c == S_MAXACT ? (x > acc ? x : acc) : acc + x;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (int(threadIdx.x) < o) {
+            const unsigned long long y = part[threadIdx.x + o];
+            part[threadIdx.x] = c == S_MAXACT ? (y > part[threadIdx.x] ? y : part[threadIdx.x]) : part[threadIdx.x] + y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) stats[c] = part[0];
+}
 
 
 template <int KS, int SM>
@@ -81,13 +103,12 @@ void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float*
     A.blob = s->d_blob;
     A.par = s->d_par;
     A.kill = s->d_kill;
-    A.range = reinterpret_cast<const uint2*>(s->d_range);
+    A.kslot = reinterpret_cast<const uint4*>(s->d_kslot);
     A.rmq = s->d_rmq;
     A.n_nodes = uint32_t(s->n_nodes);
     A.tile_off = s->d_tile_off;
+    A.tile_cnt = s->d_tile_cnt;
     A.e_node = s->d_e_node;
-    A.e_lo = s->d_e_lo;
-    A.e_hi = s->d_e_hi;
     A.e_zin = s->d_e_zin;
     A.e_zout = s->d_e_zout;
     A.tile_ovl = s->d_tile_ovl;
@@ -121,7 +142,7 @@ int wide_capacity(const st_scene* s) {
 }
 
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
-                       hipStream_t stream, const DumpTarget* dump) {
+                       hipStream_t stream, const DumpTarget* dump, bool want_stats) {
     TraceArgs A;
     fill_trace_args(s, t, depth, normal, info, A);
     int sm = t.step_mode == ST_STEP_OVERRELAX ? SM_OVER : t.step_mode == ST_STEP_LEARNED ? SM_LEARNED : SM_PLAIN;
@@ -141,6 +162,15 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     uint32_t n_jobs = uint32_t(s->n_tiles) * spt;
     uint32_t nwg = (n_jobs + 3) / 4;
+    // one counter record per block, every one written by its block
+    const size_t rec_bytes = size_t(n_jobs) * kWaveStats * 8u;
+    if (rec_bytes > s->wrec_bytes) {
+        dev_free(s, s->d_wrec, stream);
+        s->d_wrec = dev_alloc(s, rec_bytes, stream);
+        s->wrec_bytes = s->d_wrec ? rec_bytes : 0;
+        if (!s->d_wrec) { set_error("trace: counter record allocation failed"); return ST_E_NOMEM; }
+    }
+    A.wrec = reinterpret_cast<unsigned long long*>(s->d_wrec);
     // evaluation stack: at least the tree depth (views are never deeper)
     const bool shallow = s->depth <= 16;
     uint32_t grid = 0;
@@ -177,6 +207,11 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
         break;
     }
     if (e != hipSuccess) return device_error(e, "trace kernels");
+    if (want_stats) {
+        hipLaunchKernelGGL(reduce_counters_kernel, dim3(S_COUNT), dim3(256), 0, stream, A.wrec, n_jobs, s->d_stats);
+        e = hipGetLastError();
+        if (e != hipSuccess) return device_error(e, "counter reduction");
+    }
     return ST_OK;
 }
 
@@ -190,16 +225,8 @@ __global__ void __launch_bounds__(64) debug_eval_kernel(TraceArgs A, const uint3
     WaveLds<MA>& S = *reinterpret_cast<WaveLds<MA>*>(dyn);
     const int lane = lane_id();
     for (int s = lane; s < n; s += 64) {
-        const uint32_t x = act_sorted[s];
-        const uint32_t xc = min(x, A.n_nodes - 1u);
-        const uint32_t K = A.kill[xc];
-        const uint2 r = K < A.n_nodes ? A.range[K] : make_uint2(0u, 0u);
-        uint32_t lo, hi;
-        kill_partner_range(x, K, r.x, r.y, A.n_nodes, lo, hi);
-        S.act(0)[s] = x;
+        S.act(0)[s] = act_sorted[s];
         S.ze(0)[s] = 0.f;
-        S.olo(0)[s] = lo;
-        S.ohi(0)[s] = hi;
     }
     wave_sync();
     PruneResult pr = build_view(A, S, 0, n);
@@ -240,7 +267,7 @@ st_status debug_eval_device(const st_scene* s, const uint32_t* act_sorted_dev, i
     A.blob = s->d_blob;
     A.par = s->d_par;
     A.kill = s->d_kill;
-    A.range = reinterpret_cast<const uint2*>(s->d_range);
+    A.kslot = reinterpret_cast<const uint4*>(s->d_kslot);
     A.rmq = s->d_rmq;
     A.n_nodes = uint32_t(s->n_nodes);
     if (n > kMaDebug) { set_error("debug_eval: active set larger than 1024"); return ST_E_CAPACITY; }

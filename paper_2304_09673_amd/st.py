@@ -51,7 +51,7 @@ class StTuning(C.Structure):
     _fields_ = [("tile", C.c_int32), ("max_active", C.c_int32), ("sub_depth", C.c_float),
                 ("max_new", C.c_int32), ("eps", C.c_float), ("max_steps", C.c_int32),
                 ("refine_iters", C.c_int32), ("step_mode", C.c_int32), ("omega", C.c_float),
-                ("lipschitz", C.c_float), ("reserved", C.c_int32 * 6)]
+                ("lipschitz", C.c_float), ("keep_all_entries", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class StStats(C.Structure):
@@ -62,7 +62,7 @@ class StStats(C.Structure):
                 ("view_nodes", C.c_uint64), ("abuffer_entries", C.c_uint64), ("max_list", C.c_uint64),
                 ("max_overlap", C.c_uint64), ("max_active", C.c_uint64), ("wide_tiles", C.c_uint64),
                 ("learned_accepted", C.c_uint64), ("learned_rejected", C.c_uint64),
-                ("reserved", C.c_uint64 * 8)]
+                ("abuffer_binned", C.c_uint64), ("reserved", C.c_uint64 * 7)]
 
     def as_dict(self):
         d = {}

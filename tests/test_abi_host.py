@@ -214,6 +214,60 @@ def test_prune_random_larger_trees(seed):
             assert lip == pytest.approx(elip, rel=1e-6)
 
 
+def _kill_filter(sc, active):
+    """The dead-primitive rule of the device view build, written on the tree:
+    a primitive is dropped when some ancestor on its path discards a lone
+    operand from that side (an intersection, or a difference reached from
+    the right) and no active primitive is in the other operand; applied
+    until nothing more drops."""
+    parent = {}
+    for v in range(len(sc.kind)):
+        if sc.kind[v] >= 16:
+            parent[int(sc.left[v])] = (v, 0)
+            parent[int(sc.right[v])] = (v, 1)
+
+    def leaves(v):
+        return [v] if sc.kind[v] < 16 else leaves(int(sc.left[v])) + leaves(int(sc.right[v]))
+
+    act = set(active)
+    while True:
+        keep = set()
+        for x in act:
+            v, alive = x, True
+            while v in parent and alive:
+                pv, side = parent[v]
+                im = IGNORE[int(sc.kind[pv])]
+                kills = (im & 1) if side == 0 else (im & 2)
+                other = int(sc.right[pv]) if side == 0 else int(sc.left[pv])
+                if kills and not act.intersection(leaves(other)):
+                    alive = False
+                v = pv
+            if alive:
+                keep.add(x)
+        if keep == act:
+            return sorted(act)
+        act = keep
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dead_primitive_filter_keeps_the_view(seed):
+    """Dropping the primitives that the kill-chain rule finds dead, to a fixed
+    point, gives the same view as the full active set (the view-build filter
+    changes only the work, never the view)."""
+    rng = np.random.default_rng(500 + seed)
+    dropped = 0
+    for rep in range(40):
+        n = int(rng.integers(5, 30))
+        sc = sg.random_small_tree(seed * 1000 + rep, n, ops=tuple(OPS))
+        prims = np.nonzero(sc.kind < 16)[0]
+        for _ in range(10):
+            active = sorted(int(p) for p in prims if rng.random() < rng.uniform(0.1, 0.9))
+            kept = _kill_filter(sc, active)
+            dropped += len(active) - len(kept)
+            assert _expected(sc, kept) == _expected(sc, active)
+    assert dropped > 0
+
+
 def test_prune_left_comb_union_only_keeps_active_operators():
     """Left comb of unions (Section 7 inset): with k active primitives the
     view holds those k primitives and k-1 operators, never the skipped ones."""

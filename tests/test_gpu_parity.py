@@ -89,7 +89,7 @@ def test_abuffer_covers_every_ray_interval(cfg, tile):
     from paper_2304_09673_amd import st
     sc = sg.config1(0, 128, 128) if cfg == 1 else sg.config2(0, 96, 80)
     s = st.Scene(sc)
-    s.build_abuffer(sc.camera, st.default_tuning(tile=tile))
+    s.build_abuffer(sc.camera, st.default_tuning(tile=tile, keep_all_entries=1))
     off, node, zin, zout = s.debug_abuffer()
     osc = oracle.OracleScene(sc)
     cam = sc.camera
@@ -113,6 +113,77 @@ def test_abuffer_covers_every_ray_interval(cfg, tile):
         seg = slice(off[t], off[t + 1])
         keys = list(zip(zin[seg].tolist(), node[seg].tolist()))
         assert keys == sorted(keys)
+
+
+def _tile_alive(sc, members):
+    """Primitives of a tile's list that survive the dead-primitive rule for
+    the whole list, written on the caller tree: a primitive is dropped when an
+    ancestor on its path discards a lone operand from that side (an
+    intersection, or a difference reached from the right) and no listed
+    primitive is in the other operand; repeated until nothing drops."""
+    parent, leaves = {}, {}
+
+    def collect(v):
+        if sc.kind[v] < 16:
+            leaves[v] = frozenset([v])
+        else:
+            l, r = int(sc.left[v]), int(sc.right[v])
+            parent[l], parent[r] = (v, 0), (v, 1)
+            collect(l)
+            collect(r)
+            leaves[v] = leaves[l] | leaves[r]
+
+    collect(int(sc.root))
+    inter = {sg.INTER, sg.SINTER}
+    diff = {sg.DIFF, sg.SDIFF}
+    cur = set(members)
+    while True:
+        keep = set()
+        for x in cur:
+            v, alive = x, True
+            while v in parent and alive:
+                pv, side = parent[v]
+                k = int(sc.kind[pv])
+                kills = k in inter or (k in diff and side == 1)
+                other = int(sc.right[pv]) if side == 0 else int(sc.left[pv])
+                if kills and leaves[other].isdisjoint(cur):
+                    alive = False
+                v = pv
+            if alive:
+                keep.add(x)
+        if keep == cur:
+            return cur
+        cur = keep
+
+
+@pytest.mark.parametrize("which", ["c2", "c3small"])
+def test_abuffer_pruning_keeps_the_tile_alive_set(which):
+    """Tile-level pruning: each tile keeps exactly the entries of the
+    primitives that survive the dead-primitive rule for the tile's whole
+    binned list, with their depths, in (z_in, primitive) order; bit-exact
+    against the rule evaluated on the host from the unpruned lists."""
+    from paper_2304_09673_amd import st
+    sc = sg.config2(3, 160, 120) if which == "c2" else sg.config3(0, 192, 108, n_prims=512, max_depth=12)
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera, st.default_tuning(tile=16, keep_all_entries=1))
+    off0, node0, zin0, zout0 = s.debug_abuffer()
+    s.build_abuffer(sc.camera, st.default_tuning(tile=16))
+    off1, node1, zin1, zout1 = s.debug_abuffer()
+    assert off0.shape == off1.shape
+    dropped = 0
+    for t in range(off0.shape[0] - 1):
+        a = slice(off0[t], off0[t + 1])
+        full = {int(x): (zi, zo) for x, zi, zo in zip(node0[a], zin0[a].view(np.uint32), zout0[a].view(np.uint32))}
+        alive = _tile_alive(sc, full.keys())
+        b = slice(off1[t], off1[t + 1])
+        kept = [int(x) for x in node1[b]]
+        assert sorted(kept) == sorted(alive), t
+        for x, zi, zo in zip(node1[b], zin1[b].view(np.uint32), zout1[b].view(np.uint32)):
+            assert full[int(x)] == (zi, zo)
+        keys = list(zip(zin1[b].tolist(), node1[b].tolist()))
+        assert keys == sorted(keys)
+        dropped += len(full) - len(kept)
+    assert dropped > 0
 
 
 def test_abuffer_is_deterministic():
