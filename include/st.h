@@ -136,7 +136,8 @@ typedef struct {
     uint64_t wide_tiles;      /* tiles traced on the wide-capacity path */
     uint64_t learned_accepted, learned_rejected;   /* relaxed steps (OVERRELAX, LEARNED) */
     uint64_t abuffer_binned;  /* A-buffer entries before the tile-level pruning */
-    uint64_t reserved[7];
+    uint64_t abuffer_candidates; /* (primitive, tile) pairs tested at binning */
+    uint64_t reserved[6];
 } st_stats;
 
 /* Device memory allocator used for the scene's buffers (e.g. a framework's

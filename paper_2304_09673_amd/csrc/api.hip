@@ -112,6 +112,7 @@ void stats_from_counters(const st_scene* s, const unsigned long long* h, st_stat
     out->reserved[1] = h[22];   // compact operators evaluated on their smooth branch
     out->abuffer_entries = uint64_t(s->n_live);
     out->abuffer_binned = uint64_t(s->n_entries);
+    out->abuffer_candidates = uint64_t(s->n_cand);
     out->max_list = s->max_list;
     out->max_overlap = s->max_overlap;
 }
@@ -232,7 +233,6 @@ void st_scene_destroy(st_scene* s) {
     dev_free(s, s->d_stats, stream);
     dev_free(s, s->d_misc, stream);
     dev_free(s, s->d_mlp, stream);
-    dev_free(s, s->d_cand, stream);
     dev_free(s, s->d_long, stream);
     delete s;
 }
@@ -538,7 +538,7 @@ st_status st_debug_abuffer(const st_scene* s, uint32_t* tile_off, size_t tile_ca
     if (tile_off && tile_cap < size_t(s->n_tiles + 1)) { set_error("abuffer: tile capacity"); return ST_E_CAPACITY; }
     if (entries && entry_cap < 3 * size_t(s->n_live)) { set_error("abuffer: entry capacity"); return ST_E_CAPACITY; }
     // the kept segment of every tile: [tile_off[t], tile_off[t] + tile_cnt[t])
-    const size_t T = size_t(s->n_tiles), E = size_t(s->n_entries);
+    const size_t T = size_t(s->n_tiles), E = size_t(s->n_cand);
     std::vector<uint32_t> off(T + 1), cnt(T), a(E), b(E), c(E);
     hipError_t e = hipMemcpyAsync(off.data(), s->d_tile_off, (T + 1) * 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(cnt.data(), s->d_tile_cnt, T * 4, hipMemcpyDeviceToHost, stream);

@@ -5,20 +5,23 @@
 // tile's 8x8 rays with the volume, keeps the minimum entry and maximum exit
 // depth, and inserts {primitive, z_in, z_out} into the tile's linked list kept
 // sorted by entry depth (Section 6.2).  Here the same per-tile lists are built
-// with data-parallel kernels and no list atomics:
+// with data-parallel kernels, tile-major:
 //   voi      : per primitive, the volume of interest (bound offset by the
 //              range of interest) and a bounding sphere;
 //   rect     : per primitive, the conservative screen rectangle of tiles its
 //              bounding sphere can touch (exact tangent planes of a sphere);
-//   scan     : candidate (primitive, tile) pairs are numbered by prefix sum;
-//   test     : per candidate, the tile's pixel-centre rays are intersected
-//              with the volume; min entry / max exit view depth are kept and
-//              the tile's count incremented when some ray hits;
-//   scan     : tile offsets (CSR);
-//   scatter  : entries written to their tile's segment;
-//   prune    : per tile, entries whose primitive cannot reach the root for
-//              any subset of the tile's list are dropped (not in the paper;
-//              see tile_prune below);
+//   count    : per tile, the number of primitives whose rectangle covers it;
+//   scan     : tile segments (CSR) of candidate slots;
+//   scatter  : every primitive's index written to a slot of each tile of its
+//              rectangle;
+//   test     : per tile, the tile's pixel-centre rays (computed once, held in
+//              registers) are intersected with each candidate's volume; the
+//              minimum entry / maximum exit view depth of the rays that hit
+//              is written in the slot (a miss writes an empty interval);
+//   prune    : per tile, misses are dropped, and so are the entries whose
+//              primitive cannot reach the root for any subset of the tile's
+//              list (not in the paper; see tile_prune below); the kept ones
+//              are compacted to the front of the segment;
 //   sort     : per tile, entries sorted by (z_in, primitive) in LDS (bitonic),
 //              and the tile's largest depth overlap of intervals computed.
 #include <algorithm>
@@ -173,7 +176,7 @@ __device__ __forceinline__ void slope_range(float c, float z, float r, float& lo
 }
 
 __global__ void rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int ts, int tiles_x, int tiles_y,
-                            int4* __restrict__ rect, uint32_t* __restrict__ count) {
+                            int4* __restrict__ rect) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const Voi& v = voi[p];
@@ -185,7 +188,6 @@ __global__ void rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int 
     int i0 = 0, i1 = cam.w - 1, j0 = 0, j1 = cam.h - 1;
     if (cz + r <= 0.f) {  // entirely behind the eye
         rect[p] = make_int4(0, 0, -1, -1);
-        count[p] = 0;
         return;
     }
     if (cz > r * 1.01f + 1e-4f) {
@@ -202,12 +204,10 @@ __global__ void rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int 
     }
     if (i0 > i1 || j0 > j1) {
         rect[p] = make_int4(0, 0, -1, -1);
-        count[p] = 0;
         return;
     }
     int tx0 = i0 / ts, tx1 = i1 / ts, ty0 = j0 / ts, ty1 = j1 / ts;
     rect[p] = make_int4(tx0, ty0, tx1, ty1);
-    count[p] = uint32_t((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -279,72 +279,156 @@ static void exclusive_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* s
 // workgroup per primitive (its volume of interest is workgroup-uniform and
 // read once), one wave per candidate tile in turn, each lane testing
 // ts*ts/64 rays, then a wave min/max of the entry and exit depths
-__global__ void __launch_bounds__(256) test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
-                                                   const uint32_t* __restrict__ cand_off, int P, DevCam cam,
-                                                   int ts, int tiles_x, float2* __restrict__ cz,
-                                                   uint32_t* __restrict__ ctile, uint32_t* __restrict__ tile_count) {
-    const int p = int(blockIdx.x);
-    if (p >= P) return;
-    const int lane = int(threadIdx.x & 63u), w = int(threadIdx.x >> 6);
-    const uint32_t c0 = cand_off[p], cnt = cand_off[p + 1] - c0;
-    const int4 rc = rect[p];
-    const int wr = rc.z - rc.x + 1;
-    const Voi v = voi[p];
-    for (uint32_t l = uint32_t(w); l < cnt; l += 4u) {
-        const int tx = rc.x + int(l % uint32_t(wr)), ty = rc.y + int(l / uint32_t(wr));
+// Dispatch order of tiles: decreasing count (a tile's candidates for the
+// test, its kept entries for the trace).  The work of a tile grows with its
+// count and a launch is set by its slowest workgroups, so the heavy tiles
+// start first and the light ones fill the machine behind them.  One
+// workgroup, counting sort over kOrderBuckets count buckets (counts beyond
+// the last bucket share it); the order within a bucket is whatever the LDS
+// atomics give, which changes only the schedule, not any result.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 4 * kOrderThreads;
+
+__global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_t* __restrict__ tile_cnt,
+                                                                    int n_tiles, uint32_t* __restrict__ order) {
+    __shared__ uint32_t cnt[kOrderBuckets];
+    __shared__ uint32_t part[kOrderThreads];
+    const int tid = int(threadIdx.x);
+    auto bucket = [&](int t) {   // longest first
+        const uint32_t len = tile_cnt[t];
+        return uint32_t(kOrderBuckets - 1) - min(len, uint32_t(kOrderBuckets - 1));
+    };
+    for (int b = tid; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
+    __syncthreads();
+    for (int t = tid; t < n_tiles; t += kOrderThreads) atomicAdd(&cnt[bucket(t)], 1u);
+    __syncthreads();
+    // exclusive scan: four buckets per thread, then an inclusive scan of the
+    // per-thread sums
+    uint32_t c[4], sum = 0;
+    for (int j = 0; j < 4; j++) { c[j] = cnt[4 * tid + j]; sum += c[j]; }
+    part[tid] = sum;
+    __syncthreads();
+    for (int d = 1; d < kOrderThreads; d <<= 1) {
+        uint32_t v = tid >= d ? part[tid - d] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - sum;
+    for (int j = 0; j < 4; j++) { cnt[4 * tid + j] = run; run += c[j]; }
+    __syncthreads();
+    for (int t = tid; t < n_tiles; t += kOrderThreads) order[atomicAdd(&cnt[bucket(t)], 1u)] = uint32_t(t);
+}
+
+// per primitive (one workgroup): one candidate for every tile of its rectangle
+__global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict__ rect, int tiles_x,
+                                                         uint32_t* __restrict__ tile_count) {
+    const int4 rc = rect[blockIdx.x];
+    const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
+    if (w <= 0 || h <= 0) return;
+    for (int k = int(threadIdx.x); k < w * h; k += int(blockDim.x))
+        atomicAdd(tile_count + (rc.y + k / w) * tiles_x + rc.x + k % w, 1u);
+}
+
+// per primitive (one workgroup): its index into a slot of each tile segment
+__global__ void __launch_bounds__(256) cand_scatter_kernel(const int4* __restrict__ rect, int tiles_x,
+                                                           const uint32_t* __restrict__ tile_off,
+                                                           uint32_t* __restrict__ cursor,
+                                                           uint32_t* __restrict__ slot_prim) {
+    const int4 rc = rect[blockIdx.x];
+    const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
+    if (w <= 0 || h <= 0) return;
+    for (int k = int(threadIdx.x); k < w * h; k += int(blockDim.x)) {
+        const int tile = (rc.y + k / w) * tiles_x + rc.x + k % w;
+        slot_prim[tile_off[tile] + atomicAdd(cursor + tile, 1u)] = blockIdx.x;
+    }
+}
+
+// wave reductions over the 64 lanes through DPP row shifts and broadcasts
+// (no LDS round trips); the result is read from lane 63
+__device__ __forceinline__ float dpp_min(float v) {
+    const int inf = __float_as_int(__builtin_inff());
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x111, 0xf, 0xf, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x112, 0xf, 0xf, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x114, 0xf, 0xf, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x118, 0xf, 0xf, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x142, 0xa, 0xf, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x143, 0xc, 0xf, false)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ float dpp_max(float v) {
+    const int ninf = __float_as_int(-__builtin_inff());
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(ninf, __float_as_int(v), 0x111, 0xf, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(ninf, __float_as_int(v), 0x112, 0xf, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(ninf, __float_as_int(v), 0x114, 0xf, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(ninf, __float_as_int(v), 0x118, 0xf, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(ninf, __float_as_int(v), 0x142, 0xa, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(ninf, __float_as_int(v), 0x143, 0xc, 0xf, false)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Per tile (one workgroup of 4 waves): the tile's TS x TS pixel-centre rays,
+// TS^2/64 per lane, are built once; the waves take the tile's candidates in
+// turn and intersect every ray with the candidate's volume of interest.  The
+// slot gets the primitive's node and the padded [min entry, max exit] view
+// depth over the rays that hit, or the empty interval (+inf, -inf).
+// Workgroups take the tiles in the given order (most candidates first: the
+// longest segments start early instead of finishing the frame late).
+template <int TS>
+__global__ void __launch_bounds__(256) tile_test_kernel(const Voi* __restrict__ voi,
+                                                        const uint32_t* __restrict__ tile_off,
+                                                        const uint32_t* __restrict__ order, int tiles_x, DevCam cam,
+                                                        uint32_t* __restrict__ e_node, float* __restrict__ e_zin,
+                                                        float* __restrict__ e_zout) {
+    constexpr int RPL = TS * TS / 64;   // rays per lane
+    const int tile = int(order[blockIdx.x]);
+    const uint32_t e0 = tile_off[tile], n = tile_off[tile + 1] - e0;
+    if (n == 0) return;
+    const int lane = int(threadIdx.x & 63u);
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    float dir[RPL][3], cosv[RPL];
+    bool ok[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; r++) {
+        const int k = lane + 64 * r;
+        const int i = tx * TS + k % TS, j = ty * TS + k / TS;
+        ok[r] = i < cam.w && j < cam.h;
+        const Ray ray = pixel_ray(cam, min(i, cam.w - 1), min(j, cam.h - 1));
+        dir[r][0] = ray.d[0]; dir[r][1] = ray.d[1]; dir[r][2] = ray.d[2];
+        cosv[r] = ray.cosv;
+    }
+    const float o[3] = {cam.eye[0], cam.eye[1], cam.eye[2]};
+    for (uint32_t c = w; c < n; c += 4u) {
+        const uint32_t p = __builtin_amdgcn_readfirstlane(e_node[e0 + c]);
+        const Voi v = voi[p];
         float zmin = __builtin_inff(), zmax = -__builtin_inff();
-        const int i0 = tx * ts, j0 = ty * ts;
-        for (int k = lane; k < ts * ts; k += 64) {
-            const int i = i0 + k % ts, j = j0 + k / ts;
-            if (i >= cam.w || j >= cam.h) continue;
-            Ray r = pixel_ray(cam, i, j);
+#pragma unroll
+        for (int r = 0; r < RPL; r++) {
             float t0, t1;
-            if (ray_voi(v, r.o, r.d, t0, t1) && t1 >= 0.f) {
+            if (ok[r] && ray_voi(v, o, dir[r], t0, t1) && t1 >= 0.f) {
                 t0 = fmaxf(t0, 0.f);
-                zmin = fminf(zmin, t0 * r.cosv);
-                zmax = fmaxf(zmax, t1 * r.cosv);
+                zmin = fminf(zmin, t0 * cosv[r]);
+                zmax = fmaxf(zmax, t1 * cosv[r]);
             }
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            zmin = fminf(zmin, __shfl_xor(zmin, o));
-            zmax = fmaxf(zmax, __shfl_xor(zmax, o));
-        }
+        zmin = dpp_min(zmin);
+        zmax = dpp_max(zmax);
         if (lane == 0) {
-            const uint32_t c = c0 + l;
-            const uint32_t tile = uint32_t(ty * tiles_x + tx);
+            e_node[e0 + c] = __float_as_uint(v.v[21]);
             if (zmin <= zmax) {
                 // conservative padding for FP32 rounding of the intervals
-                float pad = 2e-5f * fmaxf(fabsf(zmax), 1.0f);
-                cz[c] = make_float2(fmaxf(zmin - pad, 0.f), zmax + pad);
-                ctile[c] = tile;
-                atomicAdd(tile_count + tile, 1u);
+                const float pad = 2e-5f * fmaxf(fabsf(zmax), 1.0f);
+                e_zin[e0 + c] = fmaxf(zmin - pad, 0.f);
+                e_zout[e0 + c] = zmax + pad;
             } else {
-                ctile[c] = 0xFFFFFFFFu;
+                e_zin[e0 + c] = __builtin_inff();
+                e_zout[e0 + c] = -__builtin_inff();
             }
         }
     }
 }
 
-__global__ void scatter_kernel(const Voi* __restrict__ voi, const uint32_t* __restrict__ cand_off, int P,
-                               uint32_t n_cand, const float2* __restrict__ cz, const uint32_t* __restrict__ ctile,
-                               const uint32_t* __restrict__ tile_off, uint32_t* __restrict__ cursor,
-                               uint32_t* __restrict__ e_node, float* __restrict__ e_zin,
-                               float* __restrict__ e_zout) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cand) return;
-    uint32_t tile = ctile[c];
-    if (tile == 0xFFFFFFFFu) return;
-    int lo = 0, hi = P - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (cand_off[mid] <= c) lo = mid; else hi = mid - 1;
-    }
-    uint32_t pos = tile_off[tile] + atomicAdd(cursor + tile, 1u);
-    float2 z = cz[c];
-    e_node[pos] = __float_as_uint(voi[lo].v[21]);
-    e_zin[pos] = z.x;
-    e_zout[pos] = z.y;
-}
 
 // ---------------------------------------------------------------------------
 // per-tile sort by (z_in, node) and largest depth overlap
@@ -484,23 +568,35 @@ __device__ int block_rank(bool keep, int* total) {
     return before + int(lanes_below_mask(mk));
 }
 
-// Prunes the list [e0, e0 + n) in place; a (2^ceil(log2 n) words), b (n
-// words) and tab (2^bits words, 2^bits >= 2n) are scratch.  Returns the
-// number of entries kept.
+// Compacts the candidate segment [e0, e0 + n) in place to the entries that
+// hit (non-empty interval) and, unless keep_all, whose primitive survives the
+// rule for the set of hits; a (2^ceil(log2 n) words), b (n words) and tab
+// (2^bits words, 2^bits >= 2n) are scratch.  Returns the number kept; *hits
+// gets the number of hits.
 __device__ int prune_tile(uint32_t e0, int n, uint32_t* e_node, float* e_zin, float* e_zout, uint32_t* a,
                           uint32_t* b, uint32_t* tab, int bits, const uint32_t* __restrict__ rmq,
-                          const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes) {
+                          const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes,
+                          bool keep_all, int* hits) {
     const int tid = int(threadIdx.x);
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
-    for (int i = tid; i < np2; i += kPruneThreads) a[i] = i < n ? e_node[e0 + i] : 0xFFFFFFFFu;
+    // the primitives that hit, sorted (misses and padding sort last)
+    int m = 0;   // primitives are distinct within a tile's segment
+    for (int c = 0; c < np2; c += kPruneThreads) {
+        const int i = c + tid;
+        const bool hit = i < n && e_zin[e0 + i] <= e_zout[e0 + i];
+        if (i < np2) a[i] = hit ? e_node[e0 + i] : 0xFFFFFFFFu;
+        int tot;
+        block_rank(hit, &tot);
+        m += tot;
+    }
+    *hits = m;
     __threadfence_block();
     __syncthreads();
-    bitonic_wg(a, (uint32_t*)nullptr, np2);
+    if (!keep_all) bitonic_wg(a, (uint32_t*)nullptr, np2);
     uint32_t* cur = a;
     uint32_t* nxt = b;
-    int m = n;   // primitives are distinct within a tile's list
-    for (int round = 0; round < 32 && m > 0; round++) {
+    for (int round = 0; round < 32 && m > 0 && !keep_all; round++) {
         for (int i = tid; i < (1 << bits); i += kPruneThreads) tab[i] = kNoKill;
         __threadfence_block();
         __syncthreads();
@@ -532,19 +628,21 @@ __device__ int prune_tile(uint32_t e0, int n, uint32_t* e_node, float* e_zin, fl
     }
     // the survivors, as a hash set; then the entries, compacted in place in
     // their order (each chunk is read whole before any of it is written)
-    for (int i = tid; i < (1 << bits); i += kPruneThreads) tab[i] = kNoKill;
-    __threadfence_block();
-    __syncthreads();
-    for (int i = tid; i < m; i += kPruneThreads) hinsert(tab, bits, cur[i]);
-    __threadfence_block();
-    __syncthreads();
+    if (!keep_all) {
+        for (int i = tid; i < (1 << bits); i += kPruneThreads) tab[i] = kNoKill;
+        __threadfence_block();
+        __syncthreads();
+        for (int i = tid; i < m; i += kPruneThreads) hinsert(tab, bits, cur[i]);
+        __threadfence_block();
+        __syncthreads();
+    }
     int kept = 0;
     for (int c = 0; c < n; c += kPruneThreads) {
         const int i = c + tid;
         const bool in = i < n;
         const uint32_t x = in ? e_node[e0 + i] : 0u;
         const float zi = in ? e_zin[e0 + i] : 0.f, zo = in ? e_zout[e0 + i] : 0.f;
-        const bool keep = in && m > 0 && hfind(tab, bits, x, tab[hslot(x, bits)]);
+        const bool keep = in && zi <= zo && (keep_all || (m > 0 && hfind(tab, bits, x, tab[hslot(x, bits)])));
         int tot;
         const int r = block_rank(keep, &tot);   // its barriers separate the reads from the writes
         if (keep) {
@@ -575,16 +673,21 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
     if (tile >= n_tiles) return;
     const uint32_t e0 = tile_off[tile];
     const int n = int(tile_off[tile + 1] - e0);
-    if (keep_all || n == 0) {
-        if (threadIdx.x == 0) tile_cnt[tile] = uint32_t(n);
+    if (n == 0) {
+        if (threadIdx.x == 0) tile_cnt[tile] = 0u;
         return;
     }
     if (n > kPruneLdsCap) {
         if (threadIdx.x == 0) long_list[atomicAdd(misc + 5, 1u)] = uint32_t(tile);
         return;
     }
-    const int kept = prune_tile(e0, n, e_node, e_zin, e_zout, a, b, tab, prune_bits(n), rmq, kslot, kill, n_nodes);
-    if (threadIdx.x == 0) tile_cnt[tile] = uint32_t(kept);
+    int hits;
+    const int kept = prune_tile(e0, n, e_node, e_zin, e_zout, a, b, tab, prune_bits(n), rmq, kslot, kill, n_nodes,
+                                keep_all != 0, &hits);
+    if (threadIdx.x == 0) {
+        tile_cnt[tile] = uint32_t(kept);
+        if (hits) atomicAdd(misc + 6, uint32_t(hits));
+    }
 }
 
 // long lists: scratch in global memory, 7 words per entry of the segment
@@ -593,16 +696,20 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_long_kernel(
         const uint32_t* __restrict__ tile_off, uint32_t* e_node, float* e_zin, float* e_zout,
         uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ long_list, const uint32_t* __restrict__ misc,
         uint32_t* scratch, const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot,
-        const uint32_t* __restrict__ kill, uint32_t n_nodes) {
+        const uint32_t* __restrict__ kill, uint32_t n_nodes, int keep_all, uint32_t* __restrict__ hits_total) {
     const uint32_t n_long = misc[5];
     for (uint32_t idx = blockIdx.x; idx < n_long; idx += gridDim.x) {
         const uint32_t tile = long_list[idx];
         const uint32_t e0 = tile_off[tile];
         const int n = int(tile_off[tile + 1] - e0);
         uint32_t* base = scratch + size_t(7) * e0;
+        int hits;
         const int kept = prune_tile(e0, n, e_node, e_zin, e_zout, base, base + 2 * n, base + 3 * n, prune_bits(n),
-                                    rmq, kslot, kill, n_nodes);
-        if (threadIdx.x == 0) tile_cnt[tile] = uint32_t(kept);
+                                    rmq, kslot, kill, n_nodes, keep_all != 0, &hits);
+        if (threadIdx.x == 0) {
+            tile_cnt[tile] = uint32_t(kept);
+            if (hits) atomicAdd(hits_total, uint32_t(hits));
+        }
         __syncthreads();
     }
 }
@@ -668,46 +775,6 @@ __global__ void __launch_bounds__(kSortThreads) tile_sort_long_kernel(
     }
 }
 
-// Dispatch order of the tiles: decreasing A-buffer list length (after pruning).  The work of
-// a tile's blocks grows with the number of depth intervals its rays cross,
-// and a frame is set by its slowest blocks, so the heavy tiles are started
-// first and the light ones fill the machine behind them.  One workgroup,
-// counting sort over kOrderBuckets length buckets (lengths beyond the last
-// bucket share it); the order within a bucket is whatever the LDS atomics
-// give, which changes only the schedule, not any result.
-constexpr int kOrderThreads = 1024;
-constexpr int kOrderBuckets = 4 * kOrderThreads;
-
-__global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_t* __restrict__ tile_cnt,
-                                                                    int n_tiles, uint32_t* __restrict__ order) {
-    __shared__ uint32_t cnt[kOrderBuckets];
-    __shared__ uint32_t part[kOrderThreads];
-    const int tid = int(threadIdx.x);
-    auto bucket = [&](int t) {   // longest first
-        const uint32_t len = tile_cnt[t];
-        return uint32_t(kOrderBuckets - 1) - min(len, uint32_t(kOrderBuckets - 1));
-    };
-    for (int b = tid; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
-    __syncthreads();
-    for (int t = tid; t < n_tiles; t += kOrderThreads) atomicAdd(&cnt[bucket(t)], 1u);
-    __syncthreads();
-    // exclusive scan: four buckets per thread, then an inclusive scan of the
-    // per-thread sums
-    uint32_t c[4], sum = 0;
-    for (int j = 0; j < 4; j++) { c[j] = cnt[4 * tid + j]; sum += c[j]; }
-    part[tid] = sum;
-    __syncthreads();
-    for (int d = 1; d < kOrderThreads; d <<= 1) {
-        uint32_t v = tid >= d ? part[tid - d] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[tid] - sum;
-    for (int j = 0; j < 4; j++) { cnt[4 * tid + j] = run; run += c[j]; }
-    __syncthreads();
-    for (int t = tid; t < n_tiles; t += kOrderThreads) order[atomicAdd(&cnt[bucket(t)], 1u)] = uint32_t(t);
-}
 
 // ---------------------------------------------------------------------------
 st_status launch_voi(st_scene* s, hipStream_t stream) {
@@ -739,14 +806,12 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     const int P = s->n_prims;
     const int T = s->n_tiles;
     const int ts = t.tile;
-    // scratch layout (bytes): rect P*16, count P*4, cand_off (P+1)*4, scan sums, tile_count T*4,
-    // cursor T*4, long list T*4, misc 16*4
-    size_t nb_p = size_t(P + kScanBlock) / kScanBlock + 2, nb_t = size_t(T + kScanBlock) / kScanBlock + 2;
+    // scratch layout (bytes): rect P*16, scan sums, tile counts (T+1)*4,
+    // cursors T*4, long list T*4, misc 64*4
+    size_t nb_t = size_t(T + kScanBlock) / kScanBlock + 2;
     size_t off_rect = 0;
-    size_t off_count = align_up(off_rect + size_t(P) * 16);
-    size_t off_coff = align_up(off_count + size_t(P) * 4);
-    size_t off_sums = align_up(off_coff + size_t(P + 1) * 4);
-    size_t off_tcnt = align_up(off_sums + std::max(nb_p, nb_t) * 4 + 16);
+    size_t off_sums = align_up(off_rect + size_t(P) * 16);
+    size_t off_tcnt = align_up(off_sums + nb_t * 4 + 16);
     size_t off_cur = align_up(off_tcnt + size_t(T + 1) * 4);
     size_t off_long = align_up(off_cur + size_t(T) * 4);
     size_t off_misc = align_up(off_long + size_t(T) * 4);
@@ -763,8 +828,6 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     }
     char* base = (char*)s->d_scratch;
     int4* rect = (int4*)(base + off_rect);
-    uint32_t* count = (uint32_t*)(base + off_count);
-    uint32_t* coff = (uint32_t*)(base + off_coff);
     uint32_t* sums = (uint32_t*)(base + off_sums);
     uint32_t* tcnt = (uint32_t*)(base + off_tcnt);
     uint32_t* cur = (uint32_t*)(base + off_cur);
@@ -774,46 +837,24 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
 #define ST_CHECK(x, what) do { e = (x); if (e != hipSuccess) return device_error(e, what); } while (0)
 
     hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
-                       s->tiles_x, s->tiles_y, rect, count);
-    exclusive_scan(count, coff, P, sums, misc + 8, coff + P, stream);
+                       s->tiles_x, s->tiles_y, rect);
+    ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
+    ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
+    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, rect, s->tiles_x, tcnt);
+    exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_cand = replay ? s->n_cand : 0u;
     if (!replay) {
-        ST_CHECK(hipMemcpyAsync(&n_cand, misc + 8, 4, hipMemcpyDeviceToHost, stream), "copy candidate count");
+        ST_CHECK(hipMemcpyAsync(&n_cand, misc + 9, 4, hipMemcpyDeviceToHost, stream), "copy candidate count");
         ST_CHECK(hipStreamSynchronize(stream), "sync (candidates)");
         s->n_cand = n_cand;
     }
 
-    // candidate results: z pair + tile id
-    size_t cand_bytes = align_up(size_t(n_cand) * 8) + align_up(size_t(n_cand) * 4) + 256;
-    if (cand_bytes > s->cand_bytes) {   // kept between builds, grown on demand
-        dev_free(s, s->d_cand, stream);
-        s->d_cand = dev_alloc(s, cand_bytes + cand_bytes / 4, stream);
-        s->cand_bytes = s->d_cand ? cand_bytes + cand_bytes / 4 : 0;
-        if (!s->d_cand) { set_error("build: candidate buffer allocation failed"); return ST_E_NOMEM; }
-    }
-    char* cbuf = (char*)s->d_cand;
-    float2* cz = (float2*)cbuf;
-    uint32_t* ctile = (uint32_t*)(cbuf + align_up(size_t(n_cand) * 8));
-
-    ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
-    ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
-    if (n_cand)
-        hipLaunchKernelGGL(test_kernel, dim3(P), dim3(256), 0, stream, s->d_voi, rect, coff, P, s->dcam, ts,
-                           s->tiles_x, cz, ctile, tcnt);
-    exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
-    uint32_t n_ent = replay ? uint32_t(s->n_entries) : 0u;
-    if (!replay) {
-        ST_CHECK(hipMemcpyAsync(&n_ent, misc + 9, 4, hipMemcpyDeviceToHost, stream), "copy entry count");
-        ST_CHECK(hipStreamSynchronize(stream), "sync (entries)");
-        s->n_entries = n_ent;
-    }
-
-    // entry arrays (grown on demand) + long-sort scratch
-    if (int64_t(n_ent) > s->ab_cap) {
+    // candidate slots = entry arrays (grown on demand)
+    if (int64_t(n_cand) > s->ab_cap) {
         dev_free(s, s->d_e_node, stream);
         dev_free(s, s->d_e_zin, stream);
         dev_free(s, s->d_e_zout, stream);
-        int64_t cap = std::max<int64_t>(int64_t(n_ent) + int64_t(n_ent) / 4, 1024);
+        int64_t cap = std::max<int64_t>(int64_t(n_cand) + int64_t(n_cand) / 4, 1024);
         s->d_e_node = (uint32_t*)dev_alloc(s, size_t(cap) * 4, stream);
         s->d_e_zin = (float*)dev_alloc(s, size_t(cap) * 4, stream);
         s->d_e_zout = (float*)dev_alloc(s, size_t(cap) * 4, stream);
@@ -825,9 +866,22 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         s->ab_cap = cap;
     }
     ST_CHECK(fill_u32(cur, uint32_t(T), 0u, stream), "clear cursors");
-    if (n_cand)
-        hipLaunchKernelGGL(scatter_kernel, dim3((n_cand + 255) / 256), dim3(256), 0, stream, s->d_voi, coff, P,
-                           n_cand, cz, ctile, s->d_tile_off, cur, s->d_e_node, s->d_e_zin, s->d_e_zout);
+    if (P && n_cand) {
+        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, rect, s->tiles_x, s->d_tile_off, cur,
+                           s->d_e_node);
+        // test order by candidate count (the trace order is made after pruning)
+        hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, tcnt, T, s->d_tile_order);
+        if (ts == 8)
+            hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T), dim3(256), 0, stream, s->d_voi, s->d_tile_off,
+                               s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
+        else if (ts == 16)
+            hipLaunchKernelGGL(tile_test_kernel<16>, dim3(T), dim3(256), 0, stream, s->d_voi, s->d_tile_off,
+                               s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
+        else
+            hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T), dim3(256), 0, stream, s->d_voi, s->d_tile_off,
+                               s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
+    }
+    const uint32_t n_ent = n_cand;   // slots the pruning and the sorts work on
     // scratch of the long lists (pruning: 7 words per entry; sorting: 2
     // padded copies of key, value and exit depth, 16 bytes per entry each)
     size_t long_bytes = size_t(2) * n_ent * (8 + 4 + 4) + 64;
@@ -846,7 +900,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipLaunchKernelGGL(tile_prune_long_kernel, dim3(std::min(T, 512)), dim3(kPruneThreads), 0, stream,
                        s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc,
                        reinterpret_cast<uint32_t*>(lbuf), s->d_rmq, reinterpret_cast<const uint4*>(s->d_kslot),
-                       s->d_kill, uint32_t(s->n_nodes));
+                       s->d_kill, uint32_t(s->n_nodes), t.keep_all_entries, misc + 6);
     ST_CHECK(fill_u32(s->d_wide, 1u, 0u, stream), "clear wide list");
     hipLaunchKernelGGL(tile_sort_kernel, dim3(T), dim3(kSortThreads), 0, stream, s->d_tile_off, s->d_tile_cnt, T,
                        s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, uint32_t(s->ab_ma_fast),
@@ -864,8 +918,8 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         e = hipGetLastError();
         return e == hipSuccess ? ST_OK : device_error(e, "binning kernels");
     }
-    uint32_t h_misc[4] = {0, 0, 0, 0}, h_wide = 0;
-    ST_CHECK(hipMemcpyAsync(h_misc, misc, 16, hipMemcpyDeviceToHost, stream), "copy build stats");
+    uint32_t h_misc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, h_wide = 0;
+    ST_CHECK(hipMemcpyAsync(h_misc, misc, 32, hipMemcpyDeviceToHost, stream), "copy build stats");
     ST_CHECK(hipMemcpyAsync(&h_wide, s->d_wide, 4, hipMemcpyDeviceToHost, stream), "copy wide count");
     e = hipGetLastError();
     if (e != hipSuccess) return device_error(e, "binning kernels");
@@ -873,6 +927,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     s->max_overlap = h_misc[1];
     s->max_list = h_misc[2];
     s->n_live = h_misc[3];
+    s->n_entries = h_misc[6];   // candidates that hit
     s->n_wide = h_wide;
 #undef ST_CHECK
     return ST_OK;

@@ -69,8 +69,6 @@ struct st_scene {
     // scratch kept between builds
     void* d_scratch = nullptr;
     size_t scratch_bytes = 0;
-    void* d_cand = nullptr;     // candidate (primitive, tile) results
-    size_t cand_bytes = 0;
     void* d_long = nullptr;     // sort scratch of long tile lists
     size_t long_bytes = 0;
 

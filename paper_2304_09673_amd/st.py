@@ -62,7 +62,7 @@ class StStats(C.Structure):
                 ("view_nodes", C.c_uint64), ("abuffer_entries", C.c_uint64), ("max_list", C.c_uint64),
                 ("max_overlap", C.c_uint64), ("max_active", C.c_uint64), ("wide_tiles", C.c_uint64),
                 ("learned_accepted", C.c_uint64), ("learned_rejected", C.c_uint64),
-                ("abuffer_binned", C.c_uint64), ("reserved", C.c_uint64 * 7)]
+                ("abuffer_binned", C.c_uint64), ("abuffer_candidates", C.c_uint64), ("reserved", C.c_uint64 * 6)]
 
     def as_dict(self):
         d = {}
