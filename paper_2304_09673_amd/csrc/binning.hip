@@ -175,21 +175,18 @@ __device__ __forceinline__ void slope_range(float c, float z, float r, float& lo
     hi = (c * z + sq) / den;
 }
 
-__global__ void rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int ts, int tiles_x, int tiles_y,
-                            int4* __restrict__ rect) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const Voi& v = voi[p];
+// Conservative pixel rectangle [i0, i1] x [j0, j1] (clamped to the image) of
+// the pixel-centre rays that can meet a bounding sphere: exact tangent lines
+// through the eye, one pixel of margin; the whole image when the sphere
+// reaches the eye plane; false when it lies behind the eye or off screen.
+__device__ __forceinline__ bool sphere_pixels(const Voi& v, const DevCam& cam, int& i0, int& i1, int& j0, int& j1) {
     float rx = v.v[0] - cam.eye[0], ry = v.v[1] - cam.eye[1], rz = v.v[2] - cam.eye[2];
     float cx = rx * cam.right[0] + ry * cam.right[1] + rz * cam.right[2];
     float cy = rx * cam.up[0] + ry * cam.up[1] + rz * cam.up[2];
     float cz = rx * cam.fwd[0] + ry * cam.fwd[1] + rz * cam.fwd[2];
     float r = v.v[3] * 1.001f + 1e-5f;
-    int i0 = 0, i1 = cam.w - 1, j0 = 0, j1 = cam.h - 1;
-    if (cz + r <= 0.f) {  // entirely behind the eye
-        rect[p] = make_int4(0, 0, -1, -1);
-        return;
-    }
+    i0 = 0; i1 = cam.w - 1; j0 = 0; j1 = cam.h - 1;
+    if (cz + r <= 0.f) return false;   // entirely behind the eye
     if (cz > r * 1.01f + 1e-4f) {
         float xl, xh, yl, yh;
         slope_range(cx, cz, r, xl, xh);
@@ -202,12 +199,21 @@ __global__ void rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int 
         j0 = max(j0, int(floorf(vl - 0.5f)) - 1);
         j1 = min(j1, int(ceilf(vh - 0.5f)) + 1);
     }
-    if (i0 > i1 || j0 > j1) {
-        rect[p] = make_int4(0, 0, -1, -1);
-        return;
-    }
-    int tx0 = i0 / ts, tx1 = i1 / ts, ty0 = j0 / ts, ty1 = j1 / ts;
-    rect[p] = make_int4(tx0, ty0, tx1, ty1);
+    return i0 <= i1 && j0 <= j1;
+}
+
+// per primitive: the pixel rectangle (i0, j0, i1, j1) of its bounding
+// sphere, empty (0, 0, -1, -1) when no pixel-centre ray can meet it
+__global__ void rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int4* __restrict__ rect) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    int i0, i1, j0, j1;
+    rect[p] = sphere_pixels(voi[p], cam, i0, i1, j0, j1) ? make_int4(i0, j0, i1, j1) : make_int4(0, 0, -1, -1);
+}
+
+// tiles (tx0, ty0, tx1, ty1) of a pixel rectangle
+__device__ __forceinline__ int4 rect_tiles(int4 pr, int ts) {
+    return pr.z < pr.x ? make_int4(0, 0, -1, -1) : make_int4(pr.x / ts, pr.y / ts, pr.z / ts, pr.w / ts);
 }
 
 // ---------------------------------------------------------------------------
@@ -321,9 +327,9 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
 }
 
 // per primitive (one workgroup): one candidate for every tile of its rectangle
-__global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict__ rect, int tiles_x,
+__global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict__ rect, int ts, int tiles_x,
                                                          uint32_t* __restrict__ tile_count) {
-    const int4 rc = rect[blockIdx.x];
+    const int4 rc = rect_tiles(rect[blockIdx.x], ts);
     const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
     if (w <= 0 || h <= 0) return;
     for (int k = int(threadIdx.x); k < w * h; k += int(blockDim.x))
@@ -331,11 +337,11 @@ __global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict_
 }
 
 // per primitive (one workgroup): its index into a slot of each tile segment
-__global__ void __launch_bounds__(256) cand_scatter_kernel(const int4* __restrict__ rect, int tiles_x,
+__global__ void __launch_bounds__(256) cand_scatter_kernel(const int4* __restrict__ rect, int ts, int tiles_x,
                                                            const uint32_t* __restrict__ tile_off,
                                                            uint32_t* __restrict__ cursor,
                                                            uint32_t* __restrict__ slot_prim) {
-    const int4 rc = rect[blockIdx.x];
+    const int4 rc = rect_tiles(rect[blockIdx.x], ts);
     const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
     if (w <= 0 || h <= 0) return;
     for (int k = int(threadIdx.x); k < w * h; k += int(blockDim.x)) {
@@ -367,15 +373,17 @@ __device__ __forceinline__ float dpp_max(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Per tile (one workgroup of 4 waves): the tile's TS x TS pixel-centre rays,
-// TS^2/64 per lane, are built once; the waves take the tile's candidates in
-// turn and intersect every ray with the candidate's volume of interest.  The
-// slot gets the primitive's node and the padded [min entry, max exit] view
-// depth over the rays that hit, or the empty interval (+inf, -inf).
-// Workgroups take the tiles in the given order (most candidates first: the
-// longest segments start early instead of finishing the frame late).
+// Per tile (one workgroup of 4 waves): the tile's TS x TS pixel-centre rays
+// are built once, one 8x8 block of them per lane-slot (TS^2/64 per lane); the
+// waves take the tile's candidates in turn and intersect every ray with the
+// candidate's volume of interest, skipping the 8x8 blocks outside the pixel
+// rectangle of its bounding sphere.  The slot gets the primitive's node and
+// the padded [min entry, max exit] view depth over the rays that hit, or the
+// empty interval (+inf, -inf).  Workgroups take the tiles in the given order
+// (most candidates first: the longest segments start early instead of
+// finishing the frame late).
 template <int TS>
-__global__ void __launch_bounds__(256) tile_test_kernel(const Voi* __restrict__ voi,
+__global__ void __launch_bounds__(256) tile_test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
                                                         const uint32_t* __restrict__ tile_off,
                                                         const uint32_t* __restrict__ order, int tiles_x, DevCam cam,
                                                         uint32_t* __restrict__ e_node, float* __restrict__ e_zin,
@@ -389,10 +397,10 @@ __global__ void __launch_bounds__(256) tile_test_kernel(const Voi* __restrict__ 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     float dir[RPL][3], cosv[RPL];
     bool ok[RPL];
+    constexpr int BX = TS / 8;   // 8x8 blocks per tile row
 #pragma unroll
     for (int r = 0; r < RPL; r++) {
-        const int k = lane + 64 * r;
-        const int i = tx * TS + k % TS, j = ty * TS + k / TS;
+        const int i = tx * TS + (r % BX) * 8 + (lane & 7), j = ty * TS + (r / BX) * 8 + (lane >> 3);
         ok[r] = i < cam.w && j < cam.h;
         const Ray ray = pixel_ray(cam, min(i, cam.w - 1), min(j, cam.h - 1));
         dir[r][0] = ray.d[0]; dir[r][1] = ray.d[1]; dir[r][2] = ray.d[2];
@@ -403,8 +411,11 @@ __global__ void __launch_bounds__(256) tile_test_kernel(const Voi* __restrict__ 
         const uint32_t p = __builtin_amdgcn_readfirstlane(e_node[e0 + c]);
         const Voi v = voi[p];
         float zmin = __builtin_inff(), zmax = -__builtin_inff();
+        const int4 pr = rect[p];   // the candidate's pixel rectangle
 #pragma unroll
         for (int r = 0; r < RPL; r++) {
+            const int bi = tx * TS + (r % BX) * 8, bj = ty * TS + (r / BX) * 8;
+            if (bi + 7 < pr.x || bi > pr.z || bj + 7 < pr.y || bj > pr.w) continue;   // uniform
             float t0, t1;
             if (ok[r] && ray_voi(v, o, dir[r], t0, t1) && t1 >= 0.f) {
                 t0 = fmaxf(t0, 0.f);
@@ -836,11 +847,10 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipError_t e;
 #define ST_CHECK(x, what) do { e = (x); if (e != hipSuccess) return device_error(e, what); } while (0)
 
-    hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
-                       s->tiles_x, s->tiles_y, rect);
+    hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, rect);
     ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
     ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
-    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, rect, s->tiles_x, tcnt);
+    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, rect, ts, s->tiles_x, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_cand = replay ? s->n_cand : 0u;
     if (!replay) {
@@ -867,18 +877,18 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     }
     ST_CHECK(fill_u32(cur, uint32_t(T), 0u, stream), "clear cursors");
     if (P && n_cand) {
-        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, rect, s->tiles_x, s->d_tile_off, cur,
-                           s->d_e_node);
+        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, rect, ts, s->tiles_x, s->d_tile_off,
+                           cur, s->d_e_node);
         // test order by candidate count (the trace order is made after pruning)
         hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, tcnt, T, s->d_tile_order);
         if (ts == 8)
-            hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T), dim3(256), 0, stream, s->d_voi, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         else if (ts == 16)
-            hipLaunchKernelGGL(tile_test_kernel<16>, dim3(T), dim3(256), 0, stream, s->d_voi, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<16>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         else
-            hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T), dim3(256), 0, stream, s->d_voi, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
     }
     const uint32_t n_ent = n_cand;   // slots the pruning and the sorts work on

@@ -9,8 +9,11 @@ namespace st {
 // ---------------------------------------------------------------------------
 // Fast path: one wave per 8x8 block, 4 waves per workgroup, LDS view of
 // capacity MA.  Blocks of tiles that overlap more than MA go to the wide path.
+// At least 3 waves per SIMD: the deep-tree and learned-step instances would
+// otherwise take more than 170 registers and run 1 or 2 waves per SIMD; the
+// few spills this costs are cheaper than the lost latency hiding.
 template <int MA, int KS, int SM>
-__global__ void __launch_bounds__(256) trace_fast_kernel(TraceArgs A, uint32_t n_jobs) {
+__global__ void __launch_bounds__(256, 3) trace_fast_kernel(TraceArgs A, uint32_t n_jobs) {
     __shared__ WaveLds<MA> lds[4];
     const int w = threadIdx.x >> 6;
     const uint32_t* tab = nullptr;
