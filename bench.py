@@ -32,32 +32,43 @@ SMOOTH_EXTRA = 20
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector, packed
 PEAK_FP32_NONPACKED = 78.6e12
 
-# HBM traffic of the trace kernel, measured with rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters and calibrated against a copy kernel of known size; it is
-# reported only while the kernel sources hash to what was measured.
-TRAFFIC_FILE = ROOT / "profiles" / "trace_c3_traffic.md"
-TRACE_SOURCES = ["trace.hip", "st_trace.h", "st_field.h", "st_prune.h", "st_common.h", "st_mlp.h"]
+# FP32 FLOPs of one ray / volume-of-interest test in the binning's tile test
+# (same counting rules; only the work that depends on the ray direction: the
+# per-candidate terms are computed once per candidate), including the update
+# of the interval (clamp, two depth products, min, max): sphere, box (three
+# slabs), capsule (two end spheres and the cylinder).
+FLOPS_TEST = {"sphere": 25, "box": 38, "capsule": 96}
+
+# HBM traffic of a kernel, measured with rocprofv3 FETCH_SIZE and WRITE_SIZE
+# counters and calibrated against a copy kernel of known size; it is reported
+# only while the kernel's sources hash to what was measured.
+TRAFFIC = {
+    "trace": (ROOT / "profiles" / "trace_c3_traffic.md",
+              ["trace.hip", "st_trace.h", "st_field.h", "st_prune.h", "st_common.h", "st_mlp.h"]),
+    "tile_test": (ROOT / "profiles" / "tile_test_c3_traffic.md", ["binning.hip", "st_common.h", "st_internal.h"]),
+}
 
 
-def trace_source_hash() -> str:
+def source_hash(names) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in TRACE_SOURCES:
+    for name in names:
         h.update((ROOT / "paper_2304_09673_amd" / "csrc" / name).read_bytes())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Bytes per trace launch from the committed counter summary, or None."""
-    if not TRAFFIC_FILE.exists():
+def measured_traffic(kernel: str):
+    """Bytes per launch of the kernel from its committed counter summary, or None."""
+    path, sources = TRAFFIC[kernel]
+    if not path.exists():
         return None
     kv = {}
-    for line in TRAFFIC_FILE.read_text().splitlines():
+    for line in path.read_text().splitlines():
         line = line.strip().lstrip("-* ")
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip().strip("`")] = v.strip().strip("`")
-    if kv.get("trace_source_sha256") != trace_source_hash():
+    if kv.get("source_sha256") != source_hash(sources):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -314,11 +325,16 @@ def main():
 
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
+    # the library records a HIP event pair around every tile-test launch, on
+    # the build stream
+    scene.kernel_timing(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(ev=evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    test_total_ms, test_launches = scene.kernel_timing(False)
+    test_ms_avg = test_total_ms / max(test_launches, 1)
     ms_per_step = wall / args.steps * 1e3
     trace_ms = [a.elapsed_time(b) for a, b in evs]
     trace_ms_avg = float(np.mean(trace_ms))
@@ -329,6 +345,21 @@ def main():
     evals_per_s = stats["field_evals"] / (trace_ms_avg * 1e-3)
     flops = algorithmic_flops(stats)
     achieved = flops / (trace_ms_avg * 1e-3)
+    pix = stats["candidate_pixels"]
+    test_flops = pix[0] * FLOPS_TEST["sphere"] + pix[1] * FLOPS_TEST["box"] + pix[2] * FLOPS_TEST["capsule"]
+    test_achieved = test_flops / (test_ms_avg * 1e-3)
+    roof_trace = {"bound": "alu", "kernel": "trace (trace_fast_kernel + trace_wide_kernel)",
+                  "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                  "frac": achieved / PEAK_FP32, "frac_nonpacked": achieved / PEAK_FP32_NONPACKED,
+                  "flops_per_launch": flops, "launch_ms": trace_ms_avg, "traffic": measured_traffic("trace")}
+    roof_test = {"bound": "alu", "kernel": "binning tile test (tile_test_kernel)",
+                 "achieved": test_achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                 "frac": test_achieved / PEAK_FP32, "frac_nonpacked": test_achieved / PEAK_FP32_NONPACKED,
+                 "flops_per_launch": test_flops, "launch_ms": test_ms_avg, "launches_timed": test_launches,
+                 "candidate_pixels": {"sphere": pix[0], "box": pix[1], "capsule": pix[2]},
+                 "traffic": measured_traffic("tile_test")}
+    # the roofline of the kernel that takes longest per frame
+    dominant, other = (roof_test, roof_trace) if test_ms_avg >= trace_ms_avg else (roof_trace, roof_test)
 
     line = {
         "metric": "Mrays/s + field evals/s at 1080p, 4096 prims; learned vs plain step at equal depth err",
@@ -365,10 +396,9 @@ def main():
         "empty_views": stats["empty_views"],
         "view_nodes": stats["view_nodes"],
         "wide_tiles": stats["wide_tiles"],
-        "roofline": {"bound": "alu", "kernel": "trace (trace_fast_kernel + trace_wide_kernel)",
-                     "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "frac_nonpacked": achieved / PEAK_FP32_NONPACKED,
-                     "flops_per_launch": flops, "traffic": measured_traffic()},
+        "abuffer_candidates": stats["abuffer_candidates"],
+        "roofline": dominant,
+        "roofline_other_kernel": other,
     }
     # binning (HBM-bound by design): algorithmic bytes = VOI reads (2 passes,
     # 48 B/primitive each), tile count/scan/offsets (12 B/tile), scatter write

@@ -137,7 +137,10 @@ typedef struct {
     uint64_t learned_accepted, learned_rejected;   /* relaxed steps (OVERRELAX, LEARNED) */
     uint64_t abuffer_binned;  /* A-buffer entries before the tile-level pruning */
     uint64_t abuffer_candidates; /* (primitive, tile) pairs tested at binning */
-    uint64_t reserved[6];
+    uint64_t candidate_pixels[3]; /* pixels of those tiles inside the pixel
+                                 rectangle of the primitive's bounding sphere,
+                                 by primitive kind: sphere, box, capsule */
+    uint64_t reserved[3];
 } st_stats;
 
 /* Device memory allocator used for the scene's buffers (e.g. a framework's
@@ -415,6 +418,17 @@ st_status st_debug_eval_field(const st_scene *s, const int32_t *active, int32_t 
 st_status st_debug_prune_tree(const st_node *nodes, int32_t n, int32_t root, const int32_t *active,
                               int32_t n_active, int32_t *out_nodes, int32_t cap, int32_t *out_len,
                               float *out_lip);
+
+/*
+ * st_debug_kernel_timing -- measurement hook: enable = 1 starts recording the
+ *   duration of every launch of the binning's tile-test kernel on the build
+ *   stream (a HIP event pair per launch, recorded on that stream; any earlier
+ *   recording is discarded); enable = 0 stops, waits for the recorded events
+ *   and returns the summed milliseconds and the number of launches.  The
+ *   event pairs are created at the first recorded launches and kept by the
+ *   scene.  Errors: ST_E_INVALID (NULL scene or outputs), ST_E_DEVICE.
+ */
+st_status st_debug_kernel_timing(st_scene *s, int32_t enable, float *total_ms, int32_t *launches);
 
 /*
  * st_debug_abuffer -- test hook: copies the current A-buffer, as the tracer

@@ -113,6 +113,7 @@ void stats_from_counters(const st_scene* s, const unsigned long long* h, st_stat
     out->abuffer_entries = uint64_t(s->n_live);
     out->abuffer_binned = uint64_t(s->n_entries);
     out->abuffer_candidates = uint64_t(s->n_cand);
+    for (int k = 0; k < 3; k++) out->candidate_pixels[k] = s->cand_pix[k];
     out->max_list = s->max_list;
     out->max_overlap = s->max_overlap;
 }
@@ -221,6 +222,7 @@ st_status st_flatten_blobtree(const st_node* nodes, int32_t n, int32_t root, con
 void st_scene_destroy(st_scene* s) {
     if (!s) return;
     hipStream_t stream = nullptr;
+    for (hipEvent_t ev : s->test_events) (void)hipEventDestroy(ev);
     free_abuffer(s, stream);
     dev_free(s, s->d_blob, stream);
     dev_free(s, s->d_kill, stream);
@@ -524,6 +526,29 @@ st_status st_debug_eval_field(const st_scene* s, const int32_t* active, int32_t 
         if (view_cap < vlen) { set_error("eval: view capacity too small"); return ST_E_CAPACITY; }
         for (int i = 0; i < vlen; i++) out_view[i] = s->caller_of_post[ventry_node(hview[size_t(i)])];
     }
+    return ST_OK;
+}
+
+st_status st_debug_kernel_timing(st_scene* s, int32_t enable, float* total_ms, int32_t* launches) {
+    if (!s) { set_error("kernel timing: NULL scene"); return ST_E_INVALID; }
+    if (enable) {
+        s->time_test = true;
+        s->test_used = 0;
+        return ST_OK;
+    }
+    if (!total_ms || !launches) { set_error("kernel timing: NULL output"); return ST_E_INVALID; }
+    s->time_test = false;
+    float sum = 0.f;
+    for (size_t k = 0; k < s->test_used; k++) {
+        hipError_t e = hipEventSynchronize(s->test_events[2 * k + 1]);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, s->test_events[2 * k], s->test_events[2 * k + 1]);
+        if (e != hipSuccess) return device_error(e, "kernel timing");
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = int32_t(s->test_used);
+    s->test_used = 0;
     return ST_OK;
 }
 

@@ -203,12 +203,28 @@ __device__ __forceinline__ bool sphere_pixels(const Voi& v, const DevCam& cam, i
 }
 
 // per primitive: the pixel rectangle (i0, j0, i1, j1) of its bounding
-// sphere, empty (0, 0, -1, -1) when no pixel-centre ray can meet it
-__global__ void rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int4* __restrict__ rect) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    int i0, i1, j0, j1;
-    rect[p] = sphere_pixels(voi[p], cam, i0, i1, j0, j1) ? make_int4(i0, j0, i1, j1) : make_int4(0, 0, -1, -1);
+// sphere, empty (0, 0, -1, -1) when no pixel-centre ray can meet it.  Its
+// area (the pixels its candidate tiles test against it) is added to the
+// primitive kind's total pix[kind]: summed over the wave first, so that a
+// few hundred atomics reach the three words instead of one per primitive.
+__global__ void __launch_bounds__(256) rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam,
+                                                   int4* __restrict__ rect, unsigned long long* __restrict__ pix) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long area[3] = {0, 0, 0};
+    if (p < P) {
+        int i0, i1, j0, j1;
+        const Voi& v = voi[p];
+        const bool any = sphere_pixels(v, cam, i0, i1, j0, j1);
+        rect[p] = any ? make_int4(i0, j0, i1, j1) : make_int4(0, 0, -1, -1);
+        const int kind = int(v.v[20]) - ST_SPHERE;
+        if (any && kind >= 0 && kind < 3)
+            area[kind] = (unsigned long long)(i1 - i0 + 1) * (unsigned long long)(j1 - j0 + 1);
+    }
+    for (int k = 0; k < 3; k++) {
+        unsigned long long a = area[k];
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+        if ((threadIdx.x & 63u) == 0 && a) atomicAdd(pix + k, a);
+    }
 }
 
 // tiles (tx0, ty0, tx1, ty1) of a pixel rectangle
@@ -847,9 +863,10 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipError_t e;
 #define ST_CHECK(x, what) do { e = (x); if (e != hipSuccess) return device_error(e, what); } while (0)
 
-    hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, rect);
     ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
     ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
+    unsigned long long* pix = reinterpret_cast<unsigned long long*>(misc + 16);   // 3 counters, 8-byte aligned
+    hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, rect, pix);
     if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, rect, ts, s->tiles_x, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_cand = replay ? s->n_cand : 0u;
@@ -881,6 +898,19 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
                            cur, s->d_e_node);
         // test order by candidate count (the trace order is made after pruning)
         hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, tcnt, T, s->d_tile_order);
+        hipEvent_t* ev = nullptr;
+        if (s->time_test) {   // a fresh pair per launch (created once, reused after a restart)
+            if (s->test_used * 2 + 2 > s->test_events.size()) {
+                hipEvent_t a = nullptr, b = nullptr;
+                ST_CHECK(hipEventCreate(&a), "timing event");
+                ST_CHECK(hipEventCreate(&b), "timing event");
+                s->test_events.push_back(a);
+                s->test_events.push_back(b);
+            }
+            ev = &s->test_events[s->test_used * 2];
+            s->test_used++;
+            ST_CHECK(hipEventRecord(ev[0], stream), "timing record");
+        }
         if (ts == 8)
             hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
@@ -890,6 +920,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         else
             hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
+        if (ev) ST_CHECK(hipEventRecord(ev[1], stream), "timing record");
     }
     const uint32_t n_ent = n_cand;   // slots the pruning and the sorts work on
     // scratch of the long lists (pruning: 7 words per entry; sorting: 2
@@ -930,6 +961,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     }
     uint32_t h_misc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, h_wide = 0;
     ST_CHECK(hipMemcpyAsync(h_misc, misc, 32, hipMemcpyDeviceToHost, stream), "copy build stats");
+    ST_CHECK(hipMemcpyAsync(s->cand_pix, pix, 24, hipMemcpyDeviceToHost, stream), "copy candidate pixels");
     ST_CHECK(hipMemcpyAsync(&h_wide, s->d_wide, 4, hipMemcpyDeviceToHost, stream), "copy wide count");
     e = hipGetLastError();
     if (e != hipSuccess) return device_error(e, "binning kernels");

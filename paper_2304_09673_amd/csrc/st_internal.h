@@ -65,6 +65,11 @@ struct st_scene {
     size_t slots_bytes = 0;
     void* d_wrec = nullptr;           // per-block counter records of the last trace
     size_t wrec_bytes = 0;
+    // launch timing of the tile test (st_debug_kernel_timing)
+    bool time_test = false;
+    std::vector<hipEvent_t> test_events;   // pairs, reused
+    size_t test_used = 0;                  // pairs recorded since enabling
+    uint64_t cand_pix[3] = {0, 0, 0};      // candidate pixels by kind, last build
 
     // scratch kept between builds
     void* d_scratch = nullptr;

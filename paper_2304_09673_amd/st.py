@@ -24,7 +24,7 @@ EXPORTS = (
     "st_debug_prune_tree",
     "st_debug_abuffer", "st_mlp_pack", "st_mlp_forward", "st_mlp_grad", "st_mlp_adam", "st_set_step_model",
     "st_trace_dump", "st_debug_mfma_probe", "st_batch_create", "st_batch_render", "st_batch_stats",
-    "st_batch_destroy", "st_batch_autotune", "st_trace_batch", "st_update_primitives",
+    "st_batch_destroy", "st_batch_autotune", "st_trace_batch", "st_update_primitives", "st_debug_kernel_timing",
 )
 
 MLP_PARAMS = 1377
@@ -62,7 +62,8 @@ class StStats(C.Structure):
                 ("view_nodes", C.c_uint64), ("abuffer_entries", C.c_uint64), ("max_list", C.c_uint64),
                 ("max_overlap", C.c_uint64), ("max_active", C.c_uint64), ("wide_tiles", C.c_uint64),
                 ("learned_accepted", C.c_uint64), ("learned_rejected", C.c_uint64),
-                ("abuffer_binned", C.c_uint64), ("abuffer_candidates", C.c_uint64), ("reserved", C.c_uint64 * 6)]
+                ("abuffer_binned", C.c_uint64), ("abuffer_candidates", C.c_uint64),
+                ("candidate_pixels", C.c_uint64 * 3), ("reserved", C.c_uint64 * 3)]
 
     def as_dict(self):
         d = {}
@@ -129,6 +130,7 @@ def lib():
         L.st_batch_autotune.argtypes = [C.POINTER(vp), C.POINTER(StCamera), i32, C.POINTER(StTuning), C.POINTER(vp),
                                         C.POINTER(vp), i32, C.POINTER(StTuning), C.POINTER(C.c_float), vp]
         L.st_update_primitives.argtypes = [vp, vp, C.POINTER(StNode), i32, vp]
+        L.st_debug_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_float), C.POINTER(i32)]
         L.st_trace_batch.argtypes = [C.POINTER(vp), C.POINTER(StCamera), i32, C.POINTER(vp), C.POINTER(vp),
                                      C.POINTER(StStats), vp]
         for name in EXPORTS:
@@ -305,6 +307,13 @@ class Scene:
         _check(lib().st_trace_dump(self._h, C.byref(cam), _ptr(depth), _ptr(normal), _ptr(features), _ptr(targets),
                                    cap, C.byref(n), _stream_ptr(stream)))
         return int(n.value), depth, normal
+
+    def kernel_timing(self, enable: bool):
+        """st_debug_kernel_timing: start recording tile-test launches (enable) or
+        stop and return (total milliseconds, launches)."""
+        ms, n = C.c_float(0), C.c_int32(0)
+        _check(lib().st_debug_kernel_timing(self._h, 1 if enable else 0, C.byref(ms), C.byref(n)))
+        return None if enable else (float(ms.value), int(n.value))
 
     def debug_abuffer(self, stream=None):
         """(tile_off[T+1], node[E], z_in[E], z_out[E]) of the current A-buffer (host numpy)."""
