@@ -194,7 +194,7 @@ def learned_vs_plain(args):
     # one tuning for all three modes: the autotuner's choice for the plain step
     progress("learned step: autotuning the plain step")
     s = st.Scene(sc)
-    tuned, _ = s.autotune(cam)
+    tuned, _ = s.autotune(cam, reps=5)
     s.close()
     kw = {"tile": tuned.tile, "max_new": tuned.max_new, "sub_depth": tuned.sub_depth}
     # training scenes: the same generator and laws, other seeds, 960x540

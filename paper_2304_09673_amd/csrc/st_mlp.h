@@ -25,6 +25,9 @@ constexpr int kMlpParams = 1377;
 constexpr int kMlpW1 = 0, kMlpB1 = 256, kMlpW2 = 288, kMlpB2 = 1312, kMlpW3 = 1344, kMlpB3 = 1376;
 constexpr float kOmegaMax = 4.0f;
 constexpr float kFeatClamp = 3.0f;   // standardised features are clamped to [-3, 3]
+// the tracer runs the model once every kMlpEvery stepping iterations of a
+// wave (the inference costs about as much as a small view's evaluation)
+constexpr int kMlpEvery = 4;
 
 // Per-lane operand table, one column per lane (entry k of lane l at k*64+l):
 //  [0,1]   W1 A operand: halves W1[h][4g..4g+3]          (h = l % 32, g = l / 32)

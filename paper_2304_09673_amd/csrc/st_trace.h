@@ -729,6 +729,8 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         float ra = 0.f, fa = 0.f, rb = 0.f, fb = 0.f;   // refinement bracket
         int nref = 0, side = 0;
         uint32_t ev_here = 0;
+        uint32_t mlp_it = 0;       // learned step: wave iterations since the last inference
+        float om_last = 1.0f;      // learned step: this lane's last proposed factor
         while (true) {
             bool act = mode == M_TRACE || mode == M_REFINE;
             if (ballot(act) == 0) break;
@@ -754,8 +756,13 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                         float f[8];
                         step_features(f, v, invL, t, tp, vp, tp_ok, steps, n, len);
                         if constexpr (SM == SM_LEARNED) {
-                            om = mlp_omega(tab, f);
-                            if (!(om >= 1.0f)) om = 1.0f;   // never below the plain step
+                            // one inference every kMlpEvery iterations of the
+                            // wave; in between a ray reuses its last factor
+                            if (mlp_it++ % uint32_t(kMlpEvery) == 0u) {
+                                om_last = mlp_omega(tab, f);
+                                if (!(om_last >= 1.0f)) om_last = 1.0f;   // never below the plain step
+                            }
+                            om = om_last;
                         }
                         else dump_samples<KS>(A, S.view(), len, ray, t, v, invL, t1, need, f);
                     }

@@ -26,8 +26,13 @@ def collect(scenes, cap_per_scene: int = 1 << 20, tuning=None):
         targ = torch.empty(cap_per_scene, dtype=torch.float32, device="cuda")
         n, _, _ = s.trace_dump(feats, targ)
         n = min(n, cap_per_scene)
-        xs.append(feats[:n].cpu().numpy())
-        ts.append(targ[:n].cpu().numpy())
+        x = feats[:n].cpu().numpy()
+        t = targ[:n].cpu().numpy()
+        # the dump's slot order follows the device's scheduling: sort the
+        # samples so that a training run depends on the samples only
+        order = np.lexsort(np.concatenate([x, t[:, None]], axis=1).T[::-1])
+        xs.append(x[order])
+        ts.append(t[order])
         s.close()
     return np.concatenate(xs), np.concatenate(ts)
 
