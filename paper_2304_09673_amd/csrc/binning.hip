@@ -179,12 +179,13 @@ __device__ __forceinline__ void slope_range(float c, float z, float r, float& lo
 // the pixel-centre rays that can meet a bounding sphere: exact tangent lines
 // through the eye, one pixel of margin; the whole image when the sphere
 // reaches the eye plane; false when it lies behind the eye or off screen.
-__device__ __forceinline__ bool sphere_pixels(const Voi& v, const DevCam& cam, int& i0, int& i1, int& j0, int& j1) {
-    float rx = v.v[0] - cam.eye[0], ry = v.v[1] - cam.eye[1], rz = v.v[2] - cam.eye[2];
+__device__ __forceinline__ bool sphere_pixels(float sx, float sy, float sz, float radius, const DevCam& cam, int& i0,
+                                              int& i1, int& j0, int& j1) {
+    float rx = sx - cam.eye[0], ry = sy - cam.eye[1], rz = sz - cam.eye[2];
     float cx = rx * cam.right[0] + ry * cam.right[1] + rz * cam.right[2];
     float cy = rx * cam.up[0] + ry * cam.up[1] + rz * cam.up[2];
     float cz = rx * cam.fwd[0] + ry * cam.fwd[1] + rz * cam.fwd[2];
-    float r = v.v[3] * 1.001f + 1e-5f;
+    float r = radius * 1.001f + 1e-5f;
     i0 = 0; i1 = cam.w - 1; j0 = 0; j1 = cam.h - 1;
     if (cz + r <= 0.f) return false;   // entirely behind the eye
     if (cz > r * 1.01f + 1e-4f) {
@@ -202,8 +203,56 @@ __device__ __forceinline__ bool sphere_pixels(const Voi& v, const DevCam& cam, i
     return i0 <= i1 && j0 <= j1;
 }
 
-// per primitive: the pixel rectangle (i0, j0, i1, j1) of its bounding
-// sphere, empty (0, 0, -1, -1) when no pixel-centre ray can meet it.  Its
+// Conservative pixel rectangle of a volume of interest, tighter than that of
+// its bounding sphere: a capsule lies in the convex hull of its two end
+// spheres, whose projection is bounded by the union of the two spheres'
+// rectangles; a box projects into the hull of its eight projected corners
+// when they all lie in front of the eye (one pixel of margin, as for the
+// spheres).  Other cases use the bounding sphere.
+__device__ __forceinline__ bool voi_pixels(const Voi& v, const DevCam& cam, int& i0, int& i1, int& j0, int& j1) {
+    const int kind = int(v.v[20]);
+    if (kind == ST_CAPSULE) {
+        int a0, a1, b0, b1, c0, c1, d0, d1;
+        const bool ha = sphere_pixels(v.v[4], v.v[5], v.v[6], v.v[7], cam, a0, a1, b0, b1);
+        const bool hb = sphere_pixels(v.v[8], v.v[9], v.v[10], v.v[7], cam, c0, c1, d0, d1);
+        if (!ha && !hb) return false;
+        i0 = ha ? (hb ? min(a0, c0) : a0) : c0;
+        i1 = ha ? (hb ? max(a1, c1) : a1) : c1;
+        j0 = ha ? (hb ? min(b0, d0) : b0) : d0;
+        j1 = ha ? (hb ? max(b1, d1) : b1) : d1;
+        return true;
+    }
+    if (kind == ST_BOX) {
+        float umin = __builtin_inff(), umax = -__builtin_inff(), vmin = __builtin_inff(), vmax = -__builtin_inff();
+        bool front = true;
+        for (int c = 0; c < 8; c++) {
+            float p[3];
+            for (int k = 0; k < 3; k++) {
+                p[k] = v.v[4 + k] - cam.eye[k];
+                for (int a = 0; a < 3; a++) p[k] += ((c >> a) & 1 ? 1.f : -1.f) * v.v[8 + 4 * a + 3] * v.v[8 + 4 * a + k];
+            }
+            const float x = p[0] * cam.right[0] + p[1] * cam.right[1] + p[2] * cam.right[2];
+            const float y = p[0] * cam.up[0] + p[1] * cam.up[1] + p[2] * cam.up[2];
+            const float z = p[0] * cam.fwd[0] + p[1] * cam.fwd[1] + p[2] * cam.fwd[2];
+            front = front && z > 1e-3f;
+            const float u = (x / (z * cam.tx) + 1.f) * 0.5f * cam.w, w = (1.f - y / (z * cam.ty)) * 0.5f * cam.h;
+            umin = fminf(umin, u); umax = fmaxf(umax, u); vmin = fminf(vmin, w); vmax = fmaxf(vmax, w);
+        }
+        if (front) {
+            // corner extent with a relative margin for FP32 rounding of the projection
+            const float mu = 1e-4f * (fabsf(umin) + fabsf(umax)) + 1e-3f, mv = 1e-4f * (fabsf(vmin) + fabsf(vmax)) + 1e-3f;
+            i0 = max(0, int(floorf(umin - mu - 0.5f)) - 1);
+            i1 = min(cam.w - 1, int(ceilf(umax + mu - 0.5f)) + 1);
+            j0 = max(0, int(floorf(vmin - mv - 0.5f)) - 1);
+            j1 = min(cam.h - 1, int(ceilf(vmax + mv - 0.5f)) + 1);
+            return i0 <= i1 && j0 <= j1;
+        }
+    }
+    return sphere_pixels(v.v[0], v.v[1], v.v[2], v.v[3], cam, i0, i1, j0, j1);
+}
+
+// per primitive: the pixel rectangle (i0, j0, i1, j1) of its volume of
+// interest, empty (0, 0, -1, -1) when no pixel-centre ray can meet it.  Its
 // area (the pixels its candidate tiles test against it) is added to the
 // primitive kind's total pix[kind]: summed over the wave first, so that a
 // few hundred atomics reach the three words instead of one per primitive.
@@ -214,7 +263,7 @@ __global__ void __launch_bounds__(256) rect_kernel(const Voi* __restrict__ voi, 
     if (p < P) {
         int i0, i1, j0, j1;
         const Voi& v = voi[p];
-        const bool any = sphere_pixels(v, cam, i0, i1, j0, j1);
+        const bool any = voi_pixels(v, cam, i0, i1, j0, j1);
         rect[p] = any ? make_int4(i0, j0, i1, j1) : make_int4(0, 0, -1, -1);
         const int kind = int(v.v[20]) - ST_SPHERE;
         if (any && kind >= 0 && kind < 3)
