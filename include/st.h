@@ -215,8 +215,12 @@ st_status st_update_primitives(st_scene *s, const int32_t *ids, const st_node *n
  * for every screen tile, the list of primitives whose volume of interest meets
  * a pixel-centre ray of the tile, with the tile's entry/exit view depth
  * (minimum entry, maximum exit over its rays), sorted by entry depth (ties by
- * primitive).  Built on the device by project -> count -> scan -> scatter ->
- * per-tile sort; synchronizes `stream` once to size the A-buffer.
+ * primitive).  Built on the device by project -> count per tile -> scan ->
+ * scatter candidates -> per-tile ray test -> tile-level pruning (see
+ * keep_all_entries) -> per-tile sort; synchronizes `stream` twice to size the
+ * A-buffer.  A build with the same camera and tuning as the scene's valid
+ * A-buffer reruns every kernel with the sizes of the last build and does not
+ * synchronize (the sizes are a function of scene, camera and tuning).
  *   cam (host), t (host, NULL = defaults).  The A-buffer is kept in the scene
  *   and tagged with the camera and tuning; st_trace refuses a different one.
  * Errors: ST_E_INVALID (camera size <= 0, fov outside (0,180), degenerate

@@ -309,23 +309,32 @@ st_status st_build_abuffer(st_scene* s, const st_camera* cam, const st_tuning* t
     if (!make_devcam(*cam, dc)) { set_error("build: degenerate camera basis"); return ST_E_INVALID; }
     int tx = (cam->width + t.tile - 1) / t.tile, ty = (cam->height + t.tile - 1) / t.tile;
     int T = tx * ty;
+    // Same scene, camera and tuning as the valid A-buffer: every count and
+    // size of the build is the same, so it is rerun on the device with the
+    // sizes of the last one (no host synchronization, no allocation).
+    if (s->ab_valid && T == s->n_tiles && std::memcmp(cam, &s->ab_cam, sizeof(st_camera)) == 0 &&
+        std::memcmp(&t, &s->ab_tune, sizeof(st_tuning)) == 0) {
+        r = build_abuffer_device(s, t, stream, true);
+        if (r != ST_OK) { s->ab_valid = false; return r; }
+        s->ab_gen++;
+        return ST_OK;
+    }
     if (T != s->n_tiles || !s->d_tile_off) {
         dev_free(s, s->d_tile_off, stream);
         dev_free(s, s->d_tile_ovl, stream);
         dev_free(s, s->d_tile_order, stream);
         dev_free(s, s->d_tile_cnt, stream);
+        dev_free(s, s->d_wide, stream);
         s->d_tile_off = (uint32_t*)dev_alloc(s, size_t(T + 1) * 4, stream);
         s->d_tile_ovl = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
         s->d_tile_order = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
         s->d_tile_cnt = (uint32_t*)dev_alloc(s, size_t(T) * 4, stream);
-        if (!s->d_tile_off || !s->d_tile_ovl || !s->d_tile_order || !s->d_tile_cnt) {
+        s->d_wide = (uint32_t*)dev_alloc(s, size_t(T + 1) * 4, stream);
+        if (!s->d_tile_off || !s->d_tile_ovl || !s->d_tile_order || !s->d_tile_cnt || !s->d_wide) {
             set_error("build: tile arrays allocation failed");
             return ST_E_NOMEM;
         }
     }
-    dev_free(s, s->d_wide, stream);
-    s->d_wide = (uint32_t*)dev_alloc(s, size_t(T + 1) * 4, stream);
-    if (!s->d_wide) { set_error("build: wide list allocation failed"); return ST_E_NOMEM; }
     s->dcam = dc;
     s->tiles_x = tx;
     s->tiles_y = ty;
