@@ -359,7 +359,7 @@ def main():
                  "achieved": test_achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                  "frac": test_achieved / PEAK_FP32, "frac_nonpacked": test_achieved / PEAK_FP32_NONPACKED,
                  "flops_per_launch": test_flops, "launch_ms": test_ms_avg, "launches_timed": test_launches,
-                 "candidate_pixels": {"sphere": pix[0], "box": pix[1], "capsule": pix[2]},
+                 "tested_pixels": {"sphere": pix[0], "box": pix[1], "capsule": pix[2]},
                  "traffic": measured_traffic("tile_test")}
     # the roofline of the kernel that takes longest per frame
     dominant, other = (roof_test, roof_trace) if test_ms_avg >= trace_ms_avg else (roof_trace, roof_test)
@@ -400,18 +400,22 @@ def main():
         "view_nodes": stats["view_nodes"],
         "wide_tiles": stats["wide_tiles"],
         "abuffer_candidates": stats["abuffer_candidates"],
+        "abuffer_tested": stats["abuffer_tested"],
         "roofline": dominant,
         "roofline_other_kernel": other,
     }
     # binning (HBM-bound by design): algorithmic bytes = VOI reads (2 passes,
-    # 48 B/primitive each), tile count/scan/offsets (12 B/tile), scatter write
-    # (12 B per binned entry), tile pruning read (12 B per binned entry) and
-    # write (12 B per kept entry), per-tile sort read + write (24 B per kept
-    # entry)
+    # 48 B/primitive each), tile count/scan/offsets (12 B/tile), per candidate
+    # the scatter write, the pre-test pruning's read and primitive-to-node
+    # lookup (12 B), per tested candidate the pruning's write, the test's read
+    # and write (4 + 4 + 12 B) and the post-test pruning's read (12 B), per
+    # kept entry the pruning's write and the per-tile sort's read + write
+    # (12 + 24 B)
     n_tiles = -(-cam.width // tune.tile) * -(-cam.height // tune.tile)
     e = stats["abuffer_entries"]
-    eb = stats["abuffer_binned"]
-    bin_bytes = 96 * sc.n_prims + 12 * n_tiles + 24 * eb + 36 * e
+    ec = stats["abuffer_candidates"]
+    et = stats["abuffer_tested"]
+    bin_bytes = 96 * sc.n_prims + 12 * n_tiles + 12 * ec + 32 * et + 36 * e
     line["binning"] = {"bound": "hbm", "algorithmic_bytes": bin_bytes, "ms_wall": round(build_ms, 4),
                        "achieved_GBps": bin_bytes / (build_ms * 1e-3) / 1e9,
                        "frac": bin_bytes / (build_ms * 1e-3) / 8e12,

@@ -135,12 +135,21 @@ typedef struct {
     uint64_t max_active;      /* largest active set used by the tracer */
     uint64_t wide_tiles;      /* tiles traced on the wide-capacity path */
     uint64_t learned_accepted, learned_rejected;   /* relaxed steps (OVERRELAX, LEARNED) */
-    uint64_t abuffer_binned;  /* A-buffer entries before the tile-level pruning */
-    uint64_t abuffer_candidates; /* (primitive, tile) pairs tested at binning */
-    uint64_t candidate_pixels[3]; /* pixels of those tiles inside the pixel
-                                 rectangle of the primitive's bounding sphere,
-                                 by primitive kind: sphere, box, capsule */
-    uint64_t reserved[3];
+    uint64_t abuffer_binned;  /* tested candidates whose volume of interest a
+                                 pixel ray of the tile meets (entries before
+                                 the tile-level pruning) */
+    uint64_t abuffer_candidates; /* (primitive, tile) pairs whose pixel
+                                 rectangle touches the tile */
+    uint64_t candidate_pixels[3]; /* pixels of the tested candidates' pixel
+                                 rectangles inside their tiles (the per-ray
+                                 test's work), by primitive kind: sphere, box,
+                                 capsule */
+    uint64_t abuffer_tested;  /* candidates left for the per-ray test: those
+                                 alive for their tile's whole candidate set */
+    uint64_t stalled;         /* blocks that stopped at their iteration bound
+                                 before every ray finished (0 in a correct run) */
+    uint64_t smooth_evals;    /* compact operators evaluated on their smooth
+                                 (blending) branch */
 } st_stats;
 
 /* Device memory allocator used for the scene's buffers (e.g. a framework's

@@ -108,12 +108,13 @@ void stats_from_counters(const st_scene* s, const unsigned long long* h, st_stat
     out->wide_tiles = h[18];
     out->learned_accepted = h[19];
     out->learned_rejected = h[20];
-    out->reserved[0] = h[21];   // stalled blocks (must be 0)
-    out->reserved[1] = h[22];   // compact operators evaluated on their smooth branch
+    out->stalled = h[21];
+    out->smooth_evals = h[22];
     out->abuffer_entries = uint64_t(s->n_live);
     out->abuffer_binned = uint64_t(s->n_entries);
     out->abuffer_candidates = uint64_t(s->n_cand);
     for (int k = 0; k < 3; k++) out->candidate_pixels[k] = s->cand_pix[k];
+    out->abuffer_tested = uint64_t(s->n_tested);
     out->max_list = s->max_list;
     out->max_overlap = s->max_overlap;
 }

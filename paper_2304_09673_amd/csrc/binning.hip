@@ -252,27 +252,14 @@ __device__ __forceinline__ bool voi_pixels(const Voi& v, const DevCam& cam, int&
 }
 
 // per primitive: the pixel rectangle (i0, j0, i1, j1) of its volume of
-// interest, empty (0, 0, -1, -1) when no pixel-centre ray can meet it.  Its
-// area (the pixels its candidate tiles test against it) is added to the
-// primitive kind's total pix[kind]: summed over the wave first, so that a
-// few hundred atomics reach the three words instead of one per primitive.
+// interest, empty (0, 0, -1, -1) when no pixel-centre ray can meet it.
 __global__ void __launch_bounds__(256) rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam,
-                                                   int4* __restrict__ rect, unsigned long long* __restrict__ pix) {
+                                                   int4* __restrict__ rect) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long area[3] = {0, 0, 0};
     if (p < P) {
         int i0, i1, j0, j1;
-        const Voi& v = voi[p];
-        const bool any = voi_pixels(v, cam, i0, i1, j0, j1);
+        const bool any = voi_pixels(voi[p], cam, i0, i1, j0, j1);
         rect[p] = any ? make_int4(i0, j0, i1, j1) : make_int4(0, 0, -1, -1);
-        const int kind = int(v.v[20]) - ST_SPHERE;
-        if (any && kind >= 0 && kind < 3)
-            area[kind] = (unsigned long long)(i1 - i0 + 1) * (unsigned long long)(j1 - j0 + 1);
-    }
-    for (int k = 0; k < 3; k++) {
-        unsigned long long a = area[k];
-        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-        if ((threadIdx.x & 63u) == 0 && a) atomicAdd(pix + k, a);
     }
 }
 
@@ -450,12 +437,13 @@ __device__ __forceinline__ float dpp_max(float v) {
 template <int TS>
 __global__ void __launch_bounds__(256) tile_test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
                                                         const uint32_t* __restrict__ tile_off,
+                                                        const uint32_t* __restrict__ tile_n,
                                                         const uint32_t* __restrict__ order, int tiles_x, DevCam cam,
                                                         uint32_t* __restrict__ e_node, float* __restrict__ e_zin,
                                                         float* __restrict__ e_zout) {
     constexpr int RPL = TS * TS / 64;   // rays per lane
     const int tile = int(order[blockIdx.x]);
-    const uint32_t e0 = tile_off[tile], n = tile_off[tile + 1] - e0;
+    const uint32_t e0 = tile_off[tile], n = tile_n[tile];
     if (n == 0) return;
     const int lane = int(threadIdx.x & 63u);
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -644,35 +632,16 @@ __device__ int block_rank(bool keep, int* total) {
     return before + int(lanes_below_mask(mk));
 }
 
-// Compacts the candidate segment [e0, e0 + n) in place to the entries that
-// hit (non-empty interval) and, unless keep_all, whose primitive survives the
-// rule for the set of hits; a (2^ceil(log2 n) words), b (n words) and tab
-// (2^bits words, 2^bits >= 2n) are scratch.  Returns the number kept; *hits
-// gets the number of hits.
-__device__ int prune_tile(uint32_t e0, int n, uint32_t* e_node, float* e_zin, float* e_zout, uint32_t* a,
-                          uint32_t* b, uint32_t* tab, int bits, const uint32_t* __restrict__ rmq,
-                          const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes,
-                          bool keep_all, int* hits) {
+// Removes from the sorted node list cur[0..m) the primitives that are dead for
+// the set (a killing ancestor with no primitive of the set on its other
+// side), repeating until nothing drops; nxt (m words) and tab (2^bits words,
+// 2^bits >= 2m) are scratch.  cur ends pointing at the survivors (sorted);
+// returns their count.
+__device__ int dead_rounds(uint32_t*& cur, uint32_t* nxt, int m, uint32_t* tab, int bits,
+                           const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot,
+                           const uint32_t* __restrict__ kill, uint32_t n_nodes) {
     const int tid = int(threadIdx.x);
-    int np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    // the primitives that hit, sorted (misses and padding sort last)
-    int m = 0;   // primitives are distinct within a tile's segment
-    for (int c = 0; c < np2; c += kPruneThreads) {
-        const int i = c + tid;
-        const bool hit = i < n && e_zin[e0 + i] <= e_zout[e0 + i];
-        if (i < np2) a[i] = hit ? e_node[e0 + i] : 0xFFFFFFFFu;
-        int tot;
-        block_rank(hit, &tot);
-        m += tot;
-    }
-    *hits = m;
-    __threadfence_block();
-    __syncthreads();
-    if (!keep_all) bitonic_wg(a, (uint32_t*)nullptr, np2);
-    uint32_t* cur = a;
-    uint32_t* nxt = b;
-    for (int round = 0; round < 32 && m > 0 && !keep_all; round++) {
+    for (int round = 0; round < 32 && m > 0; round++) {
         for (int i = tid; i < (1 << bits); i += kPruneThreads) tab[i] = kNoKill;
         __threadfence_block();
         __syncthreads();
@@ -702,6 +671,37 @@ __device__ int prune_tile(uint32_t e0, int n, uint32_t* e_node, float* e_zin, fl
         m = kept;
         if (!changed) break;
     }
+    return m;
+}
+
+// Compacts the candidate segment [e0, e0 + n) in place to the entries that
+// hit (non-empty interval) and, unless keep_all, whose primitive survives the
+// rule for the set of hits; a (2^ceil(log2 n) words), b (n words) and tab
+// (2^bits words, 2^bits >= 2n) are scratch.  Returns the number kept; *hits
+// gets the number of hits.
+__device__ int prune_tile(uint32_t e0, int n, uint32_t* e_node, float* e_zin, float* e_zout, uint32_t* a,
+                          uint32_t* b, uint32_t* tab, int bits, const uint32_t* __restrict__ rmq,
+                          const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes,
+                          bool keep_all, int* hits) {
+    const int tid = int(threadIdx.x);
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    // the primitives that hit, sorted (misses and padding sort last)
+    int m = 0;   // primitives are distinct within a tile's segment
+    for (int c = 0; c < np2; c += kPruneThreads) {
+        const int i = c + tid;
+        const bool hit = i < n && e_zin[e0 + i] <= e_zout[e0 + i];
+        if (i < np2) a[i] = hit ? e_node[e0 + i] : 0xFFFFFFFFu;
+        int tot;
+        block_rank(hit, &tot);
+        m += tot;
+    }
+    *hits = m;
+    __threadfence_block();
+    __syncthreads();
+    if (!keep_all) bitonic_wg(a, (uint32_t*)nullptr, np2);
+    uint32_t* cur = a;
+    if (!keep_all) m = dead_rounds(cur, b, m, tab, bits, rmq, kslot, kill, n_nodes);
     // the survivors, as a hash set; then the entries, compacted in place in
     // their order (each chunk is read whole before any of it is written)
     if (!keep_all) {
@@ -739,6 +739,90 @@ __device__ __forceinline__ int prune_bits(int n) {   // 2^bits >= 2n, and > 2(n 
     return bits;
 }
 
+// Drops, before the per-ray test, the candidates of a tile that are dead for
+// the tile's whole candidate set.  A primitive dead for a set is dead for any
+// subset of it (its killing ancestor has no partner there either), and the
+// set of primitives alive for the hits is alive for every set between them
+// and the hits, so the entries kept after the test are unchanged.  Segments
+// longer than the LDS capacity, and keep_all builds, keep every candidate.
+// The segment is compacted in place (order kept) and tile_n gets its length.
+// tested[0] counts the candidates kept, pix[kind] the pixels of their
+// rectangles inside the tile (the work of the per-ray test).
+__device__ void add_tested(const uint32_t* slot_prim, uint32_t e0, int n, int tile, int tiles_x, int ts,
+                           const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* tested,
+                           unsigned long long* pix) {
+    __shared__ unsigned long long part[kPruneThreads / 64][3];
+    const int tid = int(threadIdx.x), lane = tid & 63, w = tid >> 6;
+    const int x0 = (tile % tiles_x) * ts, y0 = (tile / tiles_x) * ts;
+    unsigned long long area[3] = {0, 0, 0};
+    for (int i = tid; i < n; i += kPruneThreads) {
+        const uint32_t p = slot_prim[e0 + i];
+        const int4 r = rect[p];
+        const int wx = min(r.z, x0 + ts - 1) - max(r.x, x0) + 1, wy = min(r.w, y0 + ts - 1) - max(r.y, y0) + 1;
+        const int kind = int(voi[p].v[20]) - ST_SPHERE;
+        if (wx > 0 && wy > 0 && kind >= 0 && kind < 3) area[kind] += (unsigned long long)(wx * wy);
+    }
+    for (int k = 0; k < 3; k++) {
+        for (int o = 32; o > 0; o >>= 1) area[k] += __shfl_xor(area[k], o);
+        if (lane == 0) part[w][k] = area[k];
+    }
+    __syncthreads();
+    if (tid < 3) {
+        unsigned long long t = 0;
+        for (int k = 0; k < kPruneThreads / 64; k++) t += part[k][tid];
+        if (t) atomicAdd(pix + tid, t);
+    }
+    if (tid == 0) atomicAdd(tested, uint32_t(n));
+}
+
+__global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
+        const uint32_t* __restrict__ tile_off, int n_tiles, int tiles_x, int ts, const uint32_t* __restrict__ prims,
+        const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim, uint32_t* __restrict__ tile_n,
+        const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
+        uint32_t n_nodes, int keep_all, uint32_t* tested, unsigned long long* pix) {
+    __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
+    const int tile = int(blockIdx.x);
+    if (tile >= n_tiles) return;
+    const int tid = int(threadIdx.x);
+    const uint32_t e0 = tile_off[tile];
+    const int n = int(tile_off[tile + 1] - e0);
+    if (n == 0 || n > kPruneLdsCap || keep_all) {
+        if (tid == 0) tile_n[tile] = uint32_t(n);
+        if (n) add_tested(slot_prim, e0, n, tile, tiles_x, ts, rect, voi, tested, pix);
+        return;
+    }
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int i = tid; i < np2; i += kPruneThreads) a[i] = i < n ? prims[slot_prim[e0 + i]] : 0xFFFFFFFFu;
+    __threadfence_block();
+    __syncthreads();
+    bitonic_wg(a, (uint32_t*)nullptr, np2);
+    const int bits = prune_bits(n);
+    uint32_t* cur = a;
+    const int m = dead_rounds(cur, b, n, tab, bits, rmq, kslot, kill, n_nodes);
+    for (int i = tid; i < (1 << bits); i += kPruneThreads) tab[i] = kNoKill;
+    __threadfence_block();
+    __syncthreads();
+    for (int i = tid; i < m; i += kPruneThreads) hinsert(tab, bits, cur[i]);
+    __threadfence_block();
+    __syncthreads();
+    int kept = 0;
+    for (int c = 0; c < n; c += kPruneThreads) {
+        const int i = c + tid;
+        const uint32_t p = i < n ? slot_prim[e0 + i] : 0u;
+        const uint32_t x = i < n ? prims[p] : 0u;
+        const bool keep = i < n && m > 0 && hfind(tab, bits, x, tab[hslot(x, bits)]);
+        int tot;
+        const int r = block_rank(keep, &tot);   // its barriers separate the reads from the writes
+        if (keep) slot_prim[e0 + kept + r] = p;
+        kept += tot;
+        __threadfence_block();
+        __syncthreads();
+    }
+    if (tid == 0) tile_n[tile] = uint32_t(kept);
+    if (kept) add_tested(slot_prim, e0, kept, tile, tiles_x, ts, rect, voi, tested, pix);
+}
+
 __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
         const uint32_t* __restrict__ tile_off, int n_tiles, uint32_t* e_node, float* e_zin, float* e_zout,
         uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
@@ -748,11 +832,9 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
     const int tile = int(blockIdx.x);
     if (tile >= n_tiles) return;
     const uint32_t e0 = tile_off[tile];
-    const int n = int(tile_off[tile + 1] - e0);
-    if (n == 0) {
-        if (threadIdx.x == 0) tile_cnt[tile] = 0u;
-        return;
-    }
+    const int n = int(tile_cnt[tile]);   // tested candidates of the segment
+    __syncthreads();                     // every thread has read it before thread 0 rewrites it
+    if (n == 0) return;
     if (n > kPruneLdsCap) {
         if (threadIdx.x == 0) long_list[atomicAdd(misc + 5, 1u)] = uint32_t(tile);
         return;
@@ -777,7 +859,8 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_long_kernel(
     for (uint32_t idx = blockIdx.x; idx < n_long; idx += gridDim.x) {
         const uint32_t tile = long_list[idx];
         const uint32_t e0 = tile_off[tile];
-        const int n = int(tile_off[tile + 1] - e0);
+        const int n = int(tile_cnt[tile]);   // tested candidates of the segment
+        __syncthreads();
         uint32_t* base = scratch + size_t(7) * e0;
         int hits;
         const int kept = prune_tile(e0, n, e_node, e_zin, e_zout, base, base + 2 * n, base + 3 * n, prune_bits(n),
@@ -915,7 +998,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
     ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
     unsigned long long* pix = reinterpret_cast<unsigned long long*>(misc + 16);   // 3 counters, 8-byte aligned
-    hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, rect, pix);
+    hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, rect);
     if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, rect, ts, s->tiles_x, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_cand = replay ? s->n_cand : 0u;
@@ -942,11 +1025,19 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         s->ab_cap = cap;
     }
     ST_CHECK(fill_u32(cur, uint32_t(T), 0u, stream), "clear cursors");
-    if (P && n_cand) {
+    if (P && n_cand)
         hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, rect, ts, s->tiles_x, s->d_tile_off,
                            cur, s->d_e_node);
-        // test order by candidate count (the trace order is made after pruning)
-        hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, tcnt, T, s->d_tile_order);
+    // candidates dead for their tile's candidate set: dropped before the test
+    // (d_tile_cnt: candidates left per tile)
+    hipLaunchKernelGGL(cand_prune_kernel, dim3(T), dim3(kPruneThreads), 0, stream, s->d_tile_off, T, s->tiles_x, ts,
+                       s->d_prims, rect, s->d_voi, s->d_e_node, s->d_tile_cnt, s->d_rmq,
+                       reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
+                       t.keep_all_entries, misc + 7, pix);
+    if (P && n_cand) {
+        // test order by candidates left (the trace order is made after pruning)
+        hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_cnt, T,
+                           s->d_tile_order);
         hipEvent_t* ev = nullptr;
         if (s->time_test) {   // a fresh pair per launch (created once, reused after a restart)
             if (s->test_used * 2 + 2 > s->test_events.size()) {
@@ -962,13 +1053,13 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         }
         if (ts == 8)
             hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
-                               s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
+                               s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         else if (ts == 16)
             hipLaunchKernelGGL(tile_test_kernel<16>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
-                               s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
+                               s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         else
             hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
-                               s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
+                               s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         if (ev) ST_CHECK(hipEventRecord(ev[1], stream), "timing record");
     }
     const uint32_t n_ent = n_cand;   // slots the pruning and the sorts work on
@@ -1019,6 +1110,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     s->max_list = h_misc[2];
     s->n_live = h_misc[3];
     s->n_entries = h_misc[6];   // candidates that hit
+    s->n_tested = h_misc[7];    // candidates left for the per-ray test
     s->n_wide = h_wide;
 #undef ST_CHECK
     return ST_OK;

@@ -69,7 +69,8 @@ struct st_scene {
     bool time_test = false;
     std::vector<hipEvent_t> test_events;   // pairs, reused
     size_t test_used = 0;                  // pairs recorded since enabling
-    uint64_t cand_pix[3] = {0, 0, 0};      // candidate pixels by kind, last build
+    uint64_t cand_pix[3] = {0, 0, 0};      // pixels the per-ray test covers, by kind, last build
+    uint32_t n_tested = 0;                 // candidates left for the per-ray test, last build
 
     // scratch kept between builds
     void* d_scratch = nullptr;

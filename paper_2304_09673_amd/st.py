@@ -63,16 +63,14 @@ class StStats(C.Structure):
                 ("max_overlap", C.c_uint64), ("max_active", C.c_uint64), ("wide_tiles", C.c_uint64),
                 ("learned_accepted", C.c_uint64), ("learned_rejected", C.c_uint64),
                 ("abuffer_binned", C.c_uint64), ("abuffer_candidates", C.c_uint64),
-                ("candidate_pixels", C.c_uint64 * 3), ("reserved", C.c_uint64 * 3)]
+                ("candidate_pixels", C.c_uint64 * 3), ("abuffer_tested", C.c_uint64), ("stalled", C.c_uint64),
+                ("smooth_evals", C.c_uint64)]
 
     def as_dict(self):
         d = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
             d[name] = list(v) if not isinstance(v, int) else int(v)
-        res = d.pop("reserved")
-        d["stalled"] = res[0]
-        d["smooth_evals"] = res[1]
         return d
 
 

@@ -161,14 +161,22 @@ def test_abuffer_pruning_keeps_the_tile_alive_set(which):
     """Tile-level pruning: each tile keeps exactly the entries of the
     primitives that survive the dead-primitive rule for the tile's whole
     binned list, with their depths, in (z_in, primitive) order; bit-exact
-    against the rule evaluated on the host from the unpruned lists."""
+    against the rule evaluated on the host from the unpruned lists.  The
+    candidates dropped before the per-ray test (dead for the tile's whole
+    candidate set) change nothing in the result."""
     from paper_2304_09673_amd import st
     sc = sg.config2(3, 160, 120) if which == "c2" else sg.config3(0, 192, 108, n_prims=512, max_depth=12)
     s = st.Scene(sc)
     s.build_abuffer(sc.camera, st.default_tuning(tile=16, keep_all_entries=1))
     off0, node0, zin0, zout0 = s.debug_abuffer()
+    st0 = s.trace()[2]
+    assert st0["abuffer_tested"] == st0["abuffer_candidates"]
     s.build_abuffer(sc.camera, st.default_tuning(tile=16))
     off1, node1, zin1, zout1 = s.debug_abuffer()
+    st1 = s.trace()[2]
+    assert st1["abuffer_candidates"] == st0["abuffer_candidates"]
+    assert st1["abuffer_entries"] <= st1["abuffer_binned"] <= st1["abuffer_tested"] <= st1["abuffer_candidates"]
+    assert st1["abuffer_entries"] == int(off1[-1])
     assert off0.shape == off1.shape
     dropped = 0
     for t in range(off0.shape[0] - 1):
