@@ -198,10 +198,15 @@ __device__ __forceinline__ T eval_view(const uint32_t* view, int len_in, const N
             uint32_t kind = ventry_kind(e);
             // clamp: a malformed entry reads a wrong node, never outside the array
             const cfloat* q = (const cfloat*)(par[min(ventry_node(e), n_nodes - 1u)].v);
-            // the index stays in [0, KS) for any view; a well-formed view never
-            // leaves it (KS is at least the tree depth)
+            // Every primitive pushes the running value, the first one the
+            // initial value, which is never popped (a view has one operator
+            // fewer than primitives).  A view of depth D keeps at most D
+            // operands pending above it, at indices 1..D; with KS >= D (KS is
+            // at least the tree depth) only index KS wraps, onto that dead
+            // slot 0.  An unconditional push is one indexed register move.
             if (kind <= ST_CAPSULE) {
-                if (base + jj) { stk[sp & (KS - 1)] = acc; sp++; }
+                stk[sp & (KS - 1)] = acc;
+                sp++;
                 acc = prim_eval<T>(kind, q, p);
             } else {
                 sp--;
