@@ -346,6 +346,7 @@ static void exclusive_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* s
 // atomics give, which changes only the schedule, not any result.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4 * kOrderThreads;
+constexpr int kOrderBatch = 8;
 
 __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_t* __restrict__ tile_cnt,
                                                                     int n_tiles, uint32_t* __restrict__ order) {
@@ -353,12 +354,21 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
     __shared__ uint32_t part[kOrderThreads];
     const int tid = int(threadIdx.x);
     auto bucket = [&](int t) {   // longest first
-        const uint32_t len = tile_cnt[t];
+        const uint32_t len = t < n_tiles ? tile_cnt[t] : 0u;
         return uint32_t(kOrderBuckets - 1) - min(len, uint32_t(kOrderBuckets - 1));
     };
     for (int b = tid; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
     __syncthreads();
-    for (int t = tid; t < n_tiles; t += kOrderThreads) atomicAdd(&cnt[bucket(t)], 1u);
+    // the counts are read kOrderBatch per thread at a time, all loads issued
+    // before the first atomic, so that one memory latency covers a batch
+    for (int t0 = 0; t0 < n_tiles; t0 += kOrderThreads * kOrderBatch) {
+        uint32_t bk[kOrderBatch];
+#pragma unroll
+        for (int k = 0; k < kOrderBatch; k++) bk[k] = bucket(t0 + k * kOrderThreads + tid);
+#pragma unroll
+        for (int k = 0; k < kOrderBatch; k++)
+            if (t0 + k * kOrderThreads + tid < n_tiles) atomicAdd(&cnt[bk[k]], 1u);
+    }
     __syncthreads();
     // exclusive scan: four buckets per thread, then an inclusive scan of the
     // per-thread sums
@@ -375,7 +385,16 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
     uint32_t run = part[tid] - sum;
     for (int j = 0; j < 4; j++) { cnt[4 * tid + j] = run; run += c[j]; }
     __syncthreads();
-    for (int t = tid; t < n_tiles; t += kOrderThreads) order[atomicAdd(&cnt[bucket(t)], 1u)] = uint32_t(t);
+    for (int t0 = 0; t0 < n_tiles; t0 += kOrderThreads * kOrderBatch) {
+        uint32_t bk[kOrderBatch];
+#pragma unroll
+        for (int k = 0; k < kOrderBatch; k++) bk[k] = bucket(t0 + k * kOrderThreads + tid);
+#pragma unroll
+        for (int k = 0; k < kOrderBatch; k++) {
+            const int t = t0 + k * kOrderThreads + tid;
+            if (t < n_tiles) order[atomicAdd(&cnt[bk[k]], 1u)] = uint32_t(t);
+        }
+    }
 }
 
 // per primitive (one workgroup): one candidate for every tile of its rectangle
