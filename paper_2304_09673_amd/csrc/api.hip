@@ -197,6 +197,8 @@ st_status st_flatten_blobtree(const st_node* nodes, int32_t n, int32_t root, con
         {(void**)&s->d_kslot, N * 32, s->h_kslot.data()},
         {(void**)&s->d_rmq, s->h_rmq.size() * 4, s->h_rmq.data()},
         {(void**)&s->d_prims, P * 4, s->h_prims.data()},
+        {(void**)&s->d_sub, N * 32, s->h_sub.data()},
+        {(void**)&s->d_oside, P * 32, s->h_oside.data()},
         {(void**)&s->d_par, N * sizeof(NodePar), s->h_par.data()},
         {(void**)&s->d_roi, N * 4, s->h_roi.data()},
         {(void**)&s->d_voi, P * sizeof(Voi), nullptr},
@@ -230,6 +232,8 @@ void st_scene_destroy(st_scene* s) {
     dev_free(s, s->d_kslot, stream);
     dev_free(s, s->d_rmq, stream);
     dev_free(s, s->d_prims, stream);
+    dev_free(s, s->d_sub, stream);
+    dev_free(s, s->d_oside, stream);
     dev_free(s, s->d_par, stream);
     dev_free(s, s->d_roi, stream);
     dev_free(s, s->d_voi, stream);
@@ -275,7 +279,9 @@ st_status st_update_primitives(st_scene* s, const int32_t* ids, const st_node* n
         primitive_params(nodes[i], double(s->h_roi[size_t(p)]), s->h_par[size_t(p)], s->h_box[size_t(slot[size_t(i)])]);
     }
     scene_bounds(s);
-    hipError_t e = hipSuccess;
+    subtree_boxes(s);
+    hipError_t e = hipMemcpyAsync(s->d_sub, s->h_sub.data(), s->h_sub.size() * 4, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return device_error(e, "update: upload");
     if (n <= 64) {
         for (int i = 0; i < n && e == hipSuccess; i++) {
             size_t p = size_t(s->post_of_caller[size_t(ids[i])]);

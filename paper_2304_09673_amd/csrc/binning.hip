@@ -251,21 +251,85 @@ __device__ __forceinline__ bool voi_pixels(const Voi& v, const DevCam& cam, int&
     return sphere_pixels(v.v[0], v.v[1], v.v[2], v.v[3], cam, i0, i1, j0, j1);
 }
 
-// per primitive: the pixel rectangle (i0, j0, i1, j1) of its volume of
-// interest, empty (0, 0, -1, -1) when no pixel-centre ray can meet it.
-__global__ void __launch_bounds__(256) rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam,
-                                                   int4* __restrict__ rect) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < P) {
-        int i0, i1, j0, j1;
-        const bool any = voi_pixels(voi[p], cam, i0, i1, j0, j1);
-        rect[p] = any ? make_int4(i0, j0, i1, j1) : make_int4(0, 0, -1, -1);
+// Conservative pixel rectangle of an axis-aligned box (lo, hi): its eight
+// corners projected when they all lie in front of the eye (a relative margin
+// and one pixel, as for the boxes above), else its bounding sphere.
+__device__ __forceinline__ bool aabb_pixels(const float* lo, const float* hi, const DevCam& cam, int& i0, int& i1,
+                                            int& j0, int& j1) {
+    float umin = __builtin_inff(), umax = -__builtin_inff(), vmin = __builtin_inff(), vmax = -__builtin_inff();
+    bool front = true;
+    for (int c = 0; c < 8; c++) {
+        const float px = ((c & 1) ? hi[0] : lo[0]) - cam.eye[0];
+        const float py = ((c & 2) ? hi[1] : lo[1]) - cam.eye[1];
+        const float pz = ((c & 4) ? hi[2] : lo[2]) - cam.eye[2];
+        const float x = px * cam.right[0] + py * cam.right[1] + pz * cam.right[2];
+        const float y = px * cam.up[0] + py * cam.up[1] + pz * cam.up[2];
+        const float z = px * cam.fwd[0] + py * cam.fwd[1] + pz * cam.fwd[2];
+        front = front && z > 1e-3f;
+        const float u = (x / (z * cam.tx) + 1.f) * 0.5f * cam.w, w = (1.f - y / (z * cam.ty)) * 0.5f * cam.h;
+        umin = fminf(umin, u); umax = fmaxf(umax, u); vmin = fminf(vmin, w); vmax = fmaxf(vmax, w);
     }
+    if (front) {
+        const float mu = 1e-4f * (fabsf(umin) + fabsf(umax)) + 1e-3f, mv = 1e-4f * (fabsf(vmin) + fabsf(vmax)) + 1e-3f;
+        i0 = max(0, int(floorf(umin - mu - 0.5f)) - 1);
+        i1 = min(cam.w - 1, int(ceilf(umax + mu - 0.5f)) + 1);
+        j0 = max(0, int(floorf(vmin - mv - 0.5f)) - 1);
+        j1 = min(cam.h - 1, int(ceilf(vmax + mv - 0.5f)) + 1);
+        return i0 <= i1 && j0 <= j1;
+    }
+    const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+    const float ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    return sphere_pixels(cx, cy, cz, 0.5f * sqrtf(ex * ex + ey * ey + ez * ez), cam, i0, i1, j0, j1);
 }
 
 // tiles (tx0, ty0, tx1, ty1) of a pixel rectangle
 __device__ __forceinline__ int4 rect_tiles(int4 pr, int ts) {
     return pr.z < pr.x ? make_int4(0, 0, -1, -1) : make_int4(pr.x / ts, pr.y / ts, pr.z / ts, pr.w / ts);
+}
+
+// Per primitive: the pixel rectangle (i0, j0, i1, j1) of its volume of
+// interest, empty (0, 0, -1, -1) when no pixel-centre ray can meet it, and
+// the range of tiles (tx0, ty0, tx1, ty1) it is a candidate of.  Unless
+// keep_all, that range is cut to the tiles of the rectangles of the subtree
+// boxes on the other side of the primitive's first kKillLevels killing
+// ancestors: in a tile that such a rectangle misses, the ancestor has no
+// primitive of its other side (no pixel-centre ray of the tile meets those
+// volumes of interest), so the primitive is dead there for the tile's hits
+// and for every set that the pruning passes see.  (The cut is by whole
+// tiles: the per-ray test still covers the primitive's whole rectangle in
+// each tile it keeps.)
+__global__ void __launch_bounds__(256) rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int ts,
+                                                   const uint32_t* __restrict__ oside, const float* __restrict__ sub,
+                                                   int keep_all, int4* __restrict__ rect, int4* __restrict__ trect) {
+    // eight lanes per primitive: lane 0 its own rectangle, lane k (1..7) the
+    // k-th killing ancestor's other side; the tile ranges are intersected
+    // across the eight lanes
+    const int gid = int(blockIdx.x * blockDim.x + threadIdx.x);
+    const int p = gid >> 3, j = gid & 7;
+    const bool in = p < P;
+    constexpr int kAll = 0x7FFFFFFF;
+    int4 tr = make_int4(0, 0, kAll, kAll);
+    if (in && j == 0) {
+        int i0, i1, j0, j1;
+        const bool any = voi_pixels(voi[p], cam, i0, i1, j0, j1);
+        const int4 pr = any ? make_int4(i0, j0, i1, j1) : make_int4(0, 0, -1, -1);
+        rect[p] = pr;
+        tr = rect_tiles(pr, ts);
+    } else if (in && !keep_all) {
+        const uint32_t other = oside[8 * size_t(p) + size_t(j - 1)];
+        if (other != kNoKill) {
+            int a0, a1, b0, b1;
+            tr = aabb_pixels(sub + 8 * size_t(other), sub + 8 * size_t(other) + 3, cam, a0, a1, b0, b1)
+                     ? rect_tiles(make_int4(a0, b0, a1, b1), ts) : make_int4(0, 0, -1, -1);
+        }
+    }
+    for (int o = 1; o < 8; o <<= 1) {
+        tr.x = max(tr.x, __shfl_xor(tr.x, o));
+        tr.y = max(tr.y, __shfl_xor(tr.y, o));
+        tr.z = min(tr.z, __shfl_xor(tr.z, o));
+        tr.w = min(tr.w, __shfl_xor(tr.w, o));
+    }
+    if (in && j == 0) trect[p] = tr.x <= tr.z && tr.y <= tr.w ? tr : make_int4(0, 0, -1, -1);
 }
 
 // ---------------------------------------------------------------------------
@@ -398,9 +462,9 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
 }
 
 // per primitive (one workgroup): one candidate for every tile of its rectangle
-__global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict__ rect, int ts, int tiles_x,
+__global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict__ trect, int tiles_x,
                                                          uint32_t* __restrict__ tile_count) {
-    const int4 rc = rect_tiles(rect[blockIdx.x], ts);
+    const int4 rc = trect[blockIdx.x];
     const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
     if (w <= 0 || h <= 0) return;
     for (int k = int(threadIdx.x); k < w * h; k += int(blockDim.x))
@@ -408,11 +472,11 @@ __global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict_
 }
 
 // per primitive (one workgroup): its index into a slot of each tile segment
-__global__ void __launch_bounds__(256) cand_scatter_kernel(const int4* __restrict__ rect, int ts, int tiles_x,
+__global__ void __launch_bounds__(256) cand_scatter_kernel(const int4* __restrict__ trect, int tiles_x,
                                                            const uint32_t* __restrict__ tile_off,
                                                            uint32_t* __restrict__ cursor,
                                                            uint32_t* __restrict__ slot_prim) {
-    const int4 rc = rect_tiles(rect[blockIdx.x], ts);
+    const int4 rc = trect[blockIdx.x];
     const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
     if (w <= 0 || h <= 0) return;
     for (int k = int(threadIdx.x); k < w * h; k += int(blockDim.x)) {
@@ -984,11 +1048,12 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     const int P = s->n_prims;
     const int T = s->n_tiles;
     const int ts = t.tile;
-    // scratch layout (bytes): rect P*16, scan sums, tile counts (T+1)*4,
-    // cursors T*4, long list T*4, misc 64*4
+    // scratch layout (bytes): pixel rectangles P*16, tile ranges P*16, scan
+    // sums, tile counts (T+1)*4, cursors T*4, long list T*4, misc 64*4
     size_t nb_t = size_t(T + kScanBlock) / kScanBlock + 2;
     size_t off_rect = 0;
-    size_t off_sums = align_up(off_rect + size_t(P) * 16);
+    size_t off_trect = align_up(off_rect + size_t(P) * 16);
+    size_t off_sums = align_up(off_trect + size_t(P) * 16);
     size_t off_tcnt = align_up(off_sums + nb_t * 4 + 16);
     size_t off_cur = align_up(off_tcnt + size_t(T + 1) * 4);
     size_t off_long = align_up(off_cur + size_t(T) * 4);
@@ -1006,6 +1071,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     }
     char* base = (char*)s->d_scratch;
     int4* rect = (int4*)(base + off_rect);
+    int4* trect = (int4*)(base + off_trect);
     uint32_t* sums = (uint32_t*)(base + off_sums);
     uint32_t* tcnt = (uint32_t*)(base + off_tcnt);
     uint32_t* cur = (uint32_t*)(base + off_cur);
@@ -1017,8 +1083,9 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
     ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
     unsigned long long* pix = reinterpret_cast<unsigned long long*>(misc + 16);   // 3 counters, 8-byte aligned
-    hipLaunchKernelGGL(rect_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, rect);
-    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, rect, ts, s->tiles_x, tcnt);
+    if (P) hipLaunchKernelGGL(rect_kernel, dim3((8 * P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
+                       s->d_oside, s->d_sub, t.keep_all_entries, rect, trect);
+    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, trect, s->tiles_x, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_cand = replay ? s->n_cand : 0u;
     if (!replay) {
@@ -1045,7 +1112,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     }
     ST_CHECK(fill_u32(cur, uint32_t(T), 0u, stream), "clear cursors");
     if (P && n_cand)
-        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, rect, ts, s->tiles_x, s->d_tile_off,
+        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, trect, s->tiles_x, s->d_tile_off,
                            cur, s->d_e_node);
     // candidates dead for their tile's candidate set: dropped before the test
     // (d_tile_cnt: candidates left per tile)

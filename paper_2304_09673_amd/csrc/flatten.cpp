@@ -110,6 +110,54 @@ void primitive_params(const st_node& nd, double d, NodePar& par, PrimBox& box) {
     }
 }
 
+// Subtree boxes, bottom-up in post-order: a primitive's volume-of-interest
+// box, an operator's the union of its children's (right child p - 1, left
+// child first(p - 1) - 1).  Doubles are rounded outwards to floats.
+void subtree_boxes(st_scene* s) {
+    const int n = s->n_nodes;
+    s->h_sub.assign(size_t(8) * n, 0.f);
+    size_t slot = 0;
+    for (int p = 0; p < n; p++) {
+        float* b = &s->h_sub[8 * size_t(p)];
+        uint32_t first;
+        if (blob_prim(s->h_blob[size_t(p)])) {
+            const PrimBox& pb = s->h_box[slot++];
+            for (int j = 0; j < 3; j++) {
+                b[j] = std::nextafter(float(pb.vlo[j]), -INFINITY);
+                b[3 + j] = std::nextafter(float(pb.vhi[j]), INFINITY);
+            }
+            first = uint32_t(p);
+        } else {
+            const float* r = &s->h_sub[8 * size_t(p - 1)];
+            uint32_t fr;
+            std::memcpy(&fr, r + 6, 4);
+            const float* l = &s->h_sub[8 * size_t(fr - 1)];
+            for (int j = 0; j < 3; j++) {
+                b[j] = std::min(l[j], r[j]);
+                b[3 + j] = std::max(l[3 + j], r[3 + j]);
+            }
+            std::memcpy(&first, l + 6, 4);
+        }
+        std::memcpy(b + 6, &first, 4);
+    }
+    // the other side of each killing ancestor K of a primitive x: K's right
+    // child K - 1 when x lies before it (in K's left subtree), else K's left
+    // child, which ends just before the right child's subtree
+    s->h_oside.assign(size_t(8) * s->h_prims.size(), kNoKill);
+    for (size_t i = 0; i < s->h_prims.size(); i++) {
+        const uint32_t x = s->h_prims[i];
+        for (int k = 0; k < kKillLevels; k++) {
+            const uint32_t K = s->h_kslot[8 * size_t(x) + size_t(k)];
+            if (K == kNoKill) break;
+            const uint32_t rc = K - 1u;
+            uint32_t first_r;
+            std::memcpy(&first_r, &s->h_sub[8 * size_t(rc) + 6], 4);
+            s->h_oside[8 * i + size_t(k)] = x < first_r ? rc : first_r - 1u;
+        }
+        s->h_oside[8 * i + 7] = 0u;
+    }
+}
+
 void scene_bounds(st_scene* s) {
     double ext_lo[3] = {INFINITY, INFINITY, INFINITY}, ext_hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double voi_lo[3] = {INFINITY, INFINITY, INFINITY}, voi_hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -278,6 +326,7 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
     s->n_prims = nprim;
     s->lipschitz = float(Lmax);
     scene_bounds(s);
+    subtree_boxes(s);
 
     // sparse table over post-order positions of (depth << 24 | parent)
     int levels = 1;

@@ -23,6 +23,14 @@ struct st_scene {
     std::vector<st::NodePar> h_par;
     std::vector<float> h_roi;
     std::vector<PrimBox> h_box;   // per primitive, in h_prims order
+    // per node, 8 floats: axis-aligned box of the volumes of interest of its
+    // subtree (lo xyz, hi xyz, rounded outwards), the first post-order index
+    // of its subtree (as bits), 0
+    std::vector<float> h_sub;
+    // per primitive (h_prims order), 8 words: for each of its first
+    // kKillLevels killing ancestors, the child on the other side (kNoKill
+    // padding), then 0
+    std::vector<uint32_t> h_oside;
     float extent = 0.f, lipschitz = 1.f;
     float voi_lo[3] = {0, 0, 0}, voi_hi[3] = {0, 0, 0};
 
@@ -32,6 +40,8 @@ struct st_scene {
     uint32_t* d_kslot = nullptr;     // 8 words per node
     uint32_t* d_rmq = nullptr;
     uint32_t* d_prims = nullptr;     // post-order index of each primitive
+    float* d_sub = nullptr;          // h_sub
+    uint32_t* d_oside = nullptr;     // h_oside
     st::NodePar* d_par = nullptr;
     float* d_roi = nullptr;
     st::Voi* d_voi = nullptr;
@@ -122,6 +132,7 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
 st_status validate_primitive(const st_node& nd, int i);
 // device parameter block and bounds of a primitive with range of interest d
 void primitive_params(const st_node& nd, double d, NodePar& par, PrimBox& box);
+void subtree_boxes(st_scene* s);
 // scene extent and volume-of-interest box from the primitives' boxes
 void scene_bounds(st_scene* s);
 PruneResult host_prune(const st_scene* s, std::vector<uint32_t> active_post,

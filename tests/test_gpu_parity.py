@@ -163,7 +163,8 @@ def test_abuffer_pruning_keeps_the_tile_alive_set(which):
     binned list, with their depths, in (z_in, primitive) order; bit-exact
     against the rule evaluated on the host from the unpruned lists.  The
     candidates dropped before the per-ray test (dead for the tile's whole
-    candidate set) change nothing in the result."""
+    candidate set, or outside the screen rectangle of the other side of one
+    of their killing ancestors) change nothing in the result."""
     from paper_2304_09673_amd import st
     sc = sg.config2(3, 160, 120) if which == "c2" else sg.config3(0, 192, 108, n_prims=512, max_depth=12)
     s = st.Scene(sc)
@@ -174,7 +175,7 @@ def test_abuffer_pruning_keeps_the_tile_alive_set(which):
     s.build_abuffer(sc.camera, st.default_tuning(tile=16))
     off1, node1, zin1, zout1 = s.debug_abuffer()
     st1 = s.trace()[2]
-    assert st1["abuffer_candidates"] == st0["abuffer_candidates"]
+    assert st1["abuffer_candidates"] <= st0["abuffer_candidates"]
     assert st1["abuffer_entries"] <= st1["abuffer_binned"] <= st1["abuffer_tested"] <= st1["abuffer_candidates"]
     assert st1["abuffer_entries"] == int(off1[-1])
     assert off0.shape == off1.shape
