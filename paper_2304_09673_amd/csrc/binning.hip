@@ -584,7 +584,7 @@ __device__ __forceinline__ uint32_t f2key(float f) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-constexpr int kSortThreads = 512;
+constexpr int kSortThreads = 256;
 
 // Bitonic sort of keys[0..np2) (u64) with a u32 payload, in place, by the
 // whole workgroup.  Works on LDS or on global memory (the latter with the
@@ -691,7 +691,7 @@ __device__ void sort_segment(uint64_t* keys, uint32_t* vals, uint32_t* zo_keys, 
 // entries.  One workgroup per tile; lists up to kPruneLdsCap in LDS, longer
 // ones in global scratch (7 words per entry).
 constexpr int kPruneThreads = 256;
-constexpr int kPruneLdsCap = 2048;
+constexpr int kPruneLdsCap = 1024;
 
 __device__ __forceinline__ uint32_t lanes_below_mask(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
@@ -956,7 +956,7 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_long_kernel(
     }
 }
 
-constexpr int kSortLdsCap = 4096;
+constexpr int kSortLdsCap = 1024;
 
 __global__ void __launch_bounds__(kSortThreads) tile_sort_kernel(
         const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_cnt, int n_tiles, uint32_t* e_node,
