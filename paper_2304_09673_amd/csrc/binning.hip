@@ -517,8 +517,13 @@ __device__ __forceinline__ float dpp_max(float v) {
 // empty interval (+inf, -inf).  Workgroups take the tiles in the given order
 // (most candidates first: the longest segments start early instead of
 // finishing the frame late).
+// waves per tile: sixteen take a 16x16 or 32x32 tile's candidates in turn,
+// so that the longest lists end early; an 8x8 tile (one ray per lane) has few
+// candidates to share
+constexpr uint32_t test_waves(int ts) { return ts == 8 ? 4u : 16u; }
+
 template <int TS>
-__global__ void __launch_bounds__(256) tile_test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
+__global__ void __launch_bounds__(64 * test_waves(TS)) tile_test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
                                                         const uint32_t* __restrict__ tile_off,
                                                         const uint32_t* __restrict__ tile_n,
                                                         const uint32_t* __restrict__ order, int tiles_x, DevCam cam,
@@ -543,7 +548,7 @@ __global__ void __launch_bounds__(256) tile_test_kernel(const Voi* __restrict__ 
         cosv[r] = ray.cosv;
     }
     const float o[3] = {cam.eye[0], cam.eye[1], cam.eye[2]};
-    for (uint32_t c = w; c < n; c += 4u) {
+    for (uint32_t c = w; c < n; c += test_waves(TS)) {
         const uint32_t p = __builtin_amdgcn_readfirstlane(e_node[e0 + c]);
         const Voi v = voi[p];
         float zmin = __builtin_inff(), zmax = -__builtin_inff();
@@ -1035,6 +1040,17 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t n, uint32_t v
     if (i < n) p[i] = v;
 }
 
+// clears the counters of a build in one launch: tile counts (T + 1 words),
+// scatter cursors (T), misc (64) and the wide-list length (1)
+__global__ void clear_build_kernel(uint32_t* __restrict__ tcnt, uint32_t* __restrict__ cur, uint32_t T,
+                                   uint32_t* __restrict__ misc, uint32_t* __restrict__ wide) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= T) tcnt[i] = 0u;
+    if (i < T) cur[i] = 0u;
+    if (i < 64u) misc[i] = 0u;
+    if (i == 0u) wide[0] = 0u;
+}
+
 hipError_t fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, v);
@@ -1080,8 +1096,8 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipError_t e;
 #define ST_CHECK(x, what) do { e = (x); if (e != hipSuccess) return device_error(e, what); } while (0)
 
-    ST_CHECK(fill_u32(tcnt, uint32_t(T + 1), 0u, stream), "clear tile counts");
-    ST_CHECK(fill_u32(misc, 64u, 0u, stream), "clear misc");
+    hipLaunchKernelGGL(clear_build_kernel, dim3((uint32_t(T) + 64u) / 256u + 1u), dim3(256), 0, stream, tcnt, cur,
+                       uint32_t(T), misc, s->d_wide);
     unsigned long long* pix = reinterpret_cast<unsigned long long*>(misc + 16);   // 3 counters, 8-byte aligned
     if (P) hipLaunchKernelGGL(rect_kernel, dim3((8 * P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
                        s->d_oside, s->d_sub, t.keep_all_entries, rect, trect);
@@ -1110,7 +1126,6 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         }
         s->ab_cap = cap;
     }
-    ST_CHECK(fill_u32(cur, uint32_t(T), 0u, stream), "clear cursors");
     if (P && n_cand)
         hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, trect, s->tiles_x, s->d_tile_off,
                            cur, s->d_e_node);
@@ -1138,13 +1153,13 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
             ST_CHECK(hipEventRecord(ev[0], stream), "timing record");
         }
         if (ts == 8)
-            hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T), dim3(64 * test_waves(8)), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         else if (ts == 16)
-            hipLaunchKernelGGL(tile_test_kernel<16>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<16>, dim3(T), dim3(64 * test_waves(16)), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         else
-            hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T), dim3(256), 0, stream, s->d_voi, rect, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T), dim3(64 * test_waves(32)), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         if (ev) ST_CHECK(hipEventRecord(ev[1], stream), "timing record");
     }
@@ -1168,7 +1183,6 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
                        s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc,
                        reinterpret_cast<uint32_t*>(lbuf), s->d_rmq, reinterpret_cast<const uint4*>(s->d_kslot),
                        s->d_kill, uint32_t(s->n_nodes), t.keep_all_entries, misc + 6);
-    ST_CHECK(fill_u32(s->d_wide, 1u, 0u, stream), "clear wide list");
     hipLaunchKernelGGL(tile_sort_kernel, dim3(T), dim3(kSortThreads), 0, stream, s->d_tile_off, s->d_tile_cnt, T,
                        s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, uint32_t(s->ab_ma_fast),
                        s->d_wide);
