@@ -401,8 +401,8 @@ static void exclusive_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* s
 // workgroup per primitive (its volume of interest is workgroup-uniform and
 // read once), one wave per candidate tile in turn, each lane testing
 // ts*ts/64 rays, then a wave min/max of the entry and exit depths
-// Dispatch order of tiles: decreasing count (a tile's candidates for the
-// test, its kept entries for the trace).  The work of a tile grows with its
+// Dispatch order of tiles: decreasing count of the candidates left for the
+// per-ray test (the trace reuses the order).  The work of a tile grows with its
 // count and a launch is set by its slowest workgroups, so the heavy tiles
 // start first and the light ones fill the machine behind them.  One
 // workgroup, counting sort over kOrderBuckets count buckets (counts beyond
@@ -1136,7 +1136,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
                        reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
                        t.keep_all_entries, misc + 7, pix);
     if (P && n_cand) {
-        // test order by candidates left (the trace order is made after pruning)
+        // order by candidates left, for the test and for the trace
         hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_cnt, T,
                            s->d_tile_order);
         hipEvent_t* ev = nullptr;
@@ -1193,8 +1193,9 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipLaunchKernelGGL(tile_sort_long_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream,
                        s->d_tile_off, s->d_tile_cnt, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl,
                        misc, sk, sv, sz, uint32_t(s->ab_ma_fast), s->d_wide);
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_cnt, T,
-                       s->d_tile_order);
+    // (the trace takes the tiles in the test's order: a tile's kept entries
+    // grow with its tested candidates, and a second ordering pass costs more
+    // than it gains)
     if (replay) {
         e = hipGetLastError();
         return e == hipSuccess ? ST_OK : device_error(e, "binning kernels");
