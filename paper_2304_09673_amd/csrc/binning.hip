@@ -696,6 +696,9 @@ __device__ void sort_segment(uint64_t* keys, uint32_t* vals, uint32_t* zo_keys, 
 // entries.  One workgroup per tile; lists up to kPruneLdsCap in LDS, longer
 // ones in global scratch (7 words per entry).
 constexpr int kPruneThreads = 256;
+// words of a tile's statistics record: candidates tested, tested pixels by
+// kind (3), tested candidates that hit, padding
+constexpr int kTileStat = 8;
 constexpr int kPruneLdsCap = 1024;
 
 __device__ __forceinline__ uint32_t lanes_below_mask(uint64_t mask) {
@@ -834,11 +837,10 @@ __device__ __forceinline__ int prune_bits(int n) {   // 2^bits >= 2n, and > 2(n 
 // and the hits, so the entries kept after the test are unchanged.  Segments
 // longer than the LDS capacity, and keep_all builds, keep every candidate.
 // The segment is compacted in place (order kept) and tile_n gets its length.
-// tested[0] counts the candidates kept, pix[kind] the pixels of their
-// rectangles inside the tile (the work of the per-ray test).
+// The tile's record gets the candidates kept ([0]) and, by kind, the pixels
+// of their rectangles inside the tile ([1..3], the work of the per-ray test).
 __device__ void add_tested(const uint32_t* slot_prim, uint32_t e0, int n, int tile, int tiles_x, int ts,
-                           const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* tested,
-                           unsigned long long* pix) {
+                           const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* __restrict__ tstat) {
     __shared__ unsigned long long part[kPruneThreads / 64][3];
     const int tid = int(threadIdx.x), lane = tid & 63, w = tid >> 6;
     const int x0 = (tile % tiles_x) * ts, y0 = (tile / tiles_x) * ts;
@@ -855,19 +857,20 @@ __device__ void add_tested(const uint32_t* slot_prim, uint32_t e0, int n, int ti
         if (lane == 0) part[w][k] = area[k];
     }
     __syncthreads();
+    // the tile's record (summed only for a build that reports statistics)
     if (tid < 3) {
         unsigned long long t = 0;
         for (int k = 0; k < kPruneThreads / 64; k++) t += part[k][tid];
-        if (t) atomicAdd(pix + tid, t);
+        tstat[kTileStat * size_t(tile) + 1 + tid] = uint32_t(t);
     }
-    if (tid == 0) atomicAdd(tested, uint32_t(n));
+    if (tid == 0) tstat[kTileStat * size_t(tile)] = uint32_t(n);
 }
 
 __global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
         const uint32_t* __restrict__ tile_off, int n_tiles, int tiles_x, int ts, const uint32_t* __restrict__ prims,
         const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim, uint32_t* __restrict__ tile_n,
         const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
-        uint32_t n_nodes, int keep_all, uint32_t* tested, unsigned long long* pix) {
+        uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
     __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
     const int tile = int(blockIdx.x);
     if (tile >= n_tiles) return;
@@ -876,7 +879,7 @@ __global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
     const int n = int(tile_off[tile + 1] - e0);
     if (n == 0 || n > kPruneLdsCap || keep_all) {
         if (tid == 0) tile_n[tile] = uint32_t(n);
-        if (n) add_tested(slot_prim, e0, n, tile, tiles_x, ts, rect, voi, tested, pix);
+        if (n) add_tested(slot_prim, e0, n, tile, tiles_x, ts, rect, voi, tstat);
         return;
     }
     int np2 = 1;
@@ -908,14 +911,14 @@ __global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
         __syncthreads();
     }
     if (tid == 0) tile_n[tile] = uint32_t(kept);
-    if (kept) add_tested(slot_prim, e0, kept, tile, tiles_x, ts, rect, voi, tested, pix);
+    if (kept) add_tested(slot_prim, e0, kept, tile, tiles_x, ts, rect, voi, tstat);
 }
 
 __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
         const uint32_t* __restrict__ tile_off, int n_tiles, uint32_t* e_node, float* e_zin, float* e_zout,
         uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
         const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
-        uint32_t n_nodes, int keep_all) {
+        uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
     __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
     const int tile = int(blockIdx.x);
     if (tile >= n_tiles) return;
@@ -932,7 +935,7 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
                                 keep_all != 0, &hits);
     if (threadIdx.x == 0) {
         tile_cnt[tile] = uint32_t(kept);
-        if (hits) atomicAdd(misc + 6, uint32_t(hits));
+        tstat[kTileStat * size_t(tile) + 4] = uint32_t(hits);
     }
 }
 
@@ -942,7 +945,7 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_long_kernel(
         const uint32_t* __restrict__ tile_off, uint32_t* e_node, float* e_zin, float* e_zout,
         uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ long_list, const uint32_t* __restrict__ misc,
         uint32_t* scratch, const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot,
-        const uint32_t* __restrict__ kill, uint32_t n_nodes, int keep_all, uint32_t* __restrict__ hits_total) {
+        const uint32_t* __restrict__ kill, uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
     const uint32_t n_long = misc[5];
     for (uint32_t idx = blockIdx.x; idx < n_long; idx += gridDim.x) {
         const uint32_t tile = long_list[idx];
@@ -955,7 +958,7 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_long_kernel(
                                     rmq, kslot, kill, n_nodes, keep_all != 0, &hits);
         if (threadIdx.x == 0) {
             tile_cnt[tile] = uint32_t(kept);
-            if (hits) atomicAdd(hits_total, uint32_t(hits));
+            tstat[kTileStat * size_t(tile) + 4] = uint32_t(hits);
         }
         __syncthreads();
     }
@@ -963,34 +966,78 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_long_kernel(
 
 constexpr int kSortLdsCap = 1024;
 
-__global__ void __launch_bounds__(kSortThreads) tile_sort_kernel(
+// Short lists (up to 64 entries), one wave per tile, four tiles per
+// workgroup, no barriers: each lane holds one entry; its position in
+// (z_in, node) order is the number of smaller keys, and its depth overlap the
+// number of entries entering at or before its entry depth minus those that
+// exit before it (the same counts the workgroup sort takes from its sorted
+// arrays).  Longer lists are queued for tile_sort_kernel.
+__global__ void __launch_bounds__(256) tile_sort_short_kernel(
         const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_cnt, int n_tiles, uint32_t* e_node,
-        float* e_zin, float* e_zout,
-        uint32_t* __restrict__ tile_ovl, uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
-        uint32_t ma_fast, uint32_t* __restrict__ wide) {
+        float* e_zin, float* e_zout, uint32_t* __restrict__ tile_ovl, uint32_t* __restrict__ queue,
+        uint32_t* __restrict__ misc, uint32_t ma_fast, uint32_t* __restrict__ wide) {
+    const int lane = int(threadIdx.x & 63u);
+    const int tile = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);
+    if (tile >= n_tiles) return;   // whole waves
+    const uint32_t e0 = tile_off[tile], n = tile_cnt[tile];
+    if (n == 0) {
+        if (lane == 0) tile_ovl[tile] = 0;
+        return;
+    }
+    if (n > 64u) {
+        if (lane == 0) queue[atomicAdd(misc + 10, 1u)] = uint32_t(tile);
+        return;
+    }
+    const bool in = uint32_t(lane) < n;
+    const uint32_t node = in ? e_node[e0 + lane] : 0u;
+    const float zi = in ? e_zin[e0 + lane] : 0.f, zo = in ? e_zout[e0 + lane] : 0.f;
+    const uint32_t ki = f2key(zi), ko = f2key(zo);
+    uint32_t rank = 0, a = 0, lo = 0;
+    for (int j = 0; j < int(n); j++) {
+        const uint32_t kj = __builtin_amdgcn_readlane(ki, j), nj = __builtin_amdgcn_readlane(node, j);
+        const uint32_t oj = __builtin_amdgcn_readlane(ko, j);
+        rank += (kj < ki || (kj == ki && nj < node)) ? 1u : 0u;
+        a += kj <= ki ? 1u : 0u;
+        lo += oj < ki ? 1u : 0u;
+    }
+    if (in) {   // every lane has read its entry above
+        e_node[e0 + rank] = node;
+        e_zin[e0 + rank] = zi;
+        e_zout[e0 + rank] = zo;
+    }
+    uint32_t ov = in ? a - lo : 0u;
+    for (int o = 32; o > 0; o >>= 1) ov = max(ov, uint32_t(__shfl_xor(int(ov), o)));
+    if (lane == 0) {
+        tile_ovl[tile] = ov;
+        if (ov > ma_fast) wide[1 + atomicAdd(wide, 1u)] = uint32_t(tile);
+    }
+}
+
+// Queued lists (more than 64 entries), a workgroup per tile in turn; lists
+// longer than kSortLdsCap go on to the long list.
+__global__ void __launch_bounds__(kSortThreads) tile_sort_kernel(
+        const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ tile_cnt, uint32_t* e_node,
+        float* e_zin, float* e_zout, uint32_t* __restrict__ tile_ovl, const uint32_t* __restrict__ queue,
+        uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc, uint32_t ma_fast, uint32_t* __restrict__ wide) {
     __shared__ uint64_t keys[kSortLdsCap];
     __shared__ uint32_t vals[kSortLdsCap];
     __shared__ uint32_t zo[kSortLdsCap];
-    int tile = blockIdx.x;
-    if (tile >= n_tiles) return;
-    uint32_t e0 = tile_off[tile], e1 = e0 + tile_cnt[tile];
-    uint32_t n = e1 - e0;
-    if (threadIdx.x == 0 && n) atomicAdd(misc + 3, n);   // entries the tracer reads
-    if (n > kSortLdsCap) {
-        if (threadIdx.x == 0) long_list[atomicAdd(misc + 0, 1u)] = uint32_t(tile);
-        return;
-    }
-    if (n == 0) {
-        if (threadIdx.x == 0) tile_ovl[tile] = 0;
-        return;
-    }
     __shared__ uint32_t ov;
-    sort_segment(keys, vals, zo, e0, e1, e_node, e_zin, e_zout, &ov);
-    if (threadIdx.x == 0) {
-        tile_ovl[tile] = ov;
-        atomicMax(misc + 1, ov);
-        atomicMax(misc + 2, n);
-        if (ov > ma_fast) wide[1 + atomicAdd(wide, 1u)] = uint32_t(tile);
+    const uint32_t n_queued = misc[10];
+    for (uint32_t idx = blockIdx.x; idx < n_queued; idx += gridDim.x) {
+        const uint32_t tile = queue[idx];
+        const uint32_t e0 = tile_off[tile], e1 = e0 + tile_cnt[tile];
+        const uint32_t n = e1 - e0;
+        if (n > uint32_t(kSortLdsCap)) {
+            if (threadIdx.x == 0) long_list[atomicAdd(misc + 0, 1u)] = tile;
+        } else {
+            sort_segment(keys, vals, zo, e0, e1, e_node, e_zin, e_zout, &ov);
+            if (threadIdx.x == 0) {
+                tile_ovl[tile] = ov;
+                if (ov > ma_fast) wide[1 + atomicAdd(wide, 1u)] = tile;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -1014,8 +1061,6 @@ __global__ void __launch_bounds__(kSortThreads) tile_sort_long_kernel(
         sort_segment(k, v, z, e0, e1, e_node, e_zin, e_zout, &ov);
         if (threadIdx.x == 0) {
             tile_ovl[tile] = ov;
-            atomicMax(misc + 1, ov);
-            atomicMax(misc + 2, e1 - e0);
             if (ov > ma_fast) wide[1 + atomicAdd(wide, 1u)] = tile;
         }
         __syncthreads();
@@ -1040,11 +1085,70 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t n, uint32_t v
     if (i < n) p[i] = v;
 }
 
+// Statistics of a build that reports them, from the per-tile records and
+// arrays (one workgroup, no contended atomics during the build): misc[1] the
+// largest depth overlap, misc[2] the longest kept list, misc[3] the kept
+// entries, misc[6] the tested candidates that hit, misc[7] the candidates
+// tested, pix[kind] the pixels tested.
+constexpr int kStatThreads = 1024;
+__global__ void __launch_bounds__(kStatThreads) build_stats_kernel(const uint32_t* __restrict__ tile_cnt,
+                                                                   const uint32_t* __restrict__ tile_ovl,
+                                                                   const uint32_t* __restrict__ tstat, int n_tiles,
+                                                                   uint32_t* __restrict__ misc,
+                                                                   unsigned long long* __restrict__ pix) {
+    __shared__ unsigned long long part[kStatThreads / 64][7];
+    const int tid = int(threadIdx.x), lane = tid & 63, w = tid >> 6;
+    // largest overlap, longest list, kept entries, tested candidates, tested pixels by kind
+    unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+    unsigned long long hits = 0;
+    for (int t = tid; t < n_tiles; t += kStatThreads) {
+        const uint32_t* r = tstat + kTileStat * size_t(t);
+        v[0] = max(v[0], (unsigned long long)tile_ovl[t]);
+        v[1] = max(v[1], (unsigned long long)tile_cnt[t]);
+        v[2] += tile_cnt[t];
+        v[3] += r[0];
+        v[4] += r[1];
+        v[5] += r[2];
+        v[6] += r[3];
+        hits += r[4];
+    }
+    for (int k = 0; k < 7; k++)
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long x = __shfl_xor(v[k], o);
+            v[k] = k < 2 ? max(v[k], x) : v[k] + x;
+        }
+    for (int o = 32; o > 0; o >>= 1) hits += __shfl_xor(hits, o);
+    __shared__ unsigned long long phits[kStatThreads / 64];
+    if (lane == 0) {
+        for (int k = 0; k < 7; k++) part[w][k] = v[k];
+        phits[w] = hits;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long r[7] = {0, 0, 0, 0, 0, 0, 0}, h = 0;
+        for (int q = 0; q < kStatThreads / 64; q++) {
+            for (int k = 0; k < 7; k++) r[k] = k < 2 ? max(r[k], part[q][k]) : r[k] + part[q][k];
+            h += phits[q];
+        }
+        misc[1] = uint32_t(r[0]);
+        misc[2] = uint32_t(r[1]);
+        misc[3] = uint32_t(r[2]);
+        misc[6] = uint32_t(h);
+        misc[7] = uint32_t(r[3]);
+        pix[0] = r[4];
+        pix[1] = r[5];
+        pix[2] = r[6];
+    }
+}
+
 // clears the counters of a build in one launch: tile counts (T + 1 words),
-// scatter cursors (T), misc (64) and the wide-list length (1)
+// scatter cursors (T), misc (64), the wide-list length (1) and the tiles'
+// statistics records (kTileStat T)
 __global__ void clear_build_kernel(uint32_t* __restrict__ tcnt, uint32_t* __restrict__ cur, uint32_t T,
-                                   uint32_t* __restrict__ misc, uint32_t* __restrict__ wide) {
+                                   uint32_t* __restrict__ misc, uint32_t* __restrict__ wide,
+                                   uint32_t* __restrict__ tstat) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < uint32_t(kTileStat) * T) tstat[i] = 0u;
     if (i <= T) tcnt[i] = 0u;
     if (i < T) cur[i] = 0u;
     if (i < 64u) misc[i] = 0u;
@@ -1065,7 +1169,8 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     const int T = s->n_tiles;
     const int ts = t.tile;
     // scratch layout (bytes): pixel rectangles P*16, tile ranges P*16, scan
-    // sums, tile counts (T+1)*4, cursors T*4, long list T*4, misc 64*4
+    // sums, tile counts (T+1)*4, cursors T*4, long list T*4, sort queue T*4,
+    // tile statistics records T*4*kTileStat, misc 64*4
     size_t nb_t = size_t(T + kScanBlock) / kScanBlock + 2;
     size_t off_rect = 0;
     size_t off_trect = align_up(off_rect + size_t(P) * 16);
@@ -1073,7 +1178,9 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     size_t off_tcnt = align_up(off_sums + nb_t * 4 + 16);
     size_t off_cur = align_up(off_tcnt + size_t(T + 1) * 4);
     size_t off_long = align_up(off_cur + size_t(T) * 4);
-    size_t off_misc = align_up(off_long + size_t(T) * 4);
+    size_t off_queue = align_up(off_long + size_t(T) * 4);
+    size_t off_tstat = align_up(off_queue + size_t(T) * 4);
+    size_t off_misc = align_up(off_tstat + size_t(T) * 4 * kTileStat);
     size_t need = align_up(off_misc + 64 * 4);
     if (replay && (need > s->scratch_bytes || !s->ab_valid)) {
         set_error("build replay: no previous build of this size");
@@ -1092,12 +1199,14 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     uint32_t* tcnt = (uint32_t*)(base + off_tcnt);
     uint32_t* cur = (uint32_t*)(base + off_cur);
     uint32_t* longl = (uint32_t*)(base + off_long);
+    uint32_t* tstat = (uint32_t*)(base + off_tstat);   // per tile: kTileStat words
+    uint32_t* queue = (uint32_t*)(base + off_queue);   // lists of more than 64 entries (count misc[10])
     uint32_t* misc = (uint32_t*)(base + off_misc);
     hipError_t e;
 #define ST_CHECK(x, what) do { e = (x); if (e != hipSuccess) return device_error(e, what); } while (0)
 
-    hipLaunchKernelGGL(clear_build_kernel, dim3((uint32_t(T) + 64u) / 256u + 1u), dim3(256), 0, stream, tcnt, cur,
-                       uint32_t(T), misc, s->d_wide);
+    hipLaunchKernelGGL(clear_build_kernel, dim3((uint32_t(kTileStat) * uint32_t(T) + 64u) / 256u + 1u), dim3(256), 0,
+                       stream, tcnt, cur, uint32_t(T), misc, s->d_wide, tstat);
     unsigned long long* pix = reinterpret_cast<unsigned long long*>(misc + 16);   // 3 counters, 8-byte aligned
     if (P) hipLaunchKernelGGL(rect_kernel, dim3((8 * P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
                        s->d_oside, s->d_sub, t.keep_all_entries, rect, trect);
@@ -1134,7 +1243,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipLaunchKernelGGL(cand_prune_kernel, dim3(T), dim3(kPruneThreads), 0, stream, s->d_tile_off, T, s->tiles_x, ts,
                        s->d_prims, rect, s->d_voi, s->d_e_node, s->d_tile_cnt, s->d_rmq,
                        reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
-                       t.keep_all_entries, misc + 7, pix);
+                       t.keep_all_entries, tstat);
     if (P && n_cand) {
         // order by candidates left, for the test and for the trace
         hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_cnt, T,
@@ -1178,14 +1287,17 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipLaunchKernelGGL(tile_prune_kernel, dim3(T), dim3(kPruneThreads), 0, stream, s->d_tile_off, T, s->d_e_node,
                        s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc, s->d_rmq,
                        reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
-                       t.keep_all_entries);
+                       t.keep_all_entries, tstat);
     hipLaunchKernelGGL(tile_prune_long_kernel, dim3(std::min(T, 512)), dim3(kPruneThreads), 0, stream,
                        s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc,
                        reinterpret_cast<uint32_t*>(lbuf), s->d_rmq, reinterpret_cast<const uint4*>(s->d_kslot),
-                       s->d_kill, uint32_t(s->n_nodes), t.keep_all_entries, misc + 6);
-    hipLaunchKernelGGL(tile_sort_kernel, dim3(T), dim3(kSortThreads), 0, stream, s->d_tile_off, s->d_tile_cnt, T,
-                       s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl, misc, uint32_t(s->ab_ma_fast),
-                       s->d_wide);
+                       s->d_kill, uint32_t(s->n_nodes), t.keep_all_entries, tstat);
+    hipLaunchKernelGGL(tile_sort_short_kernel, dim3((T + 3) / 4), dim3(256), 0, stream, s->d_tile_off,
+                       s->d_tile_cnt, T, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, queue, misc,
+                       uint32_t(s->ab_ma_fast), s->d_wide);
+    hipLaunchKernelGGL(tile_sort_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream, s->d_tile_off,
+                       s->d_tile_cnt, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, queue, longl, misc,
+                       uint32_t(s->ab_ma_fast), s->d_wide);
     // long tiles, if any (the kernel reads their count on the device)
     uint64_t* sk = (uint64_t*)lbuf;
     uint32_t* sv = (uint32_t*)(lbuf + size_t(2) * n_ent * 8);
@@ -1200,6 +1312,8 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         e = hipGetLastError();
         return e == hipSuccess ? ST_OK : device_error(e, "binning kernels");
     }
+    hipLaunchKernelGGL(build_stats_kernel, dim3(1), dim3(kStatThreads), 0, stream, s->d_tile_cnt, s->d_tile_ovl, tstat,
+                       T, misc, pix);
     uint32_t h_misc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, h_wide = 0;
     ST_CHECK(hipMemcpyAsync(h_misc, misc, 32, hipMemcpyDeviceToHost, stream), "copy build stats");
     ST_CHECK(hipMemcpyAsync(s->cand_pix, pix, 24, hipMemcpyDeviceToHost, stream), "copy candidate pixels");
