@@ -111,7 +111,8 @@ typedef struct {
                               of primitives that cannot reach the root for any
                               subset of their tile's list (every subfrustum
                               view stays the same; not in the paper);
-                              1: keep every entry */
+                              1: keep every entry whose volume of interest a
+                              pixel-centre ray of the tile meets */
     int32_t reserved[5];
 } st_tuning;
 
@@ -224,10 +225,14 @@ st_status st_update_primitives(st_scene *s, const int32_t *ids, const st_node *n
  * for every screen tile, the list of primitives whose volume of interest meets
  * a pixel-centre ray of the tile, with the tile's entry/exit view depth
  * (minimum entry, maximum exit over its rays), sorted by entry depth (ties by
- * primitive).  Built on the device by project -> count per tile -> scan ->
- * scatter candidates -> per-tile ray test -> tile-level pruning (see
- * keep_all_entries) -> per-tile sort; synchronizes `stream` twice to size the
- * A-buffer.  A build with the same camera and tuning as the scene's valid
+ * primitive).  Built on the device by project (each primitive's pixel
+ * rectangle; unless keep_all_entries, its candidate tiles cut to the screen
+ * rectangles of the subtree boxes on the other side of its killing
+ * ancestors) -> count per tile -> scan -> scatter candidates -> pruning of
+ * each tile's candidate set -> per-tile ray test -> tile-level pruning of the
+ * hits -> per-tile sort; the three cuts (see keep_all_entries) leave every
+ * tile with the entries of the primitives that survive the dead-primitive
+ * rule for its hits.  Synchronizes `stream` twice to size the A-buffer.  A build with the same camera and tuning as the scene's valid
  * A-buffer reruns every kernel with the sizes of the last build and does not
  * synchronize (the sizes are a function of scene, camera and tuning).
  *   cam (host), t (host, NULL = defaults).  The A-buffer is kept in the scene
