@@ -268,6 +268,65 @@ def test_dead_primitive_filter_keeps_the_view(seed):
     assert dropped > 0
 
 
+def _cut_by_ancestors(sc, cand, hits):
+    """The candidates left by the killing-ancestor cut, written on sets: a
+    candidate goes when one of its killing ancestors (an intersection, or a
+    difference reached from the right) has no hit in its other operand."""
+    parent = {}
+    for v in range(len(sc.kind)):
+        if sc.kind[v] >= 16:
+            parent[int(sc.left[v])] = (v, 0)
+            parent[int(sc.right[v])] = (v, 1)
+
+    def leaves(v):
+        return [v] if sc.kind[v] < 16 else leaves(int(sc.left[v])) + leaves(int(sc.right[v]))
+
+    h = set(hits)
+    out = []
+    for x in cand:
+        v, ok = x, True
+        while v in parent and ok:
+            pv, side = parent[v]
+            im = IGNORE[int(sc.kind[pv])]
+            kills = (im & 1) if side == 0 else (im & 2)
+            other = int(sc.right[pv]) if side == 0 else int(sc.left[pv])
+            if kills and not h.intersection(leaves(other)):
+                ok = False
+            v = pv
+        if ok:
+            out.append(x)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_candidate_cuts_keep_the_alive_set(seed):
+    """The binning's three cuts leave a tile the primitives alive for its
+    hits H, whatever superset C of H its candidates are: the killing-ancestor
+    cut keeps every primitive alive for H; the rule on the remaining
+    candidates keeps them too; and the rule on the hits left by both gives
+    alive(H), as it does from any set between alive(H) and H."""
+    rng = np.random.default_rng(700 + seed)
+    cut = 0
+    for rep in range(30):
+        n = int(rng.integers(5, 30))
+        sc = sg.random_small_tree(seed * 1000 + rep, n, ops=tuple(OPS))
+        prims = [int(p) for p in np.nonzero(sc.kind < 16)[0]]
+        for _ in range(8):
+            cand = sorted(p for p in prims if rng.random() < rng.uniform(0.3, 1.0))
+            hits = sorted(p for p in cand if rng.random() < rng.uniform(0.2, 1.0))
+            alive_h = _kill_filter(sc, hits)
+            c1 = _cut_by_ancestors(sc, cand, hits)
+            assert set(alive_h) <= set(c1)
+            c2 = _kill_filter(sc, c1)
+            assert set(alive_h) <= set(c2)
+            tested_hits = sorted(set(hits) & set(c2))
+            assert _kill_filter(sc, tested_hits) == alive_h
+            between = sorted(set(alive_h) | {x for x in hits if rng.random() < 0.5})
+            assert _kill_filter(sc, between) == alive_h
+            cut += len(cand) - len(c2)
+    assert cut > 0
+
+
 def test_prune_left_comb_union_only_keeps_active_operators():
     """Left comb of unions (Section 7 inset): with k active primitives the
     view holds those k primitives and k-1 operators, never the skipped ones."""
