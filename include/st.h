@@ -94,7 +94,7 @@ typedef struct {
     int32_t max_new;       /* new primitives fetched per subfrustum, >= 1 (values
                               above 4096 act as 4096)
                               (paper: 6) */
-    float eps;             /* minimum step and probing step, scene units */
+    float eps;             /* minimum step: the shortest probe, scene units */
     int32_t max_steps;     /* field evaluations per ray for stepping */
     int32_t refine_iters;  /* bracket refinement iterations after a crossing */
     int32_t step_mode;     /* ST_STEP_*: PLAIN, the safe step f/L; OVERRELAX,
@@ -113,7 +113,16 @@ typedef struct {
                               view stays the same; not in the paper);
                               1: keep every entry whose volume of interest a
                               pixel-centre ray of the tile meets */
-    int32_t reserved[5];
+    float probe_step;      /* where the safe step f/L falls below this (scene
+                              units; values below eps act as eps) the ray
+                              probes forward instead: by the secant estimate
+                              of the distance to the root (at least eps, at
+                              most 4x the last probe) while f falls, by twice
+                              the last probe while f rises, never by less
+                              than f/L; a sign change is refined by regula
+                              falsi.  The paper steps by max(f/L, minimum
+                              step) (Section 10, Ray processing); default 1e-3 */
+    int32_t reserved[4];
 } st_tuning;
 
 /* Counters of one st_trace call (all 64-bit). */

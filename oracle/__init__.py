@@ -63,6 +63,8 @@ def lib():
         L.or_march.argtypes = [C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp, C.c_int, C.c_double, _dp]
         L.or_voi_intervals.argtypes = [C.c_void_p, _dp, C.c_int, C.c_int, _dp, _dp, C.c_int, _ip,
                                        C.c_int, _dp]
+        L.or_crease_at.restype = C.c_int
+        L.or_crease_at.argtypes = [C.c_void_p, _dp]
         L.or_in_voi.restype = C.c_int
         L.or_in_voi.argtypes = [C.c_void_p, C.c_int, _dp]
         L.or_prim.restype = C.c_double
@@ -143,6 +145,10 @@ class OracleScene:
 
     def prim(self, i: int, x) -> float:
         return lib().or_prim(self._h, int(i), np.ascontiguousarray(x, dtype=np.float64))
+
+    def crease_at(self, x) -> bool:
+        """Sharp-crease flag of the point x (two operands of a sharp branch within 1e-6)."""
+        return bool(lib().or_crease_at(self._h, np.ascontiguousarray(x, dtype=np.float64)))
 
     def in_voi(self, i: int, x) -> bool:
         return bool(lib().or_in_voi(self._h, int(i), np.ascontiguousarray(x, dtype=np.float64)))

@@ -486,6 +486,14 @@ static int crease_walk(const or_scene *s, int i, const double x[3], double *val)
     return c;
 }
 
+/* Crease flag of the point x (the walk above from the root).  Parity pinned
+ * by analytic crease circles of two-sphere sharp operators, off-crease
+ * surface points, compact blends and a nested difference. */
+int or_crease_at(const or_scene *s, const double x[3]) {
+    double val;
+    return crease_walk(s, s->root, x, &val);
+}
+
 /* Trace the rays of pixels (px[i], py[i]) (pixel-centre coordinates, i.e.
  * col + 0.5, row + 0.5), optionally displaced parallel to themselves by
  * (off_r, off_u) along the camera right/up axes.

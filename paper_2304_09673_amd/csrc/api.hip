@@ -130,6 +130,7 @@ static st_status check_tuning(const st_tuning& t) {
     if (!(t.omega >= 1.f) || !(t.omega <= 4.f)) { set_error("tuning: omega outside [1, 4]"); return ST_E_INVALID; }
     if (!(t.lipschitz >= 0.f) || !std::isfinite(t.lipschitz)) { set_error("tuning: lipschitz < 0"); return ST_E_INVALID; }
     if (t.keep_all_entries != 0 && t.keep_all_entries != 1) { set_error("tuning: keep_all_entries must be 0 or 1"); return ST_E_INVALID; }
+    if (!std::isfinite(t.probe_step)) { set_error("tuning: probe_step not finite"); return ST_E_INVALID; }
     return ST_OK;
 }
 
@@ -167,6 +168,7 @@ st_status st_default_tuning(st_tuning* t) {
     t->step_mode = ST_STEP_PLAIN;
     t->omega = 1.7f;
     t->lipschitz = 0.f;
+    t->probe_step = 1e-3f;
     return ST_OK;
 }
 

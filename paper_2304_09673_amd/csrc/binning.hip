@@ -1244,10 +1244,12 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
                        s->d_prims, rect, s->d_voi, s->d_e_node, s->d_tile_cnt, s->d_rmq,
                        reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
                        t.keep_all_entries, tstat);
+    // order by candidates left, for the test and for the trace.  Every build
+    // writes it, also one without candidates (all counts zero: the identity
+    // up to bucket order), because the trace reads it for every block.
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_cnt, T,
+                       s->d_tile_order);
     if (P && n_cand) {
-        // order by candidates left, for the test and for the trace
-        hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, s->d_tile_cnt, T,
-                           s->d_tile_order);
         hipEvent_t* ev = nullptr;
         if (s->time_test) {   // a fresh pair per launch (created once, reused after a restart)
             if (s->test_used * 2 + 2 > s->test_events.size()) {

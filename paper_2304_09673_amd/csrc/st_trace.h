@@ -97,7 +97,7 @@ struct TraceArgs {
     DevCam cam;
     int ts, tiles_x, tiles_y, sub_x;   // sub_x = ts / 8
     uint32_t ma_fast;
-    float eps, d_sub, lip_fixed, omega;
+    float eps, probe, d_sub, lip_fixed, omega;   // probe >= eps: safe steps below it probe
     int max_steps, refine_iters, max_new, step_mode;
     float* out_depth;
     float* out_normal;
@@ -755,7 +755,7 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                     chk_ok = !chk || (v > 0.f && (vb + v) * invL >= t - tb);
                 }
                 const float sp = v * invL;
-                need = mode == M_TRACE && chk_ok && v > 0.f && sp >= A.eps && t + sp < t1 && !(t < relax_until);
+                need = mode == M_TRACE && chk_ok && v > 0.f && sp >= A.probe && t + sp < t1 && !(t < relax_until);
                 if constexpr (SM == SM_LEARNED || SM == SM_DUMP) {
                     if (ballot(need) != 0) {
                         float f[8];
@@ -815,20 +815,30 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                         if (!(t > ra && t < rb)) t = 0.5f * (ra + rb);
                     }
                 } else {
-                    float s = v * invL;
-                    bool safe = s >= A.eps;
-                    if (!safe) {
-                        // probe: the secant estimate of the distance to the
-                        // root (it under-estimates the entry of a convex dip,
-                        // so a thin sliver is not jumped), at least eps, at
-                        // most 4x the previous probe
-                        float sec = (tp_ok && vp > v) ? v * (t - tp) / (vp - v) : 0.f;
-                        s = fminf(fmaxf(sec, A.eps), 4.f * fmaxf(hp, A.eps));
+                    const float safe_s = v * invL;
+                    float s = safe_s;
+                    if (!(safe_s >= A.probe)) {
+                        // probe.  While f falls: the secant estimate of the
+                        // distance to the root (it under-estimates the entry
+                        // of a convex dip, so a thin sliver is not jumped),
+                        // at least eps, at most 4x the previous probe.  While
+                        // f rises the ray moves away from the surface it
+                        // grazed: twice the previous probe, until the safe
+                        // step exceeds the probe threshold again.  Never
+                        // shorter than the safe step.
+                        const bool falling = tp_ok && vp > v;
+                        const float hb = fmaxf(hp, A.eps);
+                        float pr;
+                        if (falling) pr = fminf(fmaxf(v * (t - tp) / (vp - v), A.eps), 4.f * hb);
+                        else pr = tp_ok ? 2.f * hb : A.eps;
+                        s = fmaxf(pr, safe_s);
                         hp = s;
                     } else {
                         hp = 0.f;
                     }
-                    last_safe = safe;
+                    // certified: the step is the safe one (a crossing found
+                    // at its end is the root itself)
+                    last_safe = !(s > safe_s);
                     tp = t; vp = v; tp_ok = true;
                     float tn = t + s;
                     if constexpr (kRelax) {

@@ -51,7 +51,8 @@ class StTuning(C.Structure):
     _fields_ = [("tile", C.c_int32), ("max_active", C.c_int32), ("sub_depth", C.c_float),
                 ("max_new", C.c_int32), ("eps", C.c_float), ("max_steps", C.c_int32),
                 ("refine_iters", C.c_int32), ("step_mode", C.c_int32), ("omega", C.c_float),
-                ("lipschitz", C.c_float), ("keep_all_entries", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("lipschitz", C.c_float), ("keep_all_entries", C.c_int32), ("probe_step", C.c_float),
+                ("reserved", C.c_int32 * 4)]
 
 
 class StStats(C.Structure):

@@ -23,13 +23,21 @@ def gpu_render(sc, tuning=None):
     return s, d.cpu().numpy(), n.cpu().numpy(), stats
 
 
-def compare(sc, depth, normal, px, py, osc=None):
-    """Parity of GPU outputs at integer pixels (px, py) against the oracle.
-    Returns a dict of counts; 'fail' must be 0."""
+def oracle_ref(osc, cam, px, py):
+    """The oracle's (t, normal, flags) at integer pixels, for reuse across
+    several GPU images of the same frame."""
+    t, nrm, flag, _ = osc.trace(cam, px.astype(np.float64) + 0.5, py.astype(np.float64) + 0.5)
+    return t, nrm, flag
+
+
+def compare(sc, depth, normal, px, py, osc=None, ref=None):
+    """Parity of GPU outputs at integer pixels (px, py) against the oracle
+    (ref: a precomputed oracle_ref of the same pixels).  Returns a dict of
+    counts; 'fail' must be 0."""
     osc = osc or oracle.OracleScene(sc)
     cam = sc.camera
     fx, fy = px.astype(np.float64) + 0.5, py.astype(np.float64) + 0.5
-    t, nrm, flag, _ = osc.trace(cam, fx, fy)
+    t, nrm, flag = ref if ref is not None else oracle_ref(osc, cam, px, py)
     hit_o = (flag & 1) != 0
     undecided = (flag & 2) != 0
     crease = (flag & 4) != 0
@@ -51,12 +59,16 @@ def compare(sc, depth, normal, px, py, osc=None):
         exempt[idx] = oracle.silhouette_flags(osc, cam, fx[idx], fy[idx], np.where(hit_o, t, np.inf)[idx],
                                               hit_o[idx], tol, SIL_OFFSET)
     fail = suspect & ~exempt
+    good = both & ~suspect
+    rel = dz / osc.extent
     return {
         "rays": int(px.shape[0]), "hits_oracle": int(hit_o.sum()), "hits_gpu": int(hit_g.sum()),
         "mask_mismatch": int(mask_bad.sum()), "depth_bad": int(depth_bad.sum()), "normal_bad": int(normal_bad.sum()),
         "exempt": int((suspect & exempt).sum()), "undecided": int(undecided.sum()), "crease": int(crease.sum()),
         "fail": int(fail.sum()), "fail_idx": np.nonzero(fail)[0][:20].tolist(),
-        "max_depth_err_rel": float(dz[both & ~suspect].max() / osc.extent) if (both & ~suspect).any() else 0.0,
+        "hits_compared": int(good.sum()),
+        "max_depth_err_rel": float(rel[good].max()) if good.any() else 0.0,
+        "p99_depth_err_rel": float(np.percentile(rel[good], 99)) if good.any() else 0.0,
         "max_normal_err": float(ang[both & ~crease & ~suspect].max()) if (both & ~crease & ~suspect).any() else 0.0,
         "extent": osc.extent,
     }
@@ -70,3 +82,30 @@ def all_pixels(cam):
 def sample_pixels(cam, n, seed):
     rng = np.random.default_rng(seed)
     return rng.integers(0, cam.width, n), rng.integers(0, cam.height, n)
+
+
+def stratified_pixels(cam, depths, n_random, seed, ring=True, max_hits=None):
+    """Parity sample of a frame where few pixels hit: n_random seeded uniform
+    pixels, the pixels that any of the GPU depth images hits (all of them, or
+    a seeded subset of max_hits), and with ring their 8-neighbours (where a
+    hit the GPU missed is most likely).  Unique pixels (px, py)."""
+    W, H = cam.width, cam.height
+    rng = np.random.default_rng(seed)
+    sel = np.zeros(H * W, dtype=bool)
+    sel[rng.choice(H * W, size=min(n_random, H * W), replace=False)] = True
+    hit = np.zeros((H, W), dtype=bool)
+    for d in depths:
+        hit |= np.isfinite(d)
+    hit_idx = np.flatnonzero(hit)
+    if max_hits is not None and hit_idx.shape[0] > max_hits:
+        hit_idx = np.sort(rng.choice(hit_idx, size=max_hits, replace=False))
+    if ring:
+        near = np.zeros((H, W), dtype=bool)
+        hy, hx = np.unravel_index(hit_idx, (H, W))
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                near[np.clip(hy + dy, 0, H - 1), np.clip(hx + dx, 0, W - 1)] = True
+        sel |= near.ravel()
+    sel[hit_idx] = True
+    idx = np.flatnonzero(sel)
+    return idx % W, idx // W

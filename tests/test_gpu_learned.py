@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import scenegen as sg
-from gpu_util import all_pixels, compare, sample_pixels
+from gpu_util import all_pixels, compare, oracle_ref, sample_pixels, stratified_pixels
 
 pytestmark = pytest.mark.gpu
 
@@ -137,10 +137,30 @@ def _timed(s, reps=3):
     return float(np.median(ts)), d, n
 
 
+# "Equal depth error" (learned against plain): both tracers end every hit
+# with the same bracket refinement, so their depth errors against the oracle
+# are set by FP32 evaluation noise near the root and differ from ray to ray
+# by that noise.  The learned tracer's p99 and maximum error may not exceed
+# the plain tracer's by more than EQUAL_SLACK (relative to the scene extent),
+# 1% of the parity tolerance.
+EQUAL_SLACK = 1e-6
+
+
+def _equal_depth_error(errs):
+    for q in ("p99_depth_err_rel", "max_depth_err_rel"):
+        assert errs["learned"][q] <= errs["plain"][q] + EQUAL_SLACK, (q, errs)
+
+
+def _mask_differences(d_ref, d_other):
+    jj, ii = np.nonzero(np.isfinite(d_ref) != np.isfinite(d_other))
+    return ii, jj
+
+
 def test_learned_vs_plain_on_large_scene(model):
-    """16384 primitives of the second workload's laws at 480x270: identical hit
-    masks, depth error against the oracle no worse than plain on sampled hit
-    rays; steps and time are reported."""
+    """16384 primitives of the second workload's laws at 480x270: every hit
+    pixel of any tracer plus random ones against the oracle; the learned
+    tracer's depth error equals the plain one's; hit masks differ only on
+    exempt rays."""
     st = _st()
     sc = sg.config5(width=480, height=270)
     kw = {"tile": 16, "max_new": 64, "sub_depth": 0.25}
@@ -154,58 +174,55 @@ def test_learned_vs_plain_on_large_scene(model):
         _, _, stats = s.trace()
         ms, d, n = _timed(s)
         out[name] = (ms, d.cpu().numpy(), n.cpu().numpy(), stats)
-    d_p = out["plain"][1]
-    hit = np.isfinite(d_p)
-    mis = np.zeros_like(hit)
-    for name in ("overrelax", "learned"):
-        mis |= np.isfinite(out[name][1]) != hit
-    assert mis.sum() <= 4, int(mis.sum())
-    # depth error on up to 96 hit pixels plus 32 random ones, plus every pixel
-    # whose hit/miss differs between the tracers (must be exempt or correct)
-    jj, ii = np.nonzero(hit)
-    rng = np.random.default_rng(3)
-    pick = rng.permutation(jj.shape[0])[:96]
-    rx, ry = sample_pixels(sc.camera, 32, 4)
-    mj, mi = np.nonzero(mis)
-    px = np.concatenate([ii[pick], rx, mi])
-    py = np.concatenate([jj[pick], ry, mj])
+    px, py = stratified_pixels(sc.camera, [out[k][1] for k in out], 2048, 4, ring=False)
     osc = oracle.OracleScene(sc)
+    ref = oracle_ref(osc, sc.camera, px, py)
     errs = {}
     for name in ("plain", "overrelax", "learned"):
-        r = compare(sc, out[name][1], out[name][2], px, py, osc=osc)
+        r = compare(sc, out[name][1], out[name][2], px, py, osc=osc, ref=ref)
+        print(f"[{name}] " + " ".join(f"{k}={v}" for k, v in r.items() if k != "fail_idx"), flush=True)
         assert r["fail"] == 0, (name, r)
-        errs[name] = r["max_depth_err_rel"]
-    assert errs["learned"] <= max(2.0 * errs["plain"], 1e-6)
+        errs[name] = r
+    _equal_depth_error(errs)
     for name in out:
         ms, _, _, stats = out[name]
         print(f"{name}: {ms:.2f} ms, {sc.camera.width * sc.camera.height / ms / 1e3:.2f} Mrays/s, "
               f"steps {stats['steps']}, evals {stats['field_evals']}, accepted {stats['learned_accepted']}, "
               f"rejected {stats['learned_rejected']}")
-    print("depth error (max rel):", errs)
 
 
+@pytest.mark.timeout(900)
 def test_full_size_large_scene_sampled(model):
     """The full 3840x2160 frame of 16384 primitives in the launch
-    configuration of the comparison: plain and learned agree on every hit/miss
-    and match the oracle on sampled pixels (hit pixels and random ones)."""
+    configuration of the comparison (the autotuner's choice for the plain
+    step): at least 2,000 hit rays (seeded from the hit pixels of both
+    tracers) plus 2,048 random pixels against the oracle.  Both pass parity;
+    the learned tracer's p99 and maximum depth error equal the plain one's;
+    every pixel whose hit/miss differs between them is exempt (within 1e-4 of
+    a silhouette)."""
     st = _st()
     sc = sg.config5()
-    kw = {"tile": 16, "max_new": 64, "sub_depth": 0.25}
+    s = st.Scene(sc)
+    tuned, _ = s.autotune(sc.camera, reps=1)
+    s.close()
+    kw = {"tile": tuned.tile, "max_new": tuned.max_new, "sub_depth": tuned.sub_depth}
+    print(f"\n[c5] tuning {kw}", flush=True)
     d_p, n_p, s_p = _render(sc, st.ST_STEP_PLAIN, tuning_kw=kw)
     d_l, n_l, s_l = _render(sc, st.ST_STEP_LEARNED, model=model, tuning_kw=kw)
     assert s_p["unconverged"] == 0 and s_l["unconverged"] == 0
     assert s_p["stalled"] == 0 and s_l["stalled"] == 0
-    # hit/miss may differ only on rays the parity rules exempt (within 1e-4 of
-    # a silhouette): every pixel where the two differ is checked against the oracle
-    mis_j, mis_i = np.nonzero(np.isfinite(d_l) != np.isfinite(d_p))
-    assert mis_j.shape[0] <= 16, mis_j.shape[0]
-    jj, ii = np.nonzero(np.isfinite(d_p))
-    rng = np.random.default_rng(11)
-    pick = rng.permutation(jj.shape[0])[:48]
-    rx, ry = sample_pixels(sc.camera, 32, 12)
-    px = np.concatenate([ii[pick], rx, mis_i])
-    py = np.concatenate([jj[pick], ry, mis_j])
+    mi, mj = _mask_differences(d_p, d_l)
+    px, py = stratified_pixels(sc.camera, [d_p, d_l], 2048, 12, ring=False, max_hits=2600)
+    px, py = np.concatenate([px, mi]), np.concatenate([py, mj])
+    print(f"[c5] {px.shape[0]} pixels, {mi.shape[0]} hit/miss differences between the tracers", flush=True)
     osc = oracle.OracleScene(sc)
+    ref = oracle_ref(osc, sc.camera, px, py)
+    print("[c5] oracle done", flush=True)
+    errs = {}
     for name, d, n in (("plain", d_p, n_p), ("learned", d_l, n_l)):
-        r = compare(sc, d, n, px, py, osc=osc)
+        r = compare(sc, d, n, px, py, osc=osc, ref=ref)
+        print(f"[c5 {name}] " + " ".join(f"{k}={v}" for k, v in r.items() if k != "fail_idx"), flush=True)
         assert r["fail"] == 0, (name, r)
+        assert r["hits_compared"] >= 2000, (name, r)
+        errs[name] = r
+    _equal_depth_error(errs)

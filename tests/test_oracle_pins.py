@@ -529,3 +529,134 @@ def test_mlp_forward_hand_example():
     # the over-prediction weight scales only the terms with omega > t
     loss16, _, _ = oracle.mlp(W, np.ones((3, 8)), np.array([2.5, 2.0, 3.0]), over_weight=16.0)
     assert loss16 == pytest.approx((0 + 16 * 0.25 + 0.25) / 3, rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Sharp-crease flag.  Normals are exempt from the parity check only where the
+# field's gradient direction is not unique: two operands of a sharp branch
+# (a sharp CSG node, or a compact node outside its operator range) are equal
+# there.  Two spheres of radius 0.5 at (0,0,0) and (0.3,0,0) meet on the
+# analytic circle x = 0.15, y^2 + z^2 = 0.25 - 0.15^2.
+
+def _crease_circle(phi):
+    r = math.sqrt(0.25 - 0.15 ** 2)
+    return np.array([0.15, r * math.cos(phi), r * math.sin(phi)])
+
+
+def _on_sphere(centre, radius, x):
+    """The point of the sphere surface at x-coordinate x (y > 0, z = 0)."""
+    y = math.sqrt(radius ** 2 - (x - centre[0]) ** 2)
+    return np.array([x, y, 0.0])
+
+
+@pytest.mark.parametrize("kind", [sg.UNION, sg.INTER, sg.DIFF])
+def test_crease_flag_on_the_analytic_crease_circle(kind):
+    o = _op_scene(kind)
+    c1 = float(np.float32(0.3))
+    for phi in np.linspace(0.1, 2 * math.pi, 9):
+        x = _crease_circle(phi)
+        x[0] = 0.5 * c1          # the bisector plane of the float32 centres
+        x[1:] *= math.sqrt(0.25 - x[0] ** 2) / np.linalg.norm(x[1:])
+        assert o.crease_at(x), (kind, phi)
+
+
+def test_crease_flag_off_the_crease_on_each_surface():
+    """A surface point 1e-3 away from the crease circle is not a crease."""
+    c1 = float(np.float32(0.3))
+    # union: on the outer part of sphere 0 (x < 0.15) and of sphere 1 (x > 0.15)
+    o = _op_scene(sg.UNION)
+    assert not o.crease_at(_on_sphere((0, 0, 0), 0.5, 0.5 * c1 - 1e-3))
+    assert not o.crease_at(_on_sphere((c1, 0, 0), 0.5, 0.5 * c1 + 1e-3))
+    # intersection: on the inner parts
+    o = _op_scene(sg.INTER)
+    assert not o.crease_at(_on_sphere((c1, 0, 0), 0.5, 0.5 * c1 - 1e-3))
+    assert not o.crease_at(_on_sphere((0, 0, 0), 0.5, 0.5 * c1 + 1e-3))
+    # difference sphere0 \ sphere1: the outer part of sphere 0, and the part of
+    # sphere 1 inside sphere 0
+    o = _op_scene(sg.DIFF)
+    assert not o.crease_at(_on_sphere((0, 0, 0), 0.5, 0.5 * c1 - 1e-3))
+    assert not o.crease_at(_on_sphere((c1, 0, 0), 0.5, 0.5 * c1 - 1e-3))
+
+
+@pytest.mark.parametrize("kind", [sg.SUNION, sg.SINTER, sg.SDIFF])
+def test_crease_flag_never_on_a_compact_blend(kind):
+    """Inside the operator range the compact operators blend (C1 field): the
+    crease circle of the two spheres is no crease of the blended field."""
+    o = _op_scene(kind)
+    c1 = float(np.float32(0.3))
+    for phi in np.linspace(0.1, 2 * math.pi, 9):
+        x = _crease_circle(phi)
+        x[0] = 0.5 * c1
+        assert not o.crease_at(x), (kind, phi)
+
+
+def test_crease_flag_of_a_compact_operator_outside_its_range():
+    """Outside R_o a compact union is the sharp min: equal operands there are
+    a crease (points of the bisector plane far from both spheres)."""
+    o = _op_scene(sg.SUNION)
+    c1 = float(np.float32(0.3))
+    assert o.crease_at(np.array([0.5 * c1, 0.0, 2.0]))
+    assert not o.crease_at(np.array([0.5 * c1 + 1e-3, 0.0, 2.0]))
+
+
+def test_crease_flag_uses_the_negated_right_operand_of_a_difference():
+    """Union of C with (A \\ B) at a point of C's surface where A and B are
+    equally far (a = b > 0): the difference node compares a with -b, which
+    differ by 2a, so nothing is a crease there; a walk comparing a with b
+    would flag it."""
+    kind = np.array([sg.SPHERE, sg.SPHERE, sg.DIFF, sg.SPHERE, sg.UNION], dtype=np.int32)
+    left = np.array([-1, -1, 0, -1, 3], dtype=np.int32)
+    right = np.array([-1, -1, 1, -1, 2], dtype=np.int32)
+    p = np.zeros((5, 16), dtype=np.float32)
+    p[0, :4] = (-0.25, 0, 0, 0.2)
+    p[1, :4] = (0.25, 0, 0, 0.2)
+    p[3, :4] = (0, 0.75, 0, 0.25)
+    o = oracle.OracleScene(kind=kind, left=left, right=right, params=p, root=4)
+    x = np.array([0.0, 0.5, 0.0])          # on C's surface, on the bisector of A and B
+    assert abs(o.eval(x[None])[0]) < 1e-7
+    assert not o.crease_at(x)
+    # and the difference's own crease (A's surface meets B's) is flagged
+    o2 = oracle.OracleScene(kind=kind[:3], left=left[:3], right=right[:3], params=p[:3], root=2)
+    assert not o2.crease_at(np.array([-0.45, 0.0, 0.0]))
+
+
+# ---------------------------------------------------------------------------
+# Scene extent (the unit of the depth tolerance): the largest edge of the
+# axis-aligned box of the primitives themselves, not of their volumes of
+# interest.
+
+def test_scene_extent_by_hand_for_a_rotated_box_and_a_capsule():
+    c8, s8 = math.cos(math.pi / 8), math.sin(math.pi / 8)
+    kind = np.array([sg.BOX, sg.CAPSULE, sg.SUNION], dtype=np.int32)
+    left = np.array([-1, -1, 0], dtype=np.int32)
+    right = np.array([-1, -1, 1], dtype=np.int32)
+    p = np.zeros((3, 16), dtype=np.float32)
+    p[0, :10] = (0.1, -0.2, 0.05, 0.2, 0.1, 0.3, c8, 0, 0, s8)   # 45 degrees about z
+    p[1, :7] = (1.0, 0.0, 0.0, 1.5, 0.5, 0.0, 0.1)
+    p[2, :2] = (0.1, 0.0)
+    o = oracle.OracleScene(kind=kind, left=left, right=right, params=p, root=2)
+    # box: half extents along x and y (0.2 + 0.1)/sqrt(2), along z 0.3
+    hxy = 0.3 / math.sqrt(2)
+    x_lo, x_hi = 0.1 - hxy, 1.5 + 0.1
+    y_lo, y_hi = -0.2 - hxy, 0.5 + 0.1
+    z_lo, z_hi = 0.05 - 0.3, 0.05 + 0.3
+    want = max(x_hi - x_lo, y_hi - y_lo, z_hi - z_lo)
+    assert want == pytest.approx(1.5 + 0.1 - 0.1 + hxy)
+    assert o.extent == pytest.approx(want, abs=2e-6)
+    # the volumes of interest are larger: the box's local half extents and
+    # the capsule's radius grow by the operator range d = 7k/6, so along x
+    # the box side moves by 2d/sqrt(2) and the capsule side by d
+    d = 7 * float(np.float32(0.1)) / 6
+    lo, hi = o.voi_box()
+    assert (hi - lo).max() == pytest.approx((1.5 + 0.1 + d) - (0.1 - (0.3 + 2 * d) / math.sqrt(2)), abs=2e-6)
+    assert o.extent < (hi - lo).max() - 0.2
+
+
+def test_scene_extent_of_a_lone_rotated_box():
+    """A box rotated 45 degrees about z: its x edge is (h0 + h1) sqrt(2), not 2 h0."""
+    c8, s8 = math.cos(math.pi / 8), math.sin(math.pi / 8)
+    kind = np.array([sg.BOX], dtype=np.int32)
+    p = np.zeros((1, 16), dtype=np.float32)
+    p[0, :10] = (0, 0, 0, 0.5, 0.1, 0.1, c8, 0, 0, s8)
+    o = oracle.OracleScene(kind=kind, left=np.array([-1], np.int32), right=np.array([-1], np.int32), params=p, root=0)
+    assert o.extent == pytest.approx(0.6 * math.sqrt(2), abs=2e-6)
