@@ -324,13 +324,15 @@ def test_camera_facing_away_gives_an_empty_image():
         assert bool((normal == 0).all())
 
 
-@pytest.mark.parametrize("max_active", [4, 16])
-def test_small_capacity_runs_the_wide_path_with_the_same_image(max_active):
+@pytest.mark.parametrize("n_prims,max_active", [(142, 4), (1024, 16)])
+def test_small_capacity_runs_the_wide_path_with_the_same_image(n_prims, max_active):
     """Tiles whose volumes of interest overlap more than max_active run on the
     wide-capacity path (never a failure): the image is bitwise that of the
-    default capacity, and matches the oracle."""
+    default capacity, and matches the oracle.  The second workload's laws at
+    256x256; with 142 primitives the kept overlap reaches 8, with 1024 it
+    passes 16."""
     from paper_2304_09673_amd import st
-    sc = sg.config2(0, 256, 256)
+    sc = sg.config2(0, 256, 256, n_prims=n_prims)
     _, d0, n0, s0 = gpu_render(sc, st.default_tuning())
     _, d1, n1, s1 = gpu_render(sc, st.default_tuning(max_active=max_active))
     print(f"\n[capacity {max_active}] wide tiles {s1['wide_tiles']} (default {s0['wide_tiles']}), "
