@@ -79,7 +79,7 @@ typedef struct {
     int32_t width, height; /* > 0 */
 } st_camera;
 
-enum { ST_STEP_PLAIN = 0, ST_STEP_OVERRELAX = 1, ST_STEP_LEARNED = 2 };
+enum { ST_STEP_PLAIN = 0, ST_STEP_OVERRELAX = 1, ST_STEP_LEARNED = 2, ST_STEP_SEGMENT = 3 };
 
 /* Tuning of the A-buffer build and the tracer.  st_default_tuning() fills the
  * paper's defaults where it gives one (Section 10, Implementation details). */
@@ -102,7 +102,17 @@ typedef struct {
                               of radius f/L at both ends overlap, else the plain
                               step (Section 10, Ray processing); LEARNED, the
                               same test with omega from the step model
-                              (st_set_step_model; not in the paper) */
+                              (st_set_step_model; not in the paper); SEGMENT,
+                              segment tracing (Galin et al. 2020, which the
+                              paper names as the more robust replacement of
+                              its global Lipschitz constant, Section 2 and
+                              Section 10): the step is the longer of f/L and
+                              min(c, f/lam), lam a bound on the field's
+                              derivative along the ray over the candidate
+                              segment [t, t+c] (compact operators whose two
+                              operands cannot both reach d_o on it count as
+                              min/max), and the next candidate is twice the
+                              step */
     float omega;           /* over-relaxation factor for ST_STEP_OVERRELAX, in
                               [1, 4] (paper: 1.7) */
     float lipschitz;       /* 0: proven bound of each pruned view; > 0: this

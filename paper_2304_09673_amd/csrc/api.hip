@@ -126,7 +126,7 @@ static st_status check_tuning(const st_tuning& t) {
     if (t.max_new < 1) { set_error("tuning: max_new < 1"); return ST_E_INVALID; }
     if (!(t.eps > 0.f) || !std::isfinite(t.eps)) { set_error("tuning: eps must be > 0"); return ST_E_INVALID; }
     if (t.max_steps < 1 || t.refine_iters < 0 || t.refine_iters > 64) { set_error("tuning: step limits"); return ST_E_INVALID; }
-    if (t.step_mode < ST_STEP_PLAIN || t.step_mode > ST_STEP_LEARNED) { set_error("tuning: step_mode"); return ST_E_INVALID; }
+    if (t.step_mode < ST_STEP_PLAIN || t.step_mode > ST_STEP_SEGMENT) { set_error("tuning: step_mode"); return ST_E_INVALID; }
     if (!(t.omega >= 1.f) || !(t.omega <= 4.f)) { set_error("tuning: omega outside [1, 4]"); return ST_E_INVALID; }
     if (!(t.lipschitz >= 0.f) || !std::isfinite(t.lipschitz)) { set_error("tuning: lipschitz < 0"); return ST_E_INVALID; }
     if (t.keep_all_entries != 0 && t.keep_all_entries != 1) { set_error("tuning: keep_all_entries must be 0 or 1"); return ST_E_INVALID; }

@@ -113,7 +113,7 @@ struct TraceArgs {
 };
 
 // step modes (template parameter of the tracer)
-enum { SM_PLAIN = 0, SM_OVER = 1, SM_LEARNED = 2, SM_DUMP = 3 };
+enum { SM_PLAIN = 0, SM_OVER = 1, SM_LEARNED = 2, SM_DUMP = 3, SM_SEGMENT = 4 };
 
 // active-set capacity of the LDS fast path (per wave)
 constexpr int kMaFast = 256;
@@ -214,6 +214,56 @@ __device__ __forceinline__ T eval_view(const uint32_t* view, int len_in, const N
             }
         }
     }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Segment tracing (Galin et al. 2020, which the paper names as the more robust
+// alternative to its empirical Lipschitz constant): the value of the pruned
+// view at p and a bound lam on |d f / d tau| over the segment
+// p + tau dir, tau in [0, seg] (seg per lane).  Bottom-up: a primitive is a
+// signed distance (lam 1); a sharp operator, or a compact one whose two
+// operands cannot both reach d_o on the segment (each operand stays within
+// its value +- lam seg there), is min / max over the segment (lam = max of
+// its operands'); otherwise the compact operator's Lipschitz factor
+// 1 + k/(6 d_o - k) multiplies the larger operand bound.  The value is the
+// one eval_view returns (same operations).  Called with every lane active.
+template <int KS>
+__device__ __forceinline__ float eval_view_seg(const uint32_t* view, int len_in, const NodePar* __restrict__ par,
+                                               uint32_t n_nodes, const P3<float>& p, float seg, float& lam_out,
+                                               uint32_t& sm) {
+    float stk[KS], stl[KS];
+    float acc = 0.f, lam = 1.f;
+    int sp = 0;
+    const int len = int(uni(uint32_t(len_in)));
+    for (int base = 0; base < len; base += 64) {
+        const uint32_t chunk = view[base + lane_id()];
+        const int cnt = int(uni(uint32_t(min(64, len - base))));
+        for (int jj = 0; jj < cnt; jj++) {
+            uint32_t e = rdlane(chunk, jj);
+            uint32_t kind = ventry_kind(e);
+            const cfloat* q = (const cfloat*)(par[min(ventry_node(e), n_nodes - 1u)].v);
+            // push as in eval_view (slot 0 is the dead bottom value)
+            if (kind <= ST_CAPSULE) {
+                stk[sp & (KS - 1)] = acc;
+                stl[sp & (KS - 1)] = lam;
+                sp++;
+                acc = prim_eval<float>(kind, q, p);
+                lam = 1.f;
+            } else {
+                sp--;
+                const float a = stk[sp & (KS - 1)], la = stl[sp & (KS - 1)];
+                float m = fmaxf(la, lam);
+                if (kind >= ST_SUNION) {
+                    const bool blend = a - la * seg <= q[3] && acc - lam * seg <= q[3];
+                    if (blend) m *= q[4];
+                }
+                acc = op_eval<float>(kind, q, a, acc, sm);
+                lam = m;
+            }
+        }
+    }
+    lam_out = lam;
     return acc;
 }
 
@@ -736,12 +786,15 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         uint32_t ev_here = 0;
         uint32_t mlp_it = 0;       // learned step: wave iterations since the last inference
         float om_last = 1.0f;      // learned step: this lane's last proposed factor
+        float seg = fmaxf(t1 - t, 0.f);   // segment tracing: candidate segment of the next step
         while (true) {
             bool act = mode == M_TRACE || mode == M_REFINE;
             if (ballot(act) == 0) break;
             P3<float> p{fmaf(t, ray.d[0], ray.o[0]), fmaf(t, ray.d[1], ray.o[1]), fmaf(t, ray.d[2], ray.o[2])};
             uint32_t sm_l = 0;
-            float v = eval_view<float, KS>(S.view(), len, A.par, A.n_nodes, p, sm_l);
+            float v, lam_seg = L;
+            if constexpr (SM == SM_SEGMENT) v = eval_view_seg<KS>(S.view(), len, A.par, A.n_nodes, p, seg, lam_seg, sm_l);
+            else v = eval_view<float, KS>(S.view(), len, A.par, A.n_nodes, p, sm_l);
             if (act) {
                 ev_here++;
                 smooth += sm_l;
@@ -749,7 +802,7 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
             // relaxed-step bookkeeping, in wave-uniform control flow
             bool chk = false, chk_ok = true, need = false;
             float om = A.omega;
-            if constexpr (SM != SM_PLAIN) {
+            if constexpr (SM != SM_PLAIN && SM != SM_SEGMENT) {
                 if constexpr (kRelax) {
                     chk = mode == M_TRACE && pend;
                     chk_ok = !chk || (v > 0.f && (vb + v) * invL >= t - tb);
@@ -815,7 +868,11 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                         if (!(t > ra && t < rb)) t = 0.5f * (ra + rb);
                     }
                 } else {
-                    const float safe_s = v * invL;
+                    // certified step: f/L of the view; with segment
+                    // tracing also f/lam over the candidate segment, at
+                    // most the segment itself (whichever is longer)
+                    float safe_s = v * invL;
+                    if constexpr (SM == SM_SEGMENT) safe_s = fmaxf(safe_s, fminf(v / lam_seg, seg));
                     float s = safe_s;
                     if (!(safe_s >= A.probe)) {
                         // probe.  While f falls: the secant estimate of the
@@ -860,6 +917,7 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                             relax_until = -__builtin_inff();
                         }
                     }
+                    if constexpr (SM == SM_SEGMENT) seg = fminf(2.f * s, t1 - tn);   // next candidate
                     if (tn >= t1 && !pend) {
                         t = t1;
                         mode = M_IDLE;

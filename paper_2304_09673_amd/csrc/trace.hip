@@ -149,7 +149,10 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
                        hipStream_t stream, const DumpTarget* dump, bool want_stats) {
     TraceArgs A;
     fill_trace_args(s, t, depth, normal, info, A);
-    int sm = t.step_mode == ST_STEP_OVERRELAX ? SM_OVER : t.step_mode == ST_STEP_LEARNED ? SM_LEARNED : SM_PLAIN;
+    int sm = t.step_mode == ST_STEP_OVERRELAX ? SM_OVER
+           : t.step_mode == ST_STEP_LEARNED   ? SM_LEARNED
+           : t.step_mode == ST_STEP_SEGMENT   ? SM_SEGMENT
+                                              : SM_PLAIN;
     if (sm == SM_LEARNED) {
         if (!s->has_model) { set_error("trace: learned step mode without a step model"); return ST_E_INVALID; }
         A.mlp = s->d_mlp;
@@ -205,6 +208,10 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
     case SM_LEARNED:
         e = shallow ? launch_trace<16, SM_LEARNED>(A, nwg, n_jobs, grid, slots, ma, stream)
                     : launch_trace<32, SM_LEARNED>(A, nwg, n_jobs, grid, slots, ma, stream);
+        break;
+    case SM_SEGMENT:
+        e = shallow ? launch_trace<16, SM_SEGMENT>(A, nwg, n_jobs, grid, slots, ma, stream)
+                    : launch_trace<32, SM_SEGMENT>(A, nwg, n_jobs, grid, slots, ma, stream);
         break;
     default:
         e = launch_trace<32, SM_DUMP>(A, nwg, n_jobs, grid, slots, ma, stream);

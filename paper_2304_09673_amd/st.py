@@ -15,7 +15,7 @@ _PKG = Path(__file__).resolve().parent
 LIB_PATH = _PKG / "libsynctrace.so"
 
 ST_OK, ST_E_INVALID, ST_E_TREE, ST_E_CAPACITY, ST_E_NOMEM, ST_E_DEVICE, ST_E_STALE = range(7)
-ST_STEP_PLAIN, ST_STEP_OVERRELAX, ST_STEP_LEARNED = 0, 1, 2
+ST_STEP_PLAIN, ST_STEP_OVERRELAX, ST_STEP_LEARNED, ST_STEP_SEGMENT = 0, 1, 2, 3
 
 # every symbol include/st.h declares
 EXPORTS = (
