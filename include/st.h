@@ -292,6 +292,29 @@ st_status st_trace_ex(st_scene *s, const st_camera *cam, float *out_depth, float
                       uint32_t *out_info, st_stats *out_stats, void *stream);
 
 /*
+ * st_trace_noalloc -- st_trace that allocates no device memory, for callers
+ * that cannot allocate (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same kernels and the same outputs as
+ * st_trace; the trace's scratch (one 192-byte counter record per 8x8 pixel
+ * block, and the wide path's per-workgroup slots when an overlap is too large
+ * for LDS) lives in a 32 MiB device array of the library, one copy per GPU,
+ * held until the process ends.
+ *   Arguments, layout and ownership as st_trace.  out_stats non-NULL makes
+ *   the call synchronize `stream` (the counters are summed into the scene's
+ *   own device words, allocated by st_flatten_blobtree).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on the same GPU (two streams, two threads) race and give undefined
+ * results; calls on one stream are ordered and safe.  The array needs no
+ * clearing: every block writes its whole record.
+ * Errors: ST_E_CAPACITY when the frame has more than 174,762 blocks of 8x8
+ * pixels (about 11 million pixels; the message gives the sizes), or no room
+ * is left for one wide-path slot; ST_E_STALE, ST_E_INVALID, ST_E_DEVICE as
+ * st_trace.  Nothing is launched on a capacity error.
+ */
+st_status st_trace_noalloc(st_scene *s, const st_camera *cam, float *out_depth, float *out_normal,
+                           st_stats *out_stats, void *stream);
+
+/*
  * st_autotune -- picks, for this scene and camera, the tuning with the
  * shortest A-buffer build + trace time among a grid of A-buffer tile sizes
  * {8, 16, 32}, fetch caps max_new {6, 16, 64, 256} (the paper's 6 first) and

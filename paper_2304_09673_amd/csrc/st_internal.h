@@ -120,9 +120,17 @@ struct DumpTarget {
     unsigned long long* n;     // samples produced (may exceed cap)
     unsigned long long cap;
 };
-// want_stats: sum the blocks' counter records into d_stats after the trace
+// caller-provided device scratch for the trace's counter records and
+// wide-path slots (instead of the scene's own, allocated on demand)
+struct TraceScratch {
+    void* base;      // device address, 256-byte aligned
+    size_t bytes;
+};
+// want_stats: sum the blocks' counter records into d_stats after the trace;
+// ext: use this scratch and allocate nothing (ST_E_CAPACITY if it is too small)
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
-                       hipStream_t stream, const DumpTarget* dump = nullptr, bool want_stats = false);
+                       hipStream_t stream, const DumpTarget* dump = nullptr, bool want_stats = false,
+                       const TraceScratch* ext = nullptr);
 st_status debug_eval_device(const st_scene* s, const uint32_t* active_post, int n_active,
                             const float* pts, int n_pts, float* out_f, float* out_grad,
                             int* root_used, hipStream_t stream);

@@ -1,6 +1,7 @@
 // Single-scene tracing kernels (fast LDS path, wide path) and their launch;
 // the per-block tracer is in st_trace.h.
 #include <algorithm>
+#include <string>
 
 #include "st_trace.h"
 
@@ -146,7 +147,7 @@ int wide_capacity(const st_scene* s) {
 }
 
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
-                       hipStream_t stream, const DumpTarget* dump, bool want_stats) {
+                       hipStream_t stream, const DumpTarget* dump, bool want_stats, const TraceScratch* ext) {
     TraceArgs A;
     fill_trace_args(s, t, depth, normal, info, A);
     int sm = t.step_mode == ST_STEP_OVERRELAX ? SM_OVER
@@ -164,38 +165,67 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
         A.dump_n = dump->n;
         A.dump_cap = dump->cap;
     }
-    hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(s->d_stats), 2u * kStatCount, 0u, stream);
-    if (e != hipSuccess) return device_error(e, "clear stats");
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     uint32_t n_jobs = uint32_t(s->n_tiles) * spt;
     uint32_t nwg = (n_jobs + 3) / 4;
-    // one counter record per block, every one written by its block
+    // one counter record per block, every one written by its block (so a
+    // caller's scratch needs no clearing)
     const size_t rec_bytes = size_t(n_jobs) * kWaveStats * 8u;
-    if (rec_bytes > s->wrec_bytes) {
-        dev_free(s, s->d_wrec, stream);
-        s->d_wrec = dev_alloc(s, rec_bytes, stream);
-        s->wrec_bytes = s->d_wrec ? rec_bytes : 0;
-        if (!s->d_wrec) { set_error("trace: counter record allocation failed"); return ST_E_NOMEM; }
+    if (ext) {
+        if (rec_bytes > ext->bytes) {
+            set_error("trace: the frame needs " + std::to_string(rec_bytes) + " bytes of counter records, above the " +
+                      std::to_string(ext->bytes) + "-byte scratch");
+            return ST_E_CAPACITY;
+        }
+        A.wrec = reinterpret_cast<unsigned long long*>(ext->base);
+    } else {
+        if (rec_bytes > s->wrec_bytes) {
+            dev_free(s, s->d_wrec, stream);
+            s->d_wrec = dev_alloc(s, rec_bytes, stream);
+            s->wrec_bytes = s->d_wrec ? rec_bytes : 0;
+            if (!s->d_wrec) { set_error("trace: counter record allocation failed"); return ST_E_NOMEM; }
+        }
+        A.wrec = reinterpret_cast<unsigned long long*>(s->d_wrec);
     }
-    A.wrec = reinterpret_cast<unsigned long long*>(s->d_wrec);
     // evaluation stack: at least the tree depth (views are never deeper)
     const bool shallow = s->depth <= 16;
     uint32_t grid = 0;
     int ma = 512;
+    uint32_t* slots = reinterpret_cast<uint32_t*>(s->d_slots);
     if (s->n_wide > 0) {
         ma = wide_capacity(s);
         uint32_t jobs = s->n_wide * spt;
         const bool in_lds = slot_words(ma) * 4u <= kSlotLdsBytes;
         grid = std::min<uint32_t>(jobs, in_lds ? 16384u : 3072u);
-        size_t need = in_lds ? 0 : size_t(grid) * slot_words(ma) * 4u;
-        if (need > s->slots_bytes) {
-            dev_free(s, s->d_slots, stream);
-            s->d_slots = dev_alloc(s, need, stream);
-            s->slots_bytes = s->d_slots ? need : 0;
-            if (!s->d_slots) { set_error("trace: wide-path slot allocation failed"); return ST_E_NOMEM; }
+        const size_t slot_bytes = slot_words(ma) * 4u;
+        if (in_lds) {
+            // slots in dynamic LDS
+        } else if (ext) {
+            // slots after the records; the wide kernel strides over its jobs,
+            // so fewer workgroups only take longer
+            const size_t off = (rec_bytes + 255u) / 256u * 256u;
+            const size_t fit = off < ext->bytes ? (ext->bytes - off) / slot_bytes : 0u;
+            if (fit == 0) {
+                set_error("trace: no room left in the " + std::to_string(ext->bytes) +
+                          "-byte scratch for one wide-path slot of " + std::to_string(slot_bytes) + " bytes");
+                return ST_E_CAPACITY;
+            }
+            grid = uint32_t(std::min<size_t>(grid, fit));
+            slots = reinterpret_cast<uint32_t*>(static_cast<char*>(ext->base) + off);
+        } else {
+            size_t need = size_t(grid) * slot_bytes;
+            if (need > s->slots_bytes) {
+                dev_free(s, s->d_slots, stream);
+                s->d_slots = dev_alloc(s, need, stream);
+                s->slots_bytes = s->d_slots ? need : 0;
+                if (!s->d_slots) { set_error("trace: wide-path slot allocation failed"); return ST_E_NOMEM; }
+            }
+            slots = reinterpret_cast<uint32_t*>(s->d_slots);
         }
     }
-    uint32_t* slots = reinterpret_cast<uint32_t*>(s->d_slots);
+    // every size is checked: launch from here on
+    hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(s->d_stats), 2u * kStatCount, 0u, stream);
+    if (e != hipSuccess) return device_error(e, "clear stats");
     switch (sm) {
     case SM_PLAIN:
         e = shallow ? launch_trace<16, SM_PLAIN>(A, nwg, n_jobs, grid, slots, ma, stream)

@@ -25,6 +25,7 @@ EXPORTS = (
     "st_debug_abuffer", "st_mlp_pack", "st_mlp_forward", "st_mlp_grad", "st_mlp_adam", "st_set_step_model",
     "st_trace_dump", "st_debug_mfma_probe", "st_batch_create", "st_batch_render", "st_batch_stats",
     "st_batch_destroy", "st_batch_autotune", "st_trace_batch", "st_update_primitives", "st_debug_kernel_timing",
+    "st_trace_noalloc",
 )
 
 MLP_PARAMS = 1377
@@ -109,6 +110,7 @@ def lib():
         L.st_build_abuffer.argtypes = [vp, C.POINTER(StCamera), C.POINTER(StTuning), vp]
         L.st_trace.argtypes = [vp, C.POINTER(StCamera), vp, vp, C.POINTER(StStats), vp]
         L.st_trace_ex.argtypes = [vp, C.POINTER(StCamera), vp, vp, vp, C.POINTER(StStats), vp]
+        L.st_trace_noalloc.argtypes = [vp, C.POINTER(StCamera), vp, vp, C.POINTER(StStats), vp]
         L.st_autotune.argtypes = [vp, C.POINTER(StCamera), C.POINTER(StTuning), i32, C.POINTER(StTuning), C.POINTER(C.c_float), vp]
         L.st_debug_eval_field.argtypes = [vp, vp, i32, vp, i32, vp, vp, C.POINTER(i32), vp, i32, C.POINTER(i32), vp]
         L.st_debug_prune_tree.argtypes = [C.POINTER(StNode), i32, i32, vp, i32, vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]
@@ -251,6 +253,17 @@ class Scene:
                                  C.c_void_p(info.data_ptr()) if info is not None else None,
                                  C.byref(st) if st is not None else None, _stream_ptr(stream)))
         return depth, normal, (st.as_dict() if st is not None else None)
+
+    def trace_noalloc(self, depth, normal, camera=None, stats: bool = True, stream=None):
+        """st_trace_noalloc into caller-allocated float32 CUDA tensors depth [H,W] and
+        normal [H,W,3]; returns the stats dict or None.  The library allocates nothing."""
+        cam = make_camera(camera) if camera is not None else self._cam
+        _f32_cuda(depth, cam.width * cam.height)
+        _f32_cuda(normal, 3 * cam.width * cam.height)
+        st = StStats() if stats else None
+        _check(lib().st_trace_noalloc(self._h, C.byref(cam), _ptr(depth), _ptr(normal),
+                                      C.byref(st) if st is not None else None, _stream_ptr(stream)))
+        return st.as_dict() if st is not None else None
 
     def debug_eval(self, pts, active=None, grad: bool = False, stream=None):
         """Pruned field f_A of the active primitives (caller node indices, None = all) at
