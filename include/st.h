@@ -314,6 +314,32 @@ st_status st_trace_ex(st_scene *s, const st_camera *cam, float *out_depth, float
 st_status st_trace_noalloc(st_scene *s, const st_camera *cam, float *out_depth, float *out_normal,
                            st_stats *out_stats, void *stream);
 
+/* Ancestor pointers of the ablation variants (Table 1 of the paper):
+ * Algorithm 1 climbing parent pointers, or fast ancestor pointers. */
+enum { ST_ABLATION_PARENT_PTR = 0, ST_ABLATION_FAST_PTR = 1 };
+
+/*
+ * st_trace_ablation -- the paper's ablation variants ParentPtr/Full and
+ * FastPtr/Full (Table 1; Section 11, analysis of the rendering times): the
+ * same images without synchronization.  A full-resolution dexel buffer is
+ * built from the scene's A-buffer (for every pixel, the primitives whose
+ * volume of interest its ray meets, with the ray's own entry and exit t,
+ * sorted by address), then every ray is traced on its own: in each interval
+ * of its list with a fixed active set it sphere-traces with the field
+ * evaluated at every step by the sparse bottom-up traversal of Algorithm 1
+ * (Section 7), climbing parent pointers (variant ST_ABLATION_PARENT_PTR) or
+ * fast ancestor pointers (ST_ABLATION_FAST_PTR).  Stepping, refinement and
+ * normals follow the A-buffer's tuning as in st_trace.
+ *   Outputs and their layout as st_trace.  The dexel buffer is owned by the
+ *   scene (grown on demand).  Synchronizes `stream` once to size it, and
+ *   again when out_stats is non-NULL (abuffer_entries then counts the
+ *   dexel entries, view_nodes the operators the traversals visited).
+ * Errors: ST_E_STALE (no A-buffer for this camera), ST_E_INVALID (NULL
+ * argument, unknown variant), ST_E_NOMEM, ST_E_DEVICE.
+ */
+st_status st_trace_ablation(st_scene *s, const st_camera *cam, int32_t variant, float *out_depth,
+                            float *out_normal, st_stats *out_stats, void *stream);
+
 /*
  * st_autotune -- picks, for this scene and camera, the tuning with the
  * shortest A-buffer build + trace time among a grid of A-buffer tile sizes
@@ -478,6 +504,28 @@ st_status st_debug_eval_field(const st_scene *s, const int32_t *active, int32_t 
 st_status st_debug_prune_tree(const st_node *nodes, int32_t n, int32_t root, const int32_t *active,
                               int32_t n_active, int32_t *out_nodes, int32_t cap, int32_t *out_len,
                               float *out_lip);
+
+/*
+ * st_debug_sparse_traversal -- test hook, host only (no device needed):
+ * flattens nodes[n] (same rules as st_flatten_blobtree) and runs the sparse
+ * bottom-up traversal of Algorithm 1 (Section 7: shadowing condition, stacked
+ * operands popped at operators with two active operands; with fast pointers
+ * the clamping to the stacked ancestor and the second pop condition) over the
+ * active primitives, with the ignoreMod rules of Section 9 at operators
+ * reached by one operand.  The same traversal code evaluates the field in
+ * st_trace_ablation; here it is evaluated symbolically.  Writes the resulting
+ * pruned expression in evaluation (post) order as caller node indices to
+ * out_nodes[cap] (length *out_len, 0 when the root is unused), its Lipschitz
+ * bound to *out_lip and the number of operators the traversal visited to
+ * *out_visited (both may be NULL).
+ *   variant: ST_ABLATION_PARENT_PTR or ST_ABLATION_FAST_PTR.
+ * Errors: those of st_flatten_blobtree, ST_E_INVALID (bad active index or
+ * variant), ST_E_CAPACITY (cap too small, or a traversal that did not end
+ * with one value).
+ */
+st_status st_debug_sparse_traversal(const st_node *nodes, int32_t n, int32_t root, const int32_t *active,
+                                    int32_t n_active, int32_t variant, int32_t *out_nodes, int32_t cap,
+                                    int32_t *out_len, float *out_lip, int32_t *out_visited);
 
 /*
  * st_debug_kernel_timing -- measurement hook: enable = 1 starts recording the

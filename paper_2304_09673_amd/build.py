@@ -13,7 +13,7 @@ OUT = PKG / "libsynctrace.so"
 BUILD = PKG / "_build"
 
 ARCH = os.environ.get("ST_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["api.hip", "binning.hip", "trace.hip", "batch.hip", "mlp.hip", "noalloc.hip", "flatten.cpp"]
+SOURCES = ["api.hip", "binning.hip", "trace.hip", "batch.hip", "mlp.hip", "noalloc.hip", "ablation.hip", "flatten.cpp"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions off (device code generation)

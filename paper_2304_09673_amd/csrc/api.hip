@@ -48,6 +48,10 @@ static void free_abuffer(st_scene* s, hipStream_t stream) {
     dev_free(s, s->d_slots, stream); s->d_slots = nullptr;
     s->slots_bytes = 0;
     dev_free(s, s->d_wrec, stream); s->d_wrec = nullptr;
+    dev_free(s, s->d_dx_meta, stream); s->d_dx_meta = nullptr;
+    s->dx_meta_bytes = 0;
+    dev_free(s, s->d_dx, stream); s->d_dx = nullptr;
+    s->dx_bytes = 0;
     s->wrec_bytes = 0;
     s->scratch_bytes = 0;
     s->ab_cap = 0;
@@ -201,6 +205,8 @@ st_status st_flatten_blobtree(const st_node* nodes, int32_t n, int32_t root, con
         {(void**)&s->d_prims, P * 4, s->h_prims.data()},
         {(void**)&s->d_sub, N * 32, s->h_sub.data()},
         {(void**)&s->d_oside, P * 32, s->h_oside.data()},
+        {(void**)&s->d_fast, N * 4, s->h_fast.data()},
+        {(void**)&s->d_pslot, N * 4, s->h_pslot.data()},
         {(void**)&s->d_par, N * sizeof(NodePar), s->h_par.data()},
         {(void**)&s->d_roi, N * 4, s->h_roi.data()},
         {(void**)&s->d_voi, P * sizeof(Voi), nullptr},
@@ -236,6 +242,8 @@ void st_scene_destroy(st_scene* s) {
     dev_free(s, s->d_prims, stream);
     dev_free(s, s->d_sub, stream);
     dev_free(s, s->d_oside, stream);
+    dev_free(s, s->d_fast, stream);
+    dev_free(s, s->d_pslot, stream);
     dev_free(s, s->d_par, stream);
     dev_free(s, s->d_roi, stream);
     dev_free(s, s->d_voi, stream);
@@ -496,6 +504,39 @@ st_status st_debug_prune_tree(const st_node* nodes, int32_t n, int32_t root, con
         }
     } catch (const std::bad_alloc&) {
         set_error("prune: host allocation failed");
+        return ST_E_NOMEM;
+    }
+    return ST_OK;
+}
+
+st_status st_debug_sparse_traversal(const st_node* nodes, int32_t n, int32_t root, const int32_t* active,
+                                    int32_t n_active, int32_t variant, int32_t* out_nodes, int32_t cap,
+                                    int32_t* out_len, float* out_lip, int32_t* out_visited) {
+    if (!out_len) { set_error("sparse: NULL out_len"); return ST_E_INVALID; }
+    if (variant != ST_ABLATION_PARENT_PTR && variant != ST_ABLATION_FAST_PTR) {
+        set_error("sparse: variant must be ST_ABLATION_PARENT_PTR or ST_ABLATION_FAST_PTR");
+        return ST_E_INVALID;
+    }
+    st_scene s;
+    try {
+        st_status r = flatten_host(nodes, n, root, &s);
+        if (r != ST_OK) return r;
+        std::vector<uint32_t> post, view;
+        r = active_to_post(&s, active, n_active, post);
+        if (r != ST_OK) return r;
+        float lip = 0.f;
+        uint32_t visited = 0;
+        r = host_sparse(&s, post, variant == ST_ABLATION_FAST_PTR, view, lip, visited);
+        if (r != ST_OK) return r;
+        *out_len = int32_t(view.size());
+        if (out_lip) *out_lip = lip;
+        if (out_visited) *out_visited = int32_t(visited);
+        if (!view.empty()) {
+            if (!out_nodes || cap < int32_t(view.size())) { set_error("sparse: output capacity too small"); return ST_E_CAPACITY; }
+            for (size_t i = 0; i < view.size(); i++) out_nodes[i] = s.caller_of_post[view[i]];
+        }
+    } catch (const std::bad_alloc&) {
+        set_error("sparse: host allocation failed");
         return ST_E_NOMEM;
     }
     return ST_OK;

@@ -18,6 +18,7 @@
 #include <cstring>
 
 #include "st_internal.h"
+#include "st_sparse.h"
 
 namespace st {
 
@@ -283,6 +284,9 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
         }
         s->h_roi[p] = float(roi[p]);
     }
+    // fast ancestor pointers (Algorithm 1's long jumps; the ablation tracer)
+    s->h_fast.assign(n, kNoNode);
+    for (int p = 0; p < n; p++) s->h_fast[p] = fast_ancestor(s->h_blob.data(), uint32_t(p));
     // chain rows: a node's first kKillLevels killing ancestors, nearest first
     // (following the kill pointers from node to node visits every killing
     // ancestor on the path to the root), padded with kNoKill, then their count
@@ -324,6 +328,8 @@ st_status flatten_host(const st_node* nodes, int32_t n, int32_t root, st_scene* 
         }
     }
     s->n_prims = nprim;
+    s->h_pslot.assign(n, 0xFFFFFFFFu);
+    for (int i = 0; i < nprim; i++) s->h_pslot[s->h_prims[size_t(i)]] = uint32_t(i);
     s->lipschitz = float(Lmax);
     scene_bounds(s);
     subtree_boxes(s);
@@ -396,6 +402,77 @@ PruneResult host_prune(const st_scene* s, std::vector<uint32_t> act, std::vector
     r = prune_pass(c, int(vs.size()));
     view.resize(size_t(r.len));
     return r;
+}
+
+namespace {
+
+// Symbolic evaluation of the sparse traversal: a value is a pruned
+// expression (post-order node list and its Lipschitz bound) or "unused".
+struct SymEval {
+    typedef int V;   // index into pool, -1: unused
+    const st_scene* s;
+    std::vector<std::vector<uint32_t>> pool;
+    std::vector<float> lip;
+    int make(std::vector<uint32_t> e, float L) {
+        pool.push_back(std::move(e));
+        lip.push_back(L);
+        return int(pool.size()) - 1;
+    }
+    V none() { return -1; }
+    V prim(uint32_t node) { return make({node}, 1.f); }
+    V single(uint32_t op, V v, bool from_left) {
+        if (v < 0) return -1;
+        return single_passes(s->h_blob[op], from_left) ? v : -1;
+    }
+    V op(uint32_t op, V a, V b) {
+        if (a < 0) return single(op, b, false);
+        if (b < 0) return single(op, a, true);
+        std::vector<uint32_t> e = pool[size_t(a)];
+        e.insert(e.end(), pool[size_t(b)].begin(), pool[size_t(b)].end());
+        e.push_back(op);
+        return make(std::move(e), s->h_par[op].v[4] * std::max(lip[size_t(a)], lip[size_t(b)]));
+    }
+};
+
+struct HostTree {
+    const st_scene* s;
+    bool fast;
+    uint32_t blob(uint32_t n) const { return s->h_blob[n]; }
+    uint32_t anc(uint32_t n) const { return fast ? s->h_fast[n] : blob_anc(s->h_blob[n]); }
+};
+
+struct HostAct {
+    const std::vector<uint32_t>* a;
+    size_t i = 0;
+    bool next(uint32_t& n) {
+        if (i >= a->size()) return false;
+        n = (*a)[i++];
+        return true;
+    }
+};
+
+}  // namespace
+
+st_status host_sparse(const st_scene* s, std::vector<uint32_t> act, bool fast, std::vector<uint32_t>& view,
+                      float& lip, uint32_t& visited) {
+    std::sort(act.begin(), act.end());
+    SymEval ev;
+    ev.s = s;
+    HostTree tr{s, fast};
+    HostAct ac;
+    ac.a = &act;
+    bool overflow = false;
+    visited = 0;
+    int r = fast ? sparse_traverse<true, kStack>(tr, ac, ev, visited, overflow)
+                 : sparse_traverse<false, kStack>(tr, ac, ev, visited, overflow);
+    if (overflow) { set_error("sparse traversal: stack overflow or unfinished traversal"); return ST_E_CAPACITY; }
+    view.clear();
+    lip = 0.f;
+    if (r >= 0) {
+        view = ev.pool[size_t(r)];
+        lip = ev.lip[size_t(r)];
+    }
+    return ST_OK;
 }
 
 }  // namespace st

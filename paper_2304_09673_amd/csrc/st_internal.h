@@ -31,6 +31,9 @@ struct st_scene {
     // kKillLevels killing ancestors, the child on the other side (kNoKill
     // padding), then 0
     std::vector<uint32_t> h_oside;
+    // per node: fast ancestor pointer (kNoNode above the root), and for
+    // primitives their index in h_prims (0xFFFFFFFF for operators)
+    std::vector<uint32_t> h_fast, h_pslot;
     float extent = 0.f, lipschitz = 1.f;
     float voi_lo[3] = {0, 0, 0}, voi_hi[3] = {0, 0, 0};
 
@@ -42,6 +45,8 @@ struct st_scene {
     uint32_t* d_prims = nullptr;     // post-order index of each primitive
     float* d_sub = nullptr;          // h_sub
     uint32_t* d_oside = nullptr;     // h_oside
+    uint32_t* d_fast = nullptr;      // h_fast
+    uint32_t* d_pslot = nullptr;     // h_pslot
     st::NodePar* d_par = nullptr;
     float* d_roi = nullptr;
     st::Voi* d_voi = nullptr;
@@ -69,6 +74,14 @@ struct st_scene {
     uint64_t ab_gen = 0;        // bumped by every st_build_abuffer
     uint32_t max_list = 0, max_overlap = 0, n_wide = 0;
     int32_t ab_ma_fast = 0, ab_ma_wide = 0;
+
+    // dexel buffer of the ablation tracer: per-pixel CSR offsets, counts and
+    // scan scratch (meta), then node, t_in and t_out of every entry (dx)
+    void* d_dx_meta = nullptr;
+    size_t dx_meta_bytes = 0;
+    void* d_dx = nullptr;
+    size_t dx_bytes = 0;
+    uint32_t n_dexels = 0;
 
     // wide-path per-workgroup slots (trace)
     void* d_slots = nullptr;
@@ -111,6 +124,10 @@ void dev_free(st_scene* s, void* p, hipStream_t stream);
 st_status launch_voi(st_scene* s, hipStream_t stream);
 st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stream, bool replay = false);
 hipError_t fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t stream);
+// out[0..n) = exclusive prefix sum of in[0..n), *total = the sum (and
+// *out_total_slot when non-NULL); scratch holds >= ceil(n/1024)+1 words
+void exclusive_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* scratch, uint32_t* total,
+                    uint32_t* out_total_slot, hipStream_t stream);
 
 // trace.hip
 // training-sample output of the dump mode (device pointers)
@@ -131,6 +148,9 @@ struct TraceScratch {
 st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* normal, uint32_t* info,
                        hipStream_t stream, const DumpTarget* dump = nullptr, bool want_stats = false,
                        const TraceScratch* ext = nullptr);
+// sums n_jobs per-block counter records into stats[0..S_COUNT)
+hipError_t launch_reduce_counters(const unsigned long long* wrec, uint32_t n_jobs, unsigned long long* stats,
+                                  hipStream_t stream);
 st_status debug_eval_device(const st_scene* s, const uint32_t* active_post, int n_active,
                             const float* pts, int n_pts, float* out_f, float* out_grad,
                             int* root_used, hipStream_t stream);
@@ -145,6 +165,11 @@ void subtree_boxes(st_scene* s);
 void scene_bounds(st_scene* s);
 PruneResult host_prune(const st_scene* s, std::vector<uint32_t> active_post,
                        std::vector<uint32_t>& view);
+// Algorithm 1 with parent (fast = false) or fast ancestor pointers, evaluated
+// symbolically: the pruned expression in post-order (empty: root unused), its
+// Lipschitz bound and the operators visited
+st_status host_sparse(const st_scene* s, std::vector<uint32_t> active_post, bool fast, std::vector<uint32_t>& view,
+                      float& lip, uint32_t& visited);
 
 constexpr int kStatCount = 48;
 

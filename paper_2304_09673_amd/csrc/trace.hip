@@ -79,6 +79,12 @@ __global__ void __launch_bounds__(256) reduce_counters_kernel(const unsigned lon
 }
 
 
+hipError_t launch_reduce_counters(const unsigned long long* wrec, uint32_t n_jobs, unsigned long long* stats,
+                                  hipStream_t stream) {
+    hipLaunchKernelGGL(reduce_counters_kernel, dim3(S_COUNT), dim3(256), 0, stream, wrec, n_jobs, stats);
+    return hipGetLastError();
+}
+
 template <int KS, int SM>
 static hipError_t launch_trace(const TraceArgs& A, uint32_t nwg, uint32_t n_jobs, uint32_t wide_grid,
                                uint32_t* slots, int ma, hipStream_t stream) {

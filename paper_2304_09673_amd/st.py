@@ -16,6 +16,7 @@ LIB_PATH = _PKG / "libsynctrace.so"
 
 ST_OK, ST_E_INVALID, ST_E_TREE, ST_E_CAPACITY, ST_E_NOMEM, ST_E_DEVICE, ST_E_STALE = range(7)
 ST_STEP_PLAIN, ST_STEP_OVERRELAX, ST_STEP_LEARNED, ST_STEP_SEGMENT = 0, 1, 2, 3
+ST_ABLATION_PARENT_PTR, ST_ABLATION_FAST_PTR = 0, 1
 
 # every symbol include/st.h declares
 EXPORTS = (
@@ -25,7 +26,7 @@ EXPORTS = (
     "st_debug_abuffer", "st_mlp_pack", "st_mlp_forward", "st_mlp_grad", "st_mlp_adam", "st_set_step_model",
     "st_trace_dump", "st_debug_mfma_probe", "st_batch_create", "st_batch_render", "st_batch_stats",
     "st_batch_destroy", "st_batch_autotune", "st_trace_batch", "st_update_primitives", "st_debug_kernel_timing",
-    "st_trace_noalloc",
+    "st_trace_noalloc", "st_debug_sparse_traversal", "st_trace_ablation",
 )
 
 MLP_PARAMS = 1377
@@ -111,9 +112,12 @@ def lib():
         L.st_trace.argtypes = [vp, C.POINTER(StCamera), vp, vp, C.POINTER(StStats), vp]
         L.st_trace_ex.argtypes = [vp, C.POINTER(StCamera), vp, vp, vp, C.POINTER(StStats), vp]
         L.st_trace_noalloc.argtypes = [vp, C.POINTER(StCamera), vp, vp, C.POINTER(StStats), vp]
+        L.st_trace_ablation.argtypes = [vp, C.POINTER(StCamera), i32, vp, vp, C.POINTER(StStats), vp]
         L.st_autotune.argtypes = [vp, C.POINTER(StCamera), C.POINTER(StTuning), i32, C.POINTER(StTuning), C.POINTER(C.c_float), vp]
         L.st_debug_eval_field.argtypes = [vp, vp, i32, vp, i32, vp, vp, C.POINTER(i32), vp, i32, C.POINTER(i32), vp]
         L.st_debug_prune_tree.argtypes = [C.POINTER(StNode), i32, i32, vp, i32, vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]
+        L.st_debug_sparse_traversal.argtypes = [C.POINTER(StNode), i32, i32, vp, i32, i32, vp, i32, C.POINTER(i32),
+                                                C.POINTER(C.c_float), C.POINTER(i32)]
         L.st_debug_abuffer.argtypes = [vp, vp, sz, vp, sz, C.POINTER(i32), C.POINTER(i64), vp]
         L.st_mlp_pack.argtypes = [vp, vp, vp, vp]
         L.st_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
@@ -264,6 +268,23 @@ class Scene:
         _check(lib().st_trace_noalloc(self._h, C.byref(cam), _ptr(depth), _ptr(normal),
                                       C.byref(st) if st is not None else None, _stream_ptr(stream)))
         return st.as_dict() if st is not None else None
+
+    def trace_ablation(self, variant, camera=None, depth=None, normal=None, stats: bool = True, stream=None):
+        """st_trace_ablation (per-pixel dexel buffer, unsynchronized rays, Algorithm 1 field
+        evaluation with parent or fast ancestor pointers).  Returns (depth, normal, stats or None)."""
+        import torch
+        cam = make_camera(camera) if camera is not None else self._cam
+        W, H = cam.width, cam.height
+        if depth is None:
+            depth = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        if normal is None:
+            normal = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        _f32_cuda(depth, H * W)
+        _f32_cuda(normal, 3 * H * W)
+        st = StStats() if stats else None
+        _check(lib().st_trace_ablation(self._h, C.byref(cam), int(variant), _ptr(depth), _ptr(normal),
+                                       C.byref(st) if st is not None else None, _stream_ptr(stream)))
+        return depth, normal, (st.as_dict() if st is not None else None)
 
     def debug_eval(self, pts, active=None, grad: bool = False, stream=None):
         """Pruned field f_A of the active primitives (caller node indices, None = all) at
@@ -471,3 +492,21 @@ def prune_tree(kind, left, right, params, root, active):
     _check(lib().st_debug_prune_tree(nodes, n, int(root), a.ctypes.data_as(C.c_void_p) if active is not None else None,
                                      a.shape[0], out.ctypes.data_as(C.c_void_p), cap, C.byref(ln), C.byref(lip)))
     return out[: ln.value].copy(), float(lip.value)
+
+
+def sparse_traversal(kind, left, right, params, root, active, variant):
+    """Host-only Algorithm 1 traversal (st_debug_sparse_traversal): (pruned expression as caller
+    indices in evaluation order, Lipschitz, operators visited)."""
+    nodes = nodes_from_arrays(kind, left, right, params)
+    n = len(nodes)
+    a = np.ascontiguousarray(active if active is not None else [], dtype=np.int32)
+    cap = 2 * n + 2
+    out = np.zeros(cap, dtype=np.int32)
+    ln = C.c_int32(0)
+    lip = C.c_float(0)
+    vis = C.c_int32(0)
+    _check(lib().st_debug_sparse_traversal(nodes, n, int(root),
+                                           a.ctypes.data_as(C.c_void_p) if active is not None else None,
+                                           a.shape[0], int(variant), out.ctypes.data_as(C.c_void_p), cap,
+                                           C.byref(ln), C.byref(lip), C.byref(vis)))
+    return out[: ln.value].copy(), float(lip.value), int(vis.value)

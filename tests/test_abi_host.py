@@ -214,6 +214,77 @@ def test_prune_random_larger_trees(seed):
             assert lip == pytest.approx(elip, rel=1e-6)
 
 
+# ---------------------------------------------------------------------------
+# Algorithm 1 (sparse bottom-up traversal with direct evaluation), parent and
+# fast ancestor pointers: the expression it evaluates must be the pruned view
+# of the rules above, for every shape, operator mix and active subset.
+
+def _sparse(sc, active, variant):
+    from paper_2304_09673_amd import st
+    return st.sparse_traversal(sc.kind, sc.left, sc.right, sc.params, sc.root, active, variant)
+
+
+@pytest.mark.parametrize("n_leaves", [1, 2, 3, 4, 5, 6])
+def test_sparse_traversal_exhaustive_small_trees(n_leaves):
+    from paper_2304_09673_amd import st
+    rng = np.random.default_rng(50 + n_leaves)
+    cases = 0
+    for shape in _shapes(n_leaves):
+        n_ops = n_leaves - 1
+        assigns = [[op] * n_ops for op in OPS] if n_ops else [[]]
+        assigns += [list(rng.choice(OPS, n_ops)) for _ in range(4)] if n_ops else []
+        for ops in assigns:
+            sc = sg.tree_from_shape(shape, ops, seed=cases, k=float(rng.uniform(0.05, 0.3)))
+            prims = np.nonzero(sc.kind < 16)[0]
+            for mask in range(1 << n_leaves):
+                active = [int(prims[i]) for i in range(n_leaves) if mask >> i & 1]
+                exp, elip = _expected(sc, active)
+                vis = {}
+                for variant in (st.ST_ABLATION_PARENT_PTR, st.ST_ABLATION_FAST_PTR):
+                    got, lip, vis[variant] = _sparse(sc, active, variant)
+                    assert list(got) == exp, (shape, ops, active, variant)
+                    assert lip == pytest.approx(elip, rel=1e-6)
+                assert vis[st.ST_ABLATION_FAST_PTR] <= vis[st.ST_ABLATION_PARENT_PTR]
+                cases += 1
+    assert cases > 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sparse_traversal_random_larger_trees(seed):
+    """Random trees of 7 to 60 leaves (deep and lopsided shapes), random
+    active subsets: both pointer variants give the pruned view."""
+    from paper_2304_09673_amd import st
+    rng = np.random.default_rng(300 + seed)
+    for rep in range(40):
+        n = int(rng.integers(7, 60))
+        sc = sg.random_small_tree(seed * 1000 + rep, n, ops=tuple(OPS))
+        prims = np.nonzero(sc.kind < 16)[0]
+        for _ in range(10):
+            active = [int(p) for p in prims if rng.random() < rng.uniform(0.05, 0.9)]
+            exp, elip = _expected(sc, active)
+            for variant in (st.ST_ABLATION_PARENT_PTR, st.ST_ABLATION_FAST_PTR):
+                got, lip, _ = _sparse(sc, active, variant)
+                assert list(got) == exp, (seed, rep, variant)
+                assert lip == pytest.approx(elip, rel=1e-6)
+
+
+def test_fast_pointers_skip_the_spine_of_a_left_comb():
+    """A left comb of unions with only its deepest primitive active: parent
+    pointers visit every spine operator, fast pointers jump to the root at
+    once (the left-heavy case the paper introduces them for)."""
+    from paper_2304_09673_amd import st
+    n_leaves = 12
+    shape = 0
+    for _ in range(n_leaves - 1):
+        shape = (shape, 0)
+    sc = sg.tree_from_shape(shape, [sg.SUNION] * (n_leaves - 1))
+    prims = np.nonzero(sc.kind < 16)[0]
+    deepest = int(min(prims))
+    for variant, want in ((st.ST_ABLATION_PARENT_PTR, n_leaves - 1), (st.ST_ABLATION_FAST_PTR, 1)):
+        got, _, vis = _sparse(sc, [deepest], variant)
+        assert list(got) == [deepest] and vis == want, (variant, vis)
+
+
 def _kill_filter(sc, active):
     """The dead-primitive rule of the device view build, written on the tree:
     a primitive is dropped when some ancestor on its path discards a lone

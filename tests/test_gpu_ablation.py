@@ -1,0 +1,85 @@
+"""Ablation variants of the paper's Table 1 (st_trace_ablation): per-pixel
+dexel buffer, every ray traced on its own with the field evaluated by
+Algorithm 1 over parent or fast ancestor pointers.  They must meet the same
+parity rules against the FP64 oracle as the synchronized tracer and give its
+hit masks; the fast pointers visit fewer operators than the parent pointers."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from gpu_util import all_pixels, compare, stratified_pixels
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {"parent": 0, "fast": 1}
+
+
+def _report(name, r):
+    print(f"\n[{name}] " + " ".join(f"{k}={v}" for k, v in r.items() if k != "fail_idx"), flush=True)
+
+
+def _render_all(sc, **kw):
+    import torch
+    from paper_2304_09673_amd import st
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera, st.default_tuning(**kw))
+    d, n, stats = s.trace()
+    out = {"sync": (d.cpu().numpy(), n.cpu().numpy(), stats)}
+    for name, v in VARIANTS.items():
+        d, n, stats = s.trace_ablation(v)
+        torch.cuda.synchronize()
+        out[name] = (d.cpu().numpy(), n.cpu().numpy(), stats)
+        print(f"[{sc.name} {name}] dexels {stats['abuffer_entries']} evals {stats['field_evals']} "
+              f"visited operators {stats['view_nodes']} unconverged {stats['unconverged']}", flush=True)
+    return out
+
+
+@pytest.mark.parametrize("which,kw", [("c1", {"max_steps": 128}), ("c2", {"tile": 8, "keep_all_entries": 1}),
+                                      ("c2", {"tile": 16})], ids=["c1", "c2-t8-all", "c2-t16"])
+def test_ablation_full_image_parity(which, kw):
+    sc = sg.config1(0) if which == "c1" else sg.config2(0, 256, 256)
+    out = _render_all(sc, **kw)
+    px, py = all_pixels(sc.camera)
+    for name in VARIANTS:
+        d, n, stats = out[name]
+        r = compare(sc, d, n, px, py)
+        _report(f"{which} {name}", r)
+        assert stats["stalled"] == 0 and stats["unconverged"] == 0, stats
+        assert stats["rays"] == sc.camera.width * sc.camera.height
+        assert r["hits_oracle"] > 1000 and r["fail"] == 0, r
+        np.testing.assert_array_equal(np.isfinite(d), np.isfinite(out["sync"][0]))
+    assert out["fast"][2]["view_nodes"] < out["parent"][2]["view_nodes"]
+    # same traversal values: the two variants evaluate the same expressions
+    np.testing.assert_array_equal(out["fast"][0], out["parent"][0])
+
+
+@pytest.mark.timeout(600)
+def test_ablation_c3_stratified():
+    """4096 primitives at 1920x1080 (fast pointers): every GPU hit plus a
+    seeded 8,192-pixel subset against the oracle."""
+    sc = sg.config3(0)
+    out = _render_all(sc, tile=8, keep_all_entries=1)
+    d, n, stats = out["fast"]
+    px, py = stratified_pixels(sc.camera, [d], 8192, 9, ring=False)
+    r = compare(sc, d, n, px, py)
+    _report("c3 fast", r)
+    assert stats["stalled"] == 0 and stats["unconverged"] == 0
+    assert r["hits_compared"] >= 2000 and r["fail"] == 0, r
+    np.testing.assert_array_equal(np.isfinite(out["parent"][0]), np.isfinite(out["sync"][0]))
+
+
+def test_ablation_rejects_bad_input():
+    import torch
+    from paper_2304_09673_amd import st
+    sc = sg.config1(0, 64, 64)
+    s = st.Scene(sc)
+    with pytest.raises(st.StError) as e:
+        s.trace_ablation(0, camera=sc.camera)
+    assert e.value.code == st.ST_E_STALE
+    s.build_abuffer(sc.camera)
+    with pytest.raises(st.StError) as e:
+        s.trace_ablation(7)
+    assert e.value.code == st.ST_E_INVALID
+    torch.cuda.synchronize()
