@@ -125,13 +125,16 @@ typedef struct {
                               pixel-centre ray of the tile meets */
     float probe_step;      /* where the safe step f/L falls below this (scene
                               units; values below eps act as eps) the ray
-                              probes forward instead: by the secant estimate
-                              of the distance to the root (at least eps, at
-                              most 4x the last probe) while f falls, by twice
-                              the last probe while f rises, never by less
-                              than f/L; a sign change is refined by regula
-                              falsi.  The paper steps by max(f/L, minimum
-                              step) (Section 10, Ray processing); default 1e-3 */
+                              probes forward instead: by 3/4 of the secant
+                              estimate of the distance to the root while f
+                              falls, by twice the last probe while f rises;
+                              at least eps, at most 4x the last probe and
+                              8x probe_step, never less than f/L; a sign
+                              change is refined by regula falsi.  A stretch
+                              of negative field at least 8x probe_step long
+                              is never stepped over.  The paper steps by
+                              max(f/L, minimum step) (Section 10, Ray
+                              processing); default 1e-3 */
     int32_t reserved[4];
 } st_tuning;
 

@@ -89,7 +89,7 @@ struct AblArgs {
     const uint32_t* d_node;
     const float* d_tin;
     const float* d_tout;
-    float eps, probe, lip_fixed;
+    float eps, probe, probe_cap, lip_fixed;
     int max_steps, refine_iters;
     float* out_depth;
     float* out_normal;
@@ -244,13 +244,8 @@ __global__ void __launch_bounds__(64) ablation_trace_kernel(AblArgs A) {
                     const float safe_s = v == __builtin_inff() ? te - t : v / L;
                     float s = safe_s;
                     if (!(safe_s >= A.probe)) {
-                        const bool falling = tp_ok && vp > v;
-                        const float hb = fmaxf(hp, A.eps);
-                        float pr;
-                        if (falling) pr = fminf(fmaxf(v * (t - tp) / (vp - v), A.eps), 4.f * hb);
-                        else pr = tp_ok ? 2.f * hb : A.eps;
-                        s = fmaxf(pr, safe_s);
-                        hp = s;
+                        s = probe_len(v, t, tp, vp, tp_ok, hp, A.eps, A.probe_cap, safe_s);
+                        hp = fminf(s, te - t);   // the step taken (clamped at te below)
                     } else {
                         hp = 0.f;
                     }
@@ -419,6 +414,7 @@ extern "C" st_status st_trace_ablation(st_scene* s, const st_camera* cam, int32_
     A.d_tout = A.d_tin + cap;
     A.eps = t.eps;
     A.probe = std::max(t.probe_step, t.eps);
+    A.probe_cap = kProbeCapFactor * A.probe;
     A.lip_fixed = t.lipschitz;
     A.max_steps = t.max_steps;
     A.refine_iters = t.refine_iters;

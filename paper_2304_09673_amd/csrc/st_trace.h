@@ -24,9 +24,10 @@
 // sign-equivalent to the full field inside the subfrustum.
 //
 // Stepping: the safe step is f/L with L the proven Lipschitz bound of the
-// view.  Once the safe step falls below eps the ray probes forward by the
-// secant estimate of the distance to the root (at least eps, growing at most
-// 4x per probe); a sign change is bracketed and refined by regula falsi
+// view.  Once the safe step falls below the probe threshold the ray probes
+// forward (probe_len below; never longer than kProbeCapFactor times the
+// threshold, so a stretch of negative field at least that long is never
+// stepped over); a sign change is bracketed and refined by regula falsi
 // (Illinois), and the normal is the normalised forward-mode gradient of the
 // view at the root.
 //
@@ -49,6 +50,29 @@
 #include "st_mlp.h"
 
 namespace st {
+
+// ---------------------------------------------------------------------------
+// probing near a surface (where the certified step f/L is shorter than the
+// probe threshold).  While f falls: three quarters of the secant estimate of
+// the distance to the root through the last point (tp, vp) -- where f bends
+// down faster than the secant (a concave approach, e.g. where the minimum
+// switches to a nearer primitive) the full estimate overshoots the root, and
+// a shallow dip behind it can be stepped over whole; while f rises (the ray
+// leaves a surface it grazed): twice the last probe.  Growth is at most 4x
+// the last probe (hp: the step actually taken, after clamping at the
+// subfrustum end), at least eps, at most kProbeCapFactor x the threshold,
+// never below the certified step.
+constexpr float kProbeCapFactor = 8.0f;
+
+__device__ __forceinline__ float probe_len(float v, float t, float tp, float vp, bool tp_ok, float hp, float eps,
+                                           float cap, float safe_s) {
+    const bool falling = tp_ok && vp > v;
+    const float hb = fmaxf(hp, eps);
+    float pr;
+    if (falling) pr = fminf(fmaxf(0.75f * v * (t - tp) / (vp - v), eps), 4.f * hb);
+    else pr = tp_ok ? 2.f * hb : eps;
+    return fmaxf(fminf(pr, cap), safe_s);
+}
 
 // ---------------------------------------------------------------------------
 // wave helpers
@@ -97,7 +121,7 @@ struct TraceArgs {
     DevCam cam;
     int ts, tiles_x, tiles_y, sub_x;   // sub_x = ts / 8
     uint32_t ma_fast;
-    float eps, probe, d_sub, lip_fixed, omega;   // probe >= eps: safe steps below it probe
+    float eps, probe, probe_cap, d_sub, lip_fixed, omega;   // probe >= eps: safe steps below it probe
     int max_steps, refine_iters, max_new, step_mode;
     float* out_depth;
     float* out_normal;
@@ -875,21 +899,8 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
                     if constexpr (SM == SM_SEGMENT) safe_s = fmaxf(safe_s, fminf(v / lam_seg, seg));
                     float s = safe_s;
                     if (!(safe_s >= A.probe)) {
-                        // probe.  While f falls: the secant estimate of the
-                        // distance to the root (it under-estimates the entry
-                        // of a convex dip, so a thin sliver is not jumped),
-                        // at least eps, at most 4x the previous probe.  While
-                        // f rises the ray moves away from the surface it
-                        // grazed: twice the previous probe, until the safe
-                        // step exceeds the probe threshold again.  Never
-                        // shorter than the safe step.
-                        const bool falling = tp_ok && vp > v;
-                        const float hb = fmaxf(hp, A.eps);
-                        float pr;
-                        if (falling) pr = fminf(fmaxf(v * (t - tp) / (vp - v), A.eps), 4.f * hb);
-                        else pr = tp_ok ? 2.f * hb : A.eps;
-                        s = fmaxf(pr, safe_s);
-                        hp = s;
+                        s = probe_len(v, t, tp, vp, tp_ok, hp, A.eps, A.probe_cap, safe_s);
+                        hp = fminf(s, t1 - t);   // the step taken (clamped at t1 below)
                     } else {
                         hp = 0.f;
                     }

@@ -132,6 +132,7 @@ void fill_trace_args(const st_scene* s, const st_tuning& t, float* depth, float*
     A.ma_fast = uint32_t(s->ab_ma_fast);
     A.eps = t.eps;
     A.probe = std::max(t.probe_step, t.eps);
+    A.probe_cap = kProbeCapFactor * A.probe;
     A.d_sub = t.sub_depth * (s->z_max - s->z_min);
     A.lip_fixed = t.lipschitz;
     A.omega = t.omega;
