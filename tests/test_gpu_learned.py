@@ -4,6 +4,8 @@ rules (the sphere-overlap test keeps every accepted step conservative), and
 the learned one is compared with the plain one at equal depth error."""
 from __future__ import annotations
 
+from pathlib import Path
+
 import numpy as np
 import pytest
 
@@ -191,17 +193,27 @@ def test_learned_vs_plain_on_large_scene(model):
               f"rejected {stats['learned_rejected']}")
 
 
+GOLDEN_C5 = Path(__file__).resolve().parent / "golden" / "c5_oracle_sample.npz"
+
+
 @pytest.mark.timeout(900)
 def test_full_size_large_scene_sampled(model):
     """The full 3840x2160 frame of 16384 primitives in the launch
     configuration of the comparison (the autotuner's choice for the plain
-    step): at least 2,000 hit rays (seeded from the hit pixels of both
-    tracers) plus 2,048 random pixels against the oracle.  Both pass parity;
-    the learned tracer's p99 and maximum depth error equal the plain one's;
-    every pixel whose hit/miss differs between them is exempt (within 1e-4 of
-    a silhouette)."""
+    step), against the oracle at the stored pixels of
+    ``golden/c5_oracle_sample.npz`` (uniform pixels plus windows around the
+    projected centres of seeded primitives, chosen and traced by the oracle
+    alone: at least 2,000 hits) and, traced now, a seeded subset of the pixels
+    the GPU hits outside that set and every pixel whose hit/miss differs
+    between the two tracers.  Both tracers pass parity; the learned tracer's
+    p99 and maximum depth error equal the plain one's."""
+    import sys
+    sys.path.insert(0, str(GOLDEN_C5.parent))
+    from make_c5_oracle import scene_digest
     st = _st()
     sc = sg.config5()
+    g = np.load(GOLDEN_C5)
+    assert str(g["digest"]) == scene_digest(sc), "stored oracle values are for another scene: rerun make_c5_oracle.py"
     s = st.Scene(sc)
     tuned, _ = s.autotune(sc.camera, reps=1)
     s.close()
@@ -211,12 +223,25 @@ def test_full_size_large_scene_sampled(model):
     d_l, n_l, s_l = _render(sc, st.ST_STEP_LEARNED, model=model, tuning_kw=kw)
     assert s_p["unconverged"] == 0 and s_l["unconverged"] == 0
     assert s_p["stalled"] == 0 and s_l["stalled"] == 0
-    mi, mj = _mask_differences(d_p, d_l)
-    px, py = stratified_pixels(sc.camera, [d_p, d_l], 2048, 12, ring=False, max_hits=2600)
-    px, py = np.concatenate([px, mi]), np.concatenate([py, mj])
-    print(f"[c5] {px.shape[0]} pixels, {mi.shape[0]} hit/miss differences between the tracers", flush=True)
+    W = sc.camera.width
     osc = oracle.OracleScene(sc)
-    ref = oracle_ref(osc, sc.camera, px, py)
+    assert osc.extent == float(g["extent"])
+    gp, gq = g["px"].astype(np.int64), g["py"].astype(np.int64)
+    stored = set((gq * W + gp).tolist())
+    # live part: hit/miss differences between the tracers, and 96 seeded GPU hits outside the stored set
+    mi, mj = _mask_differences(d_p, d_l)
+    hit = np.flatnonzero(np.isfinite(d_p).ravel() | np.isfinite(d_l).ravel())
+    hit = hit[~np.isin(hit, list(stored))]
+    rng = np.random.default_rng(77)
+    extra = np.sort(rng.choice(hit, size=min(96, hit.shape[0]), replace=False))
+    live = np.unique(np.concatenate([mj * W + mi, extra]))
+    live = live[~np.isin(live, list(stored))]
+    lp, lq = live % W, live // W
+    print(f"[c5] {gp.shape[0]} stored pixels ({int((g['flag'] & 1).sum())} oracle hits), {lp.shape[0]} traced now "
+          f"({mi.shape[0]} hit/miss differences between the tracers)", flush=True)
+    lt, ln, lf = oracle_ref(osc, sc.camera, lp, lq)
+    px, py = np.concatenate([gp, lp]), np.concatenate([gq, lq])
+    ref = (np.concatenate([g["t"], lt]), np.concatenate([g["normal"], ln]), np.concatenate([g["flag"], lf]))
     print("[c5] oracle done", flush=True)
     errs = {}
     for name, d, n in (("plain", d_p, n_p), ("learned", d_l, n_l)):
