@@ -673,8 +673,11 @@ st_status st_trace_dump(st_scene* s, const st_camera* cam, float* out_depth, flo
         set_error("trace_dump: the A-buffer was not built for this camera");
         return ST_E_STALE;
     }
-    // the sample counter is the last stats word (cleared with the stats)
+    // the sample counter is the last stats word, cleared here (a fill
+    // kernel, no memset)
     DumpTarget d{features, targets, s->d_stats + (kStatCount - 1), (unsigned long long)cap};
+    hipError_t ec = fill_u32(reinterpret_cast<uint32_t*>(s->d_stats + (kStatCount - 1)), 2u, 0u, stream);
+    if (ec != hipSuccess) return device_error(ec, "trace_dump: clear the sample counter");
     st_status r = trace_device(s, s->ab_tune, out_depth, out_normal, nullptr, stream, &d);
     if (r != ST_OK) return r;
     unsigned long long h = 0;

@@ -291,10 +291,63 @@ __global__ void scan_add_kernel(uint32_t* __restrict__ out, int n, const uint32_
     if (i == 0 && out_total_slot) *out_total_slot = *total;
 }
 
+// One-workgroup exclusive scan for short arrays (the per-tile counts): chunks
+// of 4 elements per thread, inclusive wave scans by shuffles, the sixteen
+// wave totals scanned by one wave, a carry across chunks; two barriers per
+// chunk of 4096 elements.
+constexpr int kScanOneMax = 32768;
+
+__global__ void __launch_bounds__(1024) scan_one_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                        int n, uint32_t* __restrict__ total,
+                                                        uint32_t* __restrict__ out_total_slot) {
+    __shared__ uint32_t wsum[16];
+    const int tid = int(threadIdx.x), lane = tid & 63, w = tid >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < n; base += 4096) {
+        const int i0 = base + 4 * tid;
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[k] = i0 + k < n ? in[i0 + k] : 0u;
+        const uint32_t local = v[0] + v[1] + v[2] + v[3];
+        uint32_t x = local;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = uint32_t(__shfl_up(int(x), o));
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        if (w == 0) {
+            uint32_t t = lane < 16 ? wsum[lane] : 0u;
+            for (int o = 1; o < 16; o <<= 1) {
+                const uint32_t y = uint32_t(__shfl_up(int(t), o));
+                if (lane >= o) t += y;
+            }
+            if (lane < 16) wsum[lane] = t;
+        }
+        __syncthreads();
+        uint32_t run = carry + (w > 0 ? wsum[w - 1] : 0u) + x - local;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (i0 + k < n) out[i0 + k] = run;
+            run += v[k];
+        }
+        carry += wsum[15];
+        __syncthreads();   // wsum is rewritten by the next chunk
+    }
+    if (tid == 0) {
+        *total = carry;
+        if (out_total_slot) *out_total_slot = carry;
+    }
+}
+
 // out[0..n) = exclusive scan of in, *total = sum; if out_total_slot, also
 // writes the total there (CSR end offset).  scratch: >= ceil(n/1024)+1 u32.
 void exclusive_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* scratch, uint32_t* total,
                            uint32_t* out_total_slot, hipStream_t stream) {
+    if (n <= kScanOneMax) {
+        hipLaunchKernelGGL(scan_one_kernel, dim3(1), dim3(1024), 0, stream, in, out, n, total, out_total_slot);
+        return;
+    }
     int nb = (n + kScanBlock - 1) / kScanBlock;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(kScanBlock), 0, stream, in, out, n, scratch);
@@ -319,6 +372,28 @@ constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4 * kOrderThreads;
 constexpr int kOrderBatch = 8;
 
+// cnt[bk] += 1 for every active lane of the wave, one atomic per distinct
+// bucket (most tiles share a few small counts, and per-lane atomics on the
+// same LDS word serialise); returns the lane's old value plus its rank among
+// the lanes of its bucket.  Called by every lane of the wave.
+__device__ __forceinline__ uint32_t wave_bucket_add(uint32_t* cnt, uint32_t bk, bool active) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t mine = 0;
+    uint64_t todo = __ballot(active);
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const uint32_t b = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(bk, leader));
+        const uint64_t m = __ballot(bk == b) & todo;
+        uint32_t base = 0;
+        if (lane == uint32_t(leader)) base = atomicAdd(cnt + b, uint32_t(__popcll(m)));
+        base = __builtin_amdgcn_readlane(base, leader);
+        if ((m >> lane) & 1ull)
+            mine = base + __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+        todo &= ~m;
+    }
+    return mine;
+}
+
 __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_t* __restrict__ tile_cnt,
                                                                     int n_tiles, uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[kOrderBuckets];
@@ -337,8 +412,7 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
 #pragma unroll
         for (int k = 0; k < kOrderBatch; k++) bk[k] = bucket(t0 + k * kOrderThreads + tid);
 #pragma unroll
-        for (int k = 0; k < kOrderBatch; k++)
-            if (t0 + k * kOrderThreads + tid < n_tiles) atomicAdd(&cnt[bk[k]], 1u);
+        for (int k = 0; k < kOrderBatch; k++) wave_bucket_add(cnt, bk[k], t0 + k * kOrderThreads + tid < n_tiles);
     }
     __syncthreads();
     // exclusive scan: four buckets per thread, then an inclusive scan of the
@@ -363,13 +437,14 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
 #pragma unroll
         for (int k = 0; k < kOrderBatch; k++) {
             const int t = t0 + k * kOrderThreads + tid;
-            if (t < n_tiles) order[atomicAdd(&cnt[bk[k]], 1u)] = uint32_t(t);
+            const uint32_t pos = wave_bucket_add(cnt, bk[k], t < n_tiles);
+            if (t < n_tiles) order[pos] = uint32_t(t);
         }
     }
 }
 
-// per primitive (one workgroup): one candidate for every tile of its rectangle
-__global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict__ trect, int tiles_x,
+// per primitive (one wave): one candidate for every tile of its rectangle
+__global__ void __launch_bounds__(64) cand_count_kernel(const int4* __restrict__ trect, int tiles_x,
                                                          uint32_t* __restrict__ tile_count) {
     const int4 rc = trect[blockIdx.x];
     const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
@@ -379,7 +454,7 @@ __global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict_
 }
 
 // per primitive (one workgroup): its index into a slot of each tile segment
-__global__ void __launch_bounds__(256) cand_scatter_kernel(const int4* __restrict__ trect, int tiles_x,
+__global__ void __launch_bounds__(64) cand_scatter_kernel(const int4* __restrict__ trect, int tiles_x,
                                                            const uint32_t* __restrict__ tile_off,
                                                            uint32_t* __restrict__ cursor,
                                                            uint32_t* __restrict__ slot_prim) {
@@ -773,6 +848,146 @@ __device__ void add_tested(const uint32_t* slot_prim, uint32_t e0, int n, int ti
     if (tid == 0) tstat[kTileStat * size_t(tile)] = uint32_t(n);
 }
 
+// ---------------------------------------------------------------------------
+// One wave per tile for lists of at most 64 entries (nearly every tile): the
+// same rule as prune_tile / dead_rounds, with the set in registers (lane i
+// holds one primitive), the order by rank counting and the compaction by
+// ballot, and a 128-slot LDS hash set per wave; no workgroup barrier.
+constexpr int kWavePruneMax = 64;
+constexpr int kWavePruneBits = 7;   // 128 slots >= 2 x 64
+
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Whether the lane's primitive x (valid when in) survives the dead-primitive
+// rule for the set of the valid lanes' primitives (distinct nodes), applied
+// until nothing drops.  srt (64 words) and tab (128 words) are the wave's LDS
+// scratch.  Must be called by every lane of the wave, in uniform control flow
+// (never behind a lane-dependent condition such as a short-circuit &&): it
+// clears the table lane by lane and reads neighbouring lanes' registers.
+__device__ bool wave_alive(uint32_t x, bool in, uint32_t* srt, uint32_t* tab, const uint32_t* __restrict__ rmq,
+                           const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes) {
+    const int lane = int(threadIdx.x & 63u);
+    const uint64_t vm = __ballot(in);
+    int m = __popcll(vm);
+    if (m == 0) return false;
+    // sorted set: rank of each valid node among the valid nodes
+    uint32_t rank = 0;
+    for (uint64_t left = vm; left; left &= left - 1) {
+        const uint32_t xj = __builtin_amdgcn_readlane(x, int(__builtin_ctzll(left)));
+        rank += xj < x ? 1u : 0u;
+    }
+    if (in) srt[rank] = x;
+    wsync();
+    uint32_t sx = lane < m ? srt[lane] : 0xFFFFFFFFu;
+    for (int round = 0; round < 32; round++) {
+        // the nodes with set members on both sides: LCAs of consecutive members
+        tab[lane] = kNoKill;
+        tab[lane + 64] = kNoKill;
+        wsync();
+        const uint32_t nx = __shfl_down(sx, 1);
+        // (the order check only guards the table reads against a logic error)
+        if (lane < m - 1 && sx < nx && nx < n_nodes) hinsert(tab, kWavePruneBits, lca_query(rmq, n_nodes, sx, nx));
+        wsync();
+        const bool keep = lane < m && chain_alive(sx, kslot, kill, n_nodes, tab, kWavePruneBits);
+        const uint64_t km = __ballot(keep);
+        const int k = __popcll(km);
+        if (k == m) break;
+        wsync();
+        if (keep) srt[lanes_below_mask(km)] = sx;
+        wsync();
+        m = k;
+        sx = lane < m ? srt[lane] : 0xFFFFFFFFu;
+        if (m == 0) break;
+    }
+    // membership of x in the surviving set
+    wsync();
+    tab[lane] = kNoKill;
+    tab[lane + 64] = kNoKill;
+    wsync();
+    if (lane < m) hinsert(tab, kWavePruneBits, sx);
+    wsync();
+    return in && m > 0 && hfind(tab, kWavePruneBits, x, tab[hslot(x, kWavePruneBits)]);
+}
+
+// Pre-test pruning of the tiles with 1..64 candidates (the workgroup kernel
+// below takes the longer lists): same result as cand_prune_kernel.
+__global__ void __launch_bounds__(256) cand_prune_wave_kernel(
+        const uint32_t* __restrict__ tile_off, int n_tiles, int tiles_x, int ts, const uint32_t* __restrict__ prims,
+        const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim, uint32_t* __restrict__ tile_n,
+        const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
+        uint32_t n_nodes, uint32_t* __restrict__ tstat) {
+    __shared__ uint32_t srt[4][kWavePruneMax], tab[4][2 * kWavePruneMax];
+    const int w = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63u);
+    const int tile = int(blockIdx.x) * 4 + w;
+    if (tile >= n_tiles) return;   // whole waves
+    const uint32_t e0 = tile_off[tile];
+    const int n = int(tile_off[tile + 1] - e0);
+    if (n == 0 || n > kWavePruneMax) return;
+    const bool in = lane < n;
+    const uint32_t p = in ? slot_prim[e0 + lane] : 0u;
+    const uint32_t x = in ? prims[p] : 0u;
+    const bool keep = wave_alive(x, in, srt[w], tab[w], rmq, kslot, kill, n_nodes);
+    const uint64_t km = __ballot(keep);
+    if (keep) slot_prim[e0 + lanes_below_mask(km)] = p;   // every lane read its slot above
+    const int kept = __popcll(km);
+    // the tile's record: candidates kept, and by kind the pixels of their
+    // rectangles inside the tile (the per-ray test's work)
+    const int x0 = (tile % tiles_x) * ts, y0 = (tile / tiles_x) * ts;
+    uint32_t area[3] = {0, 0, 0};
+    if (keep) {
+        const int4 r = rect[p];
+        const int wx = min(r.z, x0 + ts - 1) - max(r.x, x0) + 1, wy = min(r.w, y0 + ts - 1) - max(r.y, y0) + 1;
+        const int kind = int(voi[p].v[20]) - ST_SPHERE;
+        if (wx > 0 && wy > 0 && kind >= 0 && kind < 3) area[kind] = uint32_t(wx * wy);
+    }
+    for (int k = 0; k < 3; k++)
+        for (int o = 32; o > 0; o >>= 1) area[k] += uint32_t(__shfl_xor(int(area[k]), o));
+    if (lane == 0) {
+        tile_n[tile] = uint32_t(kept);
+        tstat[kTileStat * size_t(tile)] = uint32_t(kept);
+        for (int k = 0; k < 3; k++) tstat[kTileStat * size_t(tile) + 1 + k] = area[k];
+    }
+}
+
+// Post-test pruning of the tiles with 1..64 tested candidates: same result as
+// tile_prune_kernel (entries that hit and survive, compacted in order).
+__global__ void __launch_bounds__(256) tile_prune_wave_kernel(
+        const uint32_t* __restrict__ tile_off, int n_tiles, uint32_t* e_node, float* e_zin, float* e_zout,
+        uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot,
+        const uint32_t* __restrict__ kill, uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
+    __shared__ uint32_t srt[4][kWavePruneMax], tab[4][2 * kWavePruneMax];
+    const int w = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63u);
+    const int tile = int(blockIdx.x) * 4 + w;
+    if (tile >= n_tiles) return;
+    const uint32_t e0 = tile_off[tile];
+    const int n = int(tile_cnt[tile]);
+    if (n == 0 || n > kWavePruneMax) return;
+    const bool in = lane < n;
+    const uint32_t x = in ? e_node[e0 + lane] : 0u;
+    const float zi = in ? e_zin[e0 + lane] : 0.f, zo = in ? e_zout[e0 + lane] : 0.f;
+    const bool hit = in && zi <= zo;
+    bool keep = hit;
+    if (!keep_all) {   // uniform: every lane of the wave takes part in wave_alive
+        const bool alive = wave_alive(x, hit, srt[w], tab[w], rmq, kslot, kill, n_nodes);
+        keep = hit && alive;
+    }
+    const uint64_t km = __ballot(keep);
+    const uint64_t hm = __ballot(hit);
+    if (keep) {   // every lane read its entry above
+        const uint32_t d = e0 + lanes_below_mask(km);
+        e_node[d] = x;
+        e_zin[d] = zi;
+        e_zout[d] = zo;
+    }
+    if (lane == 0) {
+        tile_cnt[tile] = uint32_t(__popcll(km));
+        tstat[kTileStat * size_t(tile) + 4] = uint32_t(__popcll(hm));
+    }
+}
+
 __global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
         const uint32_t* __restrict__ tile_off, int n_tiles, int tiles_x, int ts, const uint32_t* __restrict__ prims,
         const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim, uint32_t* __restrict__ tile_n,
@@ -784,6 +999,7 @@ __global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
     const int tid = int(threadIdx.x);
     const uint32_t e0 = tile_off[tile];
     const int n = int(tile_off[tile + 1] - e0);
+    if (!keep_all && n >= 1 && n <= kWavePruneMax) return;   // cand_prune_wave_kernel's tile
     if (n == 0 || n > kPruneLdsCap || keep_all) {
         if (tid == 0) tile_n[tile] = uint32_t(n);
         if (n) add_tested(slot_prim, e0, n, tile, tiles_x, ts, rect, voi, tstat);
@@ -832,7 +1048,7 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
     const uint32_t e0 = tile_off[tile];
     const int n = int(tile_cnt[tile]);   // tested candidates of the segment
     __syncthreads();                     // every thread has read it before thread 0 rewrites it
-    if (n == 0) return;
+    if (n == 0 || n <= kWavePruneMax) return;   // empty, or pruned by tile_prune_wave_kernel
     if (n > kPruneLdsCap) {
         if (threadIdx.x == 0) long_list[atomicAdd(misc + 5, 1u)] = uint32_t(tile);
         return;
@@ -1117,7 +1333,9 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     unsigned long long* pix = reinterpret_cast<unsigned long long*>(misc + 16);   // 3 counters, 8-byte aligned
     if (P) hipLaunchKernelGGL(rect_kernel, dim3((8 * P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
                        s->d_oside, s->d_sub, t.keep_all_entries, rect, trect);
-    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, trect, s->tiles_x, tcnt);
+    // one wave per primitive: a rectangle covers about 60 tiles on the 1080p
+    // frame, so wider workgroups would mostly idle
+    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(64), 0, stream, trect, s->tiles_x, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_cand = replay ? s->n_cand : 0u;
     if (!replay) {
@@ -1143,10 +1361,14 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         s->ab_cap = cap;
     }
     if (P && n_cand)
-        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, trect, s->tiles_x, s->d_tile_off,
+        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(64), 0, stream, trect, s->tiles_x, s->d_tile_off,
                            cur, s->d_e_node);
     // candidates dead for their tile's candidate set: dropped before the test
     // (d_tile_cnt: candidates left per tile)
+    if (!t.keep_all_entries)
+        hipLaunchKernelGGL(cand_prune_wave_kernel, dim3((T + 3) / 4), dim3(256), 0, stream, s->d_tile_off, T,
+                           s->tiles_x, ts, s->d_prims, rect, s->d_voi, s->d_e_node, s->d_tile_cnt, s->d_rmq,
+                           reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes), tstat);
     hipLaunchKernelGGL(cand_prune_kernel, dim3(T), dim3(kPruneThreads), 0, stream, s->d_tile_off, T, s->tiles_x, ts,
                        s->d_prims, rect, s->d_voi, s->d_e_node, s->d_tile_cnt, s->d_rmq,
                        reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
@@ -1193,25 +1415,34 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     }
     char* lbuf = (char*)s->d_long;
     // tile-level pruning (long lists: the kernel reads their count on the device)
+    hipLaunchKernelGGL(tile_prune_wave_kernel, dim3((T + 3) / 4), dim3(256), 0, stream, s->d_tile_off, T, s->d_e_node,
+                       s->d_e_zin, s->d_e_zout, s->d_tile_cnt, s->d_rmq, reinterpret_cast<const uint4*>(s->d_kslot),
+                       s->d_kill, uint32_t(s->n_nodes), t.keep_all_entries, tstat);
     hipLaunchKernelGGL(tile_prune_kernel, dim3(T), dim3(kPruneThreads), 0, stream, s->d_tile_off, T, s->d_e_node,
                        s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc, s->d_rmq,
                        reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
                        t.keep_all_entries, tstat);
-    hipLaunchKernelGGL(tile_prune_long_kernel, dim3(std::min(T, 512)), dim3(kPruneThreads), 0, stream,
+    // A replay has the counts of its sizing build: kernels whose queue was
+    // empty then are not launched (three launches of a few microseconds each
+    // on frames without long lists).
+    if (!replay || s->n_long_prune)
+        hipLaunchKernelGGL(tile_prune_long_kernel, dim3(std::min(T, 512)), dim3(kPruneThreads), 0, stream,
                        s->d_tile_off, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc,
                        reinterpret_cast<uint32_t*>(lbuf), s->d_rmq, reinterpret_cast<const uint4*>(s->d_kslot),
                        s->d_kill, uint32_t(s->n_nodes), t.keep_all_entries, tstat);
     hipLaunchKernelGGL(tile_sort_short_kernel, dim3((T + 3) / 4), dim3(256), 0, stream, s->d_tile_off,
                        s->d_tile_cnt, T, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, queue, misc,
                        uint32_t(s->ab_ma_fast), s->d_wide);
-    hipLaunchKernelGGL(tile_sort_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream, s->d_tile_off,
+    if (!replay || s->n_sort_queue)
+        hipLaunchKernelGGL(tile_sort_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream, s->d_tile_off,
                        s->d_tile_cnt, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, queue, longl, misc,
                        uint32_t(s->ab_ma_fast), s->d_wide);
     // long tiles, if any (the kernel reads their count on the device)
     uint64_t* sk = (uint64_t*)lbuf;
     uint32_t* sv = (uint32_t*)(lbuf + size_t(2) * n_ent * 8);
     uint32_t* sz = (uint32_t*)(lbuf + size_t(2) * n_ent * 12);
-    hipLaunchKernelGGL(tile_sort_long_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream,
+    if (!replay || s->n_long_sort)
+        hipLaunchKernelGGL(tile_sort_long_kernel, dim3(std::min(T, 512)), dim3(kSortThreads), 0, stream,
                        s->d_tile_off, s->d_tile_cnt, s->d_e_node, s->d_e_zin, s->d_e_zout, s->d_tile_ovl, longl,
                        misc, sk, sv, sz, uint32_t(s->ab_ma_fast), s->d_wide);
     // (the trace takes the tiles in the test's order: a tile's kept entries
@@ -1223,8 +1454,8 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     }
     hipLaunchKernelGGL(build_stats_kernel, dim3(1), dim3(kStatThreads), 0, stream, s->d_tile_cnt, s->d_tile_ovl, tstat,
                        T, misc, pix);
-    uint32_t h_misc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, h_wide = 0;
-    ST_CHECK(hipMemcpyAsync(h_misc, misc, 32, hipMemcpyDeviceToHost, stream), "copy build stats");
+    uint32_t h_misc[16] = {}, h_wide = 0;
+    ST_CHECK(hipMemcpyAsync(h_misc, misc, 64, hipMemcpyDeviceToHost, stream), "copy build stats");
     ST_CHECK(hipMemcpyAsync(s->cand_pix, pix, 24, hipMemcpyDeviceToHost, stream), "copy candidate pixels");
     ST_CHECK(hipMemcpyAsync(&h_wide, s->d_wide, 4, hipMemcpyDeviceToHost, stream), "copy wide count");
     e = hipGetLastError();
@@ -1235,6 +1466,9 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     s->n_live = h_misc[3];
     s->n_entries = h_misc[6];   // candidates that hit
     s->n_tested = h_misc[7];    // candidates left for the per-ray test
+    s->n_long_sort = h_misc[0];   // queue lengths of the long-list kernels
+    s->n_long_prune = h_misc[5];
+    s->n_sort_queue = h_misc[10];
     s->n_wide = h_wide;
 #undef ST_CHECK
     return ST_OK;

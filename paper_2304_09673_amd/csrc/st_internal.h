@@ -73,6 +73,9 @@ struct st_scene {
     uint32_t n_cand = 0;        // (primitive, tile) candidates of the last build
     uint64_t ab_gen = 0;        // bumped by every st_build_abuffer
     uint32_t max_list = 0, max_overlap = 0, n_wide = 0;
+    // tiles queued for the long-list pruning, the workgroup sort and the
+    // long-list sort in the last sizing build (replays skip empty queues)
+    uint32_t n_long_prune = 0, n_sort_queue = 0, n_long_sort = 0;
     int32_t ab_ma_fast = 0, ab_ma_wide = 0;
 
     // dexel buffer of the ablation tracer: per-pixel CSR offsets, counts and

@@ -230,9 +230,9 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
             slots = reinterpret_cast<uint32_t*>(s->d_slots);
         }
     }
-    // every size is checked: launch from here on
-    hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(s->d_stats), 2u * kStatCount, 0u, stream);
-    if (e != hipSuccess) return device_error(e, "clear stats");
+    // every size is checked: launch from here on (the counter reduction
+    // overwrites every counter it reports, so the stats words need no clear)
+    hipError_t e = hipSuccess;
     switch (sm) {
     case SM_PLAIN:
         e = shallow ? launch_trace<16, SM_PLAIN>(A, nwg, n_jobs, grid, slots, ma, stream)
