@@ -52,6 +52,13 @@ enum {
                         p[6..9] rotation quaternion (w,x,y,z), non-zero; the
                         box axes are the columns of its rotation matrix */
     ST_CAPSULE = 2,  /* p[0..2] a, p[3..5] b, p[6] radius > 0 */
+    ST_TORUS = 3,    /* p[0..2] centre, p[3] major radius R > 0, p[4] minor
+                        radius r > 0, p[5..8] rotation quaternion (w,x,y,z),
+                        non-zero; the ring lies in the local x-z plane around
+                        the local y axis (the column of the rotation) */
+    ST_CYLINDER = 4, /* capped cylinder: p[0..2] centre, p[3] radius > 0,
+                        p[4] half height > 0, p[5..8] rotation quaternion;
+                        its axis is the local y axis */
     ST_UNION = 16,   /* sharp union, no parameters */
     ST_INTER = 17,   /* sharp intersection */
     ST_DIFF = 18,    /* sharp difference left \ right */
@@ -145,7 +152,8 @@ typedef struct {
                                  steps, probes, refinements, learned-step
                                  checks; a value+gradient evaluation counts 1 */
     uint64_t grad_evals;      /* value+gradient evaluations (normals) */
-    uint64_t node_evals[4];   /* by node class: sphere, box, capsule, operator */
+    uint64_t node_evals[4];   /* by node class: sphere, box-frame primitive
+                                 (box, torus, cylinder), capsule, operator */
     uint64_t grad_node_evals[4];
     uint64_t steps;           /* stepping evaluations (no refinement/gradient) */
     uint64_t subfrustums;     /* (wave, subfrustum) pairs processed */

@@ -28,7 +28,7 @@
 #endif
 
 enum {
-    K_SPHERE = 0, K_BOX = 1, K_CAPSULE = 2,
+    K_SPHERE = 0, K_BOX = 1, K_CAPSULE = 2, K_TORUS = 3, K_CYLINDER = 4,
     K_UNION = 16, K_INTER = 17, K_DIFF = 18,
     K_SUNION = 19, K_SINTER = 20, K_SDIFF = 21
 };
@@ -46,7 +46,10 @@ typedef struct {
     double ext_lo[3], ext_hi[3];  /* AABB of all primitives (scene extent) */
 } or_scene;
 
-static int is_prim(int k) { return k == K_SPHERE || k == K_BOX || k == K_CAPSULE; }
+static int is_prim(int k) { return k >= K_SPHERE && k <= K_CYLINDER; }
+/* primitives with a rotated local frame: the box (quaternion at p[6..9]),
+ * the torus and the cylinder (quaternion at p[5..8]) */
+static int quat_offset(int k) { return k == K_BOX ? 6 : (k == K_TORUS || k == K_CYLINDER) ? 5 : -1; }
 static int is_op(int k) { return k >= K_UNION && k <= K_SDIFF; }
 static int is_compact(int k) { return k >= K_SUNION && k <= K_SDIFF; }
 
@@ -119,8 +122,38 @@ static dual prim_dual(const or_scene *s, int i, const dual p[3]) {
         for (int j = 0; j < 3; j++) { dual w = dsub(pa[j], dscale(h, ba[j])); w2 = dadd(w2, dmul(w, w)); }
         return dsub(dsqrt(w2), dconst(a[6]));
     }
+    case K_TORUS:
+    case K_CYLINDER: {
+        /* local coordinates l = R^T (p - c); the axis of revolution is local y.
+         * Torus (ring of major radius a[3] in the local x-z plane, tube radius
+         * a[4]): distance | (sqrt(lx^2 + lz^2) - a[3], ly) | - a[4].
+         * Capped cylinder (radius a[3], half height a[4]): with
+         * w = (sqrt(lx^2 + lz^2) - a[3], |ly| - a[4]), the distance is
+         * |max(w, 0)| + min(max(w.x, w.y), 0). */
+        const double *R = s->rot + 9 * i;
+        dual d[3]; for (int j = 0; j < 3; j++) d[j] = dsub(p[j], dconst(a[j]));
+        dual l[3];
+        for (int j = 0; j < 3; j++)
+            l[j] = dadd(dadd(dscale(d[0], R[0 * 3 + j]), dscale(d[1], R[1 * 3 + j])), dscale(d[2], R[2 * 3 + j]));
+        dual rad = dsqrt(dadd(dmul(l[0], l[0]), dmul(l[2], l[2])));
+        if (s->kind[i] == K_TORUS) {
+            dual qx = dsub(rad, dconst(a[3]));
+            return dsub(dsqrt(dadd(dmul(qx, qx), dmul(l[1], l[1]))), dconst(a[4]));
+        }
+        dual wx = dsub(rad, dconst(a[3])), wy = dsub(dabs(l[1]), dconst(a[4]));
+        dual ox = dmax(wx, dconst(0)), oy = dmax(wy, dconst(0));
+        dual outside = dsqrt(dadd(dmul(ox, ox), dmul(oy, oy)));
+        return dadd(outside, dmin(dmax(wx, wy), dconst(0)));
+    }
     }
     return dconst(INFINITY);
+}
+
+/* Half extents of the local box of a torus or cylinder (local x, y, z). */
+static void ring_extents(const or_scene *s, int i, double e[3]) {
+    const double *a = s->par + 16 * i;
+    if (s->kind[i] == K_TORUS) { e[0] = e[2] = a[3] + a[4]; e[1] = a[4]; }
+    else { e[0] = e[2] = a[3]; e[1] = a[4]; }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -236,6 +269,18 @@ static void prim_aabb(const or_scene *s, int i, double d, double lo[3], double h
             lo[j] = m - a[6] - d; hi[j] = M + a[6] + d;
         }
         break;
+    case K_TORUS:
+    case K_CYLINDER: {
+        const double *R = s->rot + 9 * i;
+        double ext[3];
+        ring_extents(s, i, ext);
+        for (int j = 0; j < 3; j++) {
+            double e = 0;
+            for (int c = 0; c < 3; c++) e += fabs(R[j * 3 + c]) * (ext[c] + d);
+            lo[j] = a[j] - e; hi[j] = a[j] + e;
+        }
+        break;
+    }
     }
 }
 
@@ -262,7 +307,7 @@ or_scene *or_scene_new(const int32_t *kind, const int32_t *left, const int32_t *
         for (int j = 0; j < 16; j++) s->par[16 * i + j] = (double)params[16 * i + j];
         if (!is_prim(kind[i]) && !is_op(kind[i])) goto bad;
         if (is_op(kind[i]) && (left[i] < 0 || left[i] >= n || right[i] < 0 || right[i] >= n)) goto bad;
-        if (kind[i] == K_BOX) quat_to_rot(s->par + 16 * i + 6, s->rot + 9 * i);
+        if (quat_offset(kind[i]) >= 0) quat_to_rot(s->par + 16 * i + quat_offset(kind[i]), s->rot + 9 * i);
         if (is_compact(kind[i])) {
             double k = s->par[16 * i], d = s->par[16 * i + 1];
             if (!(k > 0)) goto bad;
@@ -582,13 +627,19 @@ static int ray_voi(const or_scene *s, int i, const double o[3], const double d[3
     switch (s->kind[i]) {
     case K_SPHERE:
         return ray_sphere(o, d, a, a[3] + dd, t0, t1);
-    case K_BOX: {
+    case K_BOX:
+    case K_TORUS:
+    case K_CYLINDER: {
+        /* the volume of interest of these three is the oriented box of the
+         * primitive's local box grown by d */
         const double *R = s->rot + 9 * i;
+        double ext[3] = {a[3], a[4], a[5]};
+        if (s->kind[i] != K_BOX) ring_extents(s, i, ext);
         double lo = -INFINITY, hi = INFINITY;
         for (int j = 0; j < 3; j++) {
             double ol = 0, dl = 0;
             for (int q = 0; q < 3; q++) { ol += R[q * 3 + j] * (o[q] - a[q]); dl += R[q * 3 + j] * d[q]; }
-            double e = a[3 + j] + dd;
+            double e = ext[j] + dd;
             if (dl == 0) { if (fabs(ol) > e) return 0; continue; }
             double u = (-e - ol) / dl, v = (e - ol) / dl;
             if (u > v) { double w = u; u = v; v = w; }
@@ -689,11 +740,15 @@ int or_in_voi(const or_scene *s, int i, const double x[3]) {
         double q = 0; for (int j = 0; j < 3; j++) q += (x[j] - a[j]) * (x[j] - a[j]);
         return sqrt(q) <= a[3] + dd;
     }
-    case K_BOX: {
+    case K_BOX:
+    case K_TORUS:
+    case K_CYLINDER: {
         const double *R = s->rot + 9 * i;
+        double ext[3] = {a[3], a[4], a[5]};
+        if (s->kind[i] != K_BOX) ring_extents(s, i, ext);
         for (int j = 0; j < 3; j++) {
             double l = 0; for (int q = 0; q < 3; q++) l += R[q * 3 + j] * (x[q] - a[q]);
-            if (fabs(l) > a[3 + j] + dd) return 0;
+            if (fabs(l) > ext[j] + dd) return 0;
         }
         return 1;
     }

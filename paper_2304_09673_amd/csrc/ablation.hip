@@ -140,7 +140,7 @@ struct EvalF {
     __device__ V none() const { return {__builtin_inff(), 0.f}; }
     __device__ V prim(uint32_t n) {
         const uint32_t k = blob_op(blob[n]);
-        kinds[k <= ST_CAPSULE ? k : 0]++;
+        kinds[node_class(k)]++;
         return {prim_eval<float>(k, (const cfloat*)(par[n].v), p), 1.f};
     }
     __device__ V single(uint32_t op, const V& a, bool from_left) const {

@@ -50,8 +50,17 @@ st_status validate_primitive(const st_node& nd, int i) {
         set_error("primitive " + std::to_string(i) + " has children");
         return ST_E_TREE;
     }
-    int cnt = k == ST_SPHERE ? 4 : k == ST_BOX ? 10 : 7;
+    int cnt = k == ST_SPHERE ? 4 : k == ST_BOX ? 10 : k == ST_CAPSULE ? 7 : 9;
     if (!finite_params(nd, cnt)) { set_error("non-finite primitive parameter"); return ST_E_INVALID; }
+    if (k == ST_TORUS || k == ST_CYLINDER) {
+        if (!(nd.p[3] > 0 && nd.p[4] > 0)) {
+            set_error(k == ST_TORUS ? "torus radius <= 0" : "cylinder radius or half height <= 0");
+            return ST_E_INVALID;
+        }
+        double qn = 0;
+        for (int j = 5; j < 9; j++) qn += double(nd.p[j]) * nd.p[j];
+        if (!(qn > 1e-20)) { set_error("zero quaternion"); return ST_E_INVALID; }
+    }
     if (k == ST_SPHERE && !(nd.p[3] > 0)) { set_error("sphere radius <= 0"); return ST_E_INVALID; }
     if (k == ST_BOX) {
         if (!(nd.p[3] > 0 && nd.p[4] > 0 && nd.p[5] > 0)) { set_error("box extent <= 0"); return ST_E_INVALID; }
@@ -90,6 +99,29 @@ void primitive_params(const st_node& nd, double d, NodePar& par, PrimBox& box) {
             for (int a = 0; a < 3; a++) {
                 e += std::fabs(ax[a][j]) * nd.p[3 + a];
                 ev += std::fabs(ax[a][j]) * (nd.p[3 + a] + d);   // VOI box: offset along the box axes
+            }
+            box.lo[j] = nd.p[j] - e; box.hi[j] = nd.p[j] + e;
+            box.vlo[j] = nd.p[j] - ev; box.vhi[j] = nd.p[j] + ev;
+        }
+        break;
+    }
+    case ST_TORUS:
+    case ST_CYLINDER: {
+        // local frame of the quaternion; axis 1 is the axis of revolution
+        double ax[3][3];
+        quat_axes(nd.p + 5, ax);
+        for (int j = 0; j < 3; j++) q[j] = nd.p[j];
+        for (int a = 0; a < 3; a++)
+            for (int c = 0; c < 3; c++) q[4 + 4 * a + c] = float(ax[a][c]);
+        q[3] = nd.p[3];
+        q[7] = nd.p[4];
+        const double ext[3] = {nd.kind == ST_TORUS ? double(nd.p[3]) + nd.p[4] : double(nd.p[3]), double(nd.p[4]),
+                               nd.kind == ST_TORUS ? double(nd.p[3]) + nd.p[4] : double(nd.p[3])};
+        for (int j = 0; j < 3; j++) {
+            double e = 0, ev = 0;
+            for (int a = 0; a < 3; a++) {
+                e += std::fabs(ax[a][j]) * ext[a];
+                ev += std::fabs(ax[a][j]) * (ext[a] + d);   // volume of interest: the local box grown by d
             }
             box.lo[j] = nd.p[j] - e; box.hi[j] = nd.p[j] + e;
             box.vlo[j] = nd.p[j] - ev; box.vhi[j] = nd.p[j] + ev;

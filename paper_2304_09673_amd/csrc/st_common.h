@@ -40,7 +40,10 @@ constexpr uint32_t kIgnoreNever = 0u;   // union-like
 constexpr uint32_t kIgnoreLeftAbsent = 2u;   // difference-like
 constexpr uint32_t kIgnoreAny = 3u;     // intersection-like
 
-HD bool is_prim_kind(uint32_t k) { return k <= ST_CAPSULE; }
+HD bool is_prim_kind(uint32_t k) { return k <= ST_CYLINDER; }
+// node class of the evaluation counters: sphere, primitive in a rotated box
+// frame (box, torus, cylinder), capsule, operator
+HD uint32_t node_class(uint32_t k) { return k == ST_SPHERE ? 0u : k == ST_CAPSULE ? 2u : k <= ST_CYLINDER ? 1u : 3u; }
 HD bool is_op_kind(uint32_t k) { return k >= ST_UNION && k <= ST_SDIFF; }
 HD bool is_compact_kind(uint32_t k) { return k >= ST_SUNION && k <= ST_SDIFF; }
 HD uint32_t ignore_of(uint32_t k) {
@@ -60,6 +63,10 @@ HD uint32_t ventry_kind(uint32_t e) { return e >> 24; }
 //  box    : [0..2] c, [4..6] axis 0, [7] h0, [8..10] axis 1, [11] h1,
 //           [12..14] axis 2, [15] h2  (local coordinate i = axis_i . (p-c))
 //  capsule: [0..2] a, [3] r, [4..6] b - a, [7] 1/|b-a|^2 (0 when a = b)
+//  torus  : [0..2] c, [3] R, [4..6] axis 0, [7] r, [8..10] axis 1 (of
+//           revolution), [12..14] axis 2
+//  cylinder: [0..2] c, [3] radius, [4..6] axis 0, [7] half height, [8..10]
+//           axis 1 (the cylinder's axis), [12..14] axis 2
 //  operator: [0] k, [1] 1/k, [2] s = 6k/(6 d_o - k), [3] d_o,
 //            [4] Lipschitz factor 1 + k/(6 d_o - k) (1 for sharp),
 //            [5] k/6
@@ -72,6 +79,8 @@ struct NodePar { float v[16]; };
 //  box    : [4..6] c, [8..10] axis0, [11] h0+d, [12..14] axis1, [15] h1+d,
 //           [16..18] axis2, [19] h2+d
 //  capsule: [4..6] a, [7] r + d, [8..10] b
+//  (a torus or cylinder has the oriented-box volume of its local box grown
+//  by d, stored as a box)
 //  [20] kind, [21] node index (as float bits)
 struct Voi { float v[24]; };
 

@@ -165,11 +165,39 @@ __device__ __forceinline__ T op_eval(uint32_t kind, const cfloat* q, const T& a,
     return cst(__builtin_inff(), a);
 }
 
+// torus and capped cylinder: exact distances in the local frame, whose
+// y axis is the axis of revolution; rad = distance to that axis.
+//  torus:    |(rad - R, ly)| - r
+//  cylinder: w = (rad - radius, |ly| - h): |max(w, 0)| + min(max(wx, wy), 0)
+template <class T>
+__device__ __forceinline__ T prim_torus(const cfloat* q, const P3<T>& p) {
+    T dx = p.x - q[0], dy = p.y - q[1], dz = p.z - q[2];
+    T lx = dx * q[4] + dy * q[5] + dz * q[6];
+    T ly = dx * q[8] + dy * q[9] + dz * q[10];
+    T lz = dx * q[12] + dy * q[13] + dz * q[14];
+    T qx = sqrt_(lx * lx + lz * lz) - q[3];
+    return sqrt_(qx * qx + ly * ly) - q[7];
+}
+
+template <class T>
+__device__ __forceinline__ T prim_cylinder(const cfloat* q, const P3<T>& p) {
+    T dx = p.x - q[0], dy = p.y - q[1], dz = p.z - q[2];
+    T lx = dx * q[4] + dy * q[5] + dz * q[6];
+    T ly = dx * q[8] + dy * q[9] + dz * q[10];
+    T lz = dx * q[12] + dy * q[13] + dz * q[14];
+    T wx = sqrt_(lx * lx + lz * lz) - q[3];
+    T wy = fabs_(ly) - q[7];
+    T ox = relu_(wx), oy = relu_(wy);
+    return sqrt_(ox * ox + oy * oy) + fmin_(fmax_(wx, wy), cst(0.f, wx));
+}
+
 template <class T>
 __device__ __forceinline__ T prim_eval(uint32_t kind, const cfloat* q, const P3<T>& p) {
     if (kind == ST_SPHERE) return prim_sphere(q, p);
     if (kind == ST_BOX) return prim_box(q, p);
-    return prim_capsule(q, p);
+    if (kind == ST_CAPSULE) return prim_capsule(q, p);
+    if (kind == ST_TORUS) return prim_torus(q, p);
+    return prim_cylinder(q, p);
 }
 
 }  // namespace st

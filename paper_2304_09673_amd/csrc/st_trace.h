@@ -228,7 +228,7 @@ __device__ __forceinline__ T eval_view(const uint32_t* view, int len_in, const N
             // operands pending above it, at indices 1..D; with KS >= D (KS is
             // at least the tree depth) only index KS wraps, onto that dead
             // slot 0.  An unconditional push is one indexed register move.
-            if (kind <= ST_CAPSULE) {
+            if (kind <= ST_CYLINDER) {
                 stk[sp & (KS - 1)] = acc;
                 sp++;
                 acc = prim_eval<T>(kind, q, p);
@@ -268,7 +268,7 @@ __device__ __forceinline__ float eval_view_seg(const uint32_t* view, int len_in,
             uint32_t kind = ventry_kind(e);
             const cfloat* q = (const cfloat*)(par[min(ventry_node(e), n_nodes - 1u)].v);
             // push as in eval_view (slot 0 is the dead bottom value)
-            if (kind <= ST_CAPSULE) {
+            if (kind <= ST_CYLINDER) {
                 stk[sp & (KS - 1)] = acc;
                 stl[sp & (KS - 1)] = lam;
                 sp++;
@@ -792,7 +792,7 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         uint32_t kc[4] = {0, 0, 0, 0};
         for (int j = lane; j < len; j += 64) {
             uint32_t kd = ventry_kind(S.view()[j]);
-            kc[kd <= ST_CAPSULE ? kd : 3]++;
+            kc[node_class(kd)]++;
         }
         for (int q = 0; q < 4; q++) kc[q] = uni(wave_sum(kc[q]));
 

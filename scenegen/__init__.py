@@ -16,6 +16,10 @@ Scene arrays (one row per blobtree node, any node order, ``root`` given):
   - BOX     : c(3), half extents h(3), unit quaternion (w, x, y, z); the box
               axes are the columns of the quaternion's rotation matrix
   - CAPSULE : segment end a(3), segment end b(3), r
+  - TORUS   : c(3), major radius R, minor radius r, unit quaternion (w, x, y, z);
+              the ring lies in the local x-z plane around the local y axis
+  - CYLINDER: c(3), radius, half height, unit quaternion; capped, its axis is
+              the local y axis
   - UNION / INTER / DIFF (sharp CSG): no parameters
   - SUNION / SINTER / SDIFF (compact smooth CSG): k, d_o (d_o <= 0 asks the
     consumer to derive d_o from k)
@@ -30,11 +34,14 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SPHERE, BOX, CAPSULE = 0, 1, 2
+SPHERE, BOX, CAPSULE, TORUS, CYLINDER = 0, 1, 2, 3, 4
 UNION, INTER, DIFF = 16, 17, 18
 SUNION, SINTER, SDIFF = 19, 20, 21
 
+# the primitive types of the configured workloads
 PRIMITIVE_KINDS = (SPHERE, BOX, CAPSULE)
+# every primitive type the library takes
+EXTENDED_KINDS = (SPHERE, BOX, CAPSULE, TORUS, CYLINDER)
 OPERATOR_KINDS = (UNION, INTER, DIFF, SUNION, SINTER, SDIFF)
 
 
@@ -125,6 +132,16 @@ def _primitive(rng, b: _Builder, centre, s, kinds=PRIMITIVE_KINDS):
         h = s * rng.uniform(0.5, 1.0, size=3)
         q = _unit_quaternion(rng)
         return b.add(BOX, p=(*c, *h, *q))
+    if t == TORUS:
+        R = s * rng.uniform(0.5, 1.0)
+        r = R * rng.uniform(0.2, 0.5)
+        q = _unit_quaternion(rng)
+        return b.add(TORUS, p=(*c, R, r, *q))
+    if t == CYLINDER:
+        rad = s * rng.uniform(0.4, 1.0)
+        h = s * rng.uniform(0.4, 1.0)
+        q = _unit_quaternion(rng)
+        return b.add(CYLINDER, p=(*c, rad, h, *q))
     u = _unit_vector(rng)
     a, e = c - 0.5 * s * u, c + 0.5 * s * u
     return b.add(CAPSULE, p=(*a, *e, 0.5 * s))
@@ -172,7 +189,7 @@ def config1(seed: int = 0, width: int = 256, height: int = 256) -> Scene:
 
 
 def _mixed_scene(name, seed, n_prims, size_range, max_depth, width, height, tile,
-                 centres=None, config=None):
+                 centres=None, config=None, kinds=PRIMITIVE_KINDS):
     rng = _rng(seed)
     b = _Builder()
     if centres is None:
@@ -180,7 +197,7 @@ def _mixed_scene(name, seed, n_prims, size_range, max_depth, width, height, tile
     leaves = []
     for i in range(n_prims):
         s = float(rng.uniform(*size_range))
-        leaves.append(_primitive(rng, b, centres[i], s))
+        leaves.append(_primitive(rng, b, centres[i], s, kinds=kinds))
     root = _random_tree(rng, b, leaves, max_depth, (0.6, 0.2, 0.2), (0.02, 0.15))
     return b.finish(name, root, Camera(width=width, height=height),
                     {"config": config, "seed": seed, "tile": tile, "max_depth": max_depth})
@@ -192,6 +209,16 @@ def config2(seed: int = 0, width: int = 1024, height: int = 1024, n_prims: int =
     compact smooth union/intersection/difference 60/20/20%, k U[0.02,0.15]; 1024^2."""
     return _mixed_scene(f"c2_{n_prims}prims", seed, n_prims, (0.05, 0.4), max_depth,
                         width, height, 16, config=2)
+
+
+def config2_extended(seed: int = 0, width: int = 256, height: int = 256, n_prims: int = 142,
+                     max_depth: int = 10) -> Scene:
+    """The second workload's laws with every primitive type the library takes
+    (sphere, box, capsule, torus, capped cylinder drawn uniformly): torus
+    major radius s U[0.5,1] and minor radius R U[0.2,0.5], cylinder radius and
+    half height s U[0.4,1], uniformly random orientations."""
+    return _mixed_scene(f"c2x_{n_prims}prims", seed, n_prims, (0.05, 0.4), max_depth,
+                        width, height, 16, config=2, kinds=EXTENDED_KINDS)
 
 
 def gaussian_mixture_centres(rng, n, n_clusters=32, sigma=0.15):

@@ -109,3 +109,23 @@ def stratified_pixels(cam, depths, n_random, seed, ring=True, max_hits=None):
     sel[hit_idx] = True
     idx = np.flatnonzero(sel)
     return idx % W, idx // W
+
+
+def assert_masks_agree(sc, da, db, osc=None):
+    """Two GPU images of one frame hit the same pixels, except at rays the
+    oracle finds within SIL_OFFSET of a silhouette (or undecided), where the
+    two tracers' different FP32 evaluation orders may decide differently."""
+    ha, hb = np.isfinite(da), np.isfinite(db)
+    jj, ii = np.nonzero(ha != hb)
+    if ii.size == 0:
+        return 0
+    osc = osc or oracle.OracleScene(sc)
+    cam = sc.camera
+    fx, fy = ii.astype(np.float64) + 0.5, jj.astype(np.float64) + 0.5
+    t, _, flag, _ = osc.trace(cam, fx, fy)
+    hit_o = (flag & 1) != 0
+    tol = DEPTH_REL_TOL * osc.extent
+    ok = ((flag & 2) != 0) | oracle.silhouette_flags(osc, cam, fx, fy, np.where(hit_o, t, np.inf), hit_o, tol,
+                                                      SIL_OFFSET)
+    assert ok.all(), f"hit masks differ away from silhouettes at {list(zip(ii[~ok][:10], jj[~ok][:10]))}"
+    return int(ii.size)

@@ -103,6 +103,24 @@ def test_flatten_rejects_bad_parameters(field, value):
     assert e.value.code == st.ST_E_INVALID
 
 
+@pytest.mark.parametrize("kind", [sg.TORUS, sg.CYLINDER])
+@pytest.mark.parametrize("col,value", [(3, 0.0), (4, -0.2), (4, float("nan")), ("quat", 0.0)])
+def test_flatten_rejects_bad_torus_and_cylinder_parameters(kind, col, value):
+    """Radii (torus R and r; cylinder radius and half height) must be > 0 and
+    finite, the quaternion non-zero; a valid one flattens."""
+    sc = sg.tree_from_shape((0, 0), [sg.SUNION], kinds=(kind,))
+    st.prune_tree(sc.kind, sc.left, sc.right, sc.params, sc.root, [])
+    p = sc.params.copy()
+    leaf = sc.left[sc.root]
+    if col == "quat":
+        p[leaf, 5:9] = 0.0
+    else:
+        p[leaf, col] = value
+    with pytest.raises(st.StError) as e:
+        st.prune_tree(sc.kind, sc.left, sc.right, p, sc.root, [])
+    assert e.value.code == st.ST_E_INVALID
+
+
 def test_flatten_rejects_too_deep_tree():
     # left comb of 33 leaves: depth 32 > 31
     shape = 0

@@ -191,6 +191,13 @@ def _analytic_hit(sc, o, d):
             u, v = (-p[3 + j] - ol[j]) / dl[j], (p[3 + j] - ol[j]) / dl[j]
             lo, hi = max(lo, min(u, v)), min(hi, max(u, v))
         return lo if lo <= hi and lo >= 0 else math.inf
+    if k in (sg.TORUS, sg.CYLINDER):
+        # local frame of the primitive (axis of revolution = local y)
+        R = _quat_rot(p[5:9])
+        ol, dl = R.T @ (o - p[:3]), R.T @ d
+        if k == sg.TORUS:
+            return _ray_torus(ol, dl, p[3], p[4])
+        return _ray_cylinder(ol, dl, p[3], p[4])
     # capsule: caps and the cylinder body between the two end planes
     a, b, r = p[:3], p[3:6], p[6]
     best = min(sphere(a, r), sphere(b, r))
@@ -208,7 +215,52 @@ def _analytic_hit(sc, o, d):
     return best
 
 
-@pytest.mark.parametrize("kind", [sg.SPHERE, sg.BOX, sg.CAPSULE])
+def _ray_torus(o, d, R, r):
+    """Smallest t >= 0 with |x|^4 - 2(R^2 + r^2)|x|^2 + 4R^2 y^2 + (R^2 - r^2)^2 = 0
+    (the implicit torus around the y axis, x = o + t d, |d| = 1): roots of the
+    quartic, polished by Newton steps on the polynomial."""
+    A, B = o @ d, o @ o + R * R - r * r
+    # (t^2 + 2At + B)^2 - 4R^2((ox + t dx)^2 + (oz + t dz)^2)
+    a2 = d[0] ** 2 + d[2] ** 2
+    a1 = 2 * (o[0] * d[0] + o[2] * d[2])
+    a0 = o[0] ** 2 + o[2] ** 2
+    c = np.array([1.0, 4 * A, 4 * A * A + 2 * B - 4 * R * R * a2, 4 * A * B - 4 * R * R * a1, B * B - 4 * R * R * a0])
+    best = math.inf
+    for z in np.roots(c):
+        if abs(z.imag) > 1e-6:
+            continue
+        t = z.real
+        for _ in range(4):
+            f, df = np.polyval(c, t), np.polyval(np.polyder(c), t)
+            if df != 0:
+                t -= f / df
+        if t >= 0:
+            best = min(best, t)
+    return best
+
+
+def _ray_cylinder(o, d, rad, h):
+    """Smallest t >= 0 on a capped cylinder around the y axis: the side
+    (x^2 + z^2 = rad^2, |y| <= h) and the two cap discs (|y| = h, x^2 + z^2 <= rad^2)."""
+    best = math.inf
+    qa = d[0] ** 2 + d[2] ** 2
+    qb = o[0] * d[0] + o[2] * d[2]
+    qc = o[0] ** 2 + o[2] ** 2 - rad * rad
+    if qa > 0 and qb * qb - qa * qc >= 0:
+        for sgn in (-1.0, 1.0):
+            t = (-qb + sgn * math.sqrt(qb * qb - qa * qc)) / qa
+            if t >= 0 and abs(o[1] + t * d[1]) <= h:
+                best = min(best, t)
+    if d[1] != 0:
+        for y in (-h, h):
+            t = (y - o[1]) / d[1]
+            x, z = o[0] + t * d[0], o[2] + t * d[2]
+            if t >= 0 and x * x + z * z <= rad * rad:
+                best = min(best, t)
+    return best
+
+
+@pytest.mark.parametrize("kind", [sg.SPHERE, sg.BOX, sg.CAPSULE, sg.TORUS, sg.CYLINDER])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_first_root_matches_analytic_hit(kind, seed):
     sc = sg.single_primitive(kind, seed=seed, width=48, height=48)
@@ -262,7 +314,7 @@ def test_gradient_matches_central_differences(cfg_scene):
     assert np.mean(err < 1e-6) > 0.97
 
 
-@pytest.mark.parametrize("kind", [sg.SPHERE, sg.BOX, sg.CAPSULE])
+@pytest.mark.parametrize("kind", [sg.SPHERE, sg.BOX, sg.CAPSULE, sg.TORUS, sg.CYLINDER])
 def test_primitive_is_a_distance(kind):
     """Exact distances: |grad f| = 1 almost everywhere."""
     sc = sg.single_primitive(kind, seed=4)
@@ -270,6 +322,52 @@ def test_primitive_is_a_distance(kind):
     pts = np.random.default_rng(4).uniform(-1.5, 1.5, size=(2000, 3))
     _, g = o.eval(pts, grad=True)
     assert np.mean(np.abs(np.linalg.norm(g, axis=1) - 1) < 1e-9) > 0.99
+
+
+def _surface_samples(kind, p, n=200):
+    """Points on the surface of a torus or capped cylinder from its
+    parametrisation (local frame, axis of revolution y), in world space."""
+    th = np.linspace(0, 2 * np.pi, 4 * n, endpoint=False)
+    if kind == sg.TORUS:
+        ph = np.linspace(0, 2 * np.pi, n, endpoint=False)
+        T, P = np.meshgrid(th, ph)
+        ring = p[3] + p[4] * np.cos(P)
+        loc = np.stack([ring * np.cos(T), p[4] * np.sin(P), ring * np.sin(T)], -1).reshape(-1, 3)
+    else:
+        ys = np.linspace(-p[4], p[4], n)
+        T, Y = np.meshgrid(th, ys)
+        side = np.stack([p[3] * np.cos(T), Y, p[3] * np.sin(T)], -1).reshape(-1, 3)
+        rr = np.linspace(0, p[3], n // 2)
+        T2, RR = np.meshgrid(th, rr)
+        caps = [np.stack([RR * np.cos(T2), np.full_like(RR, y), RR * np.sin(T2)], -1).reshape(-1, 3)
+                for y in (-p[4], p[4])]
+        loc = np.concatenate([side] + caps)
+    return loc @ _quat_rot(p[5:9]).T + p[:3]
+
+
+@pytest.mark.parametrize("kind", [sg.TORUS, sg.CYLINDER])
+def test_torus_and_cylinder_values_are_distances_to_their_surface(kind):
+    """|f(x)| equals the distance from x to a dense sampling of the surface
+    (parametrisation, no distance formula), within the sampling spacing, and
+    f < 0 exactly where x is inside (local-frame membership test)."""
+    sc = sg.single_primitive(kind, seed=6)
+    o = oracle.OracleScene(sc)
+    p = sc.params[sc.root].astype(np.float64)
+    surf = _surface_samples(kind, p)
+    spacing = 2 * np.pi * (p[3] + p[4]) / 800 + 2 * p[4] / 200
+    rng = np.random.default_rng(11)
+    pts = p[:3] + rng.uniform(-1.2, 1.2, size=(300, 3)) * (p[3] + p[4])
+    f = o.eval(pts)
+    loc = (pts - p[:3]) @ _quat_rot(p[5:9])
+    rad = np.hypot(loc[:, 0], loc[:, 2])
+    if kind == sg.TORUS:
+        inside = (rad - p[3]) ** 2 + loc[:, 1] ** 2 < p[4] ** 2
+    else:
+        inside = (rad < p[3]) & (np.abs(loc[:, 1]) < p[4])
+    for x, v, ins in zip(pts, f, inside):
+        dmin = np.sqrt(((surf - x) ** 2).sum(1)).min()
+        assert abs(abs(v) - dmin) <= spacing, (v, dmin)
+        assert (v < 0) == ins
 
 
 def test_far_union_partner_changes_nothing():
@@ -365,6 +463,9 @@ def _voi_member(sc, i, d, x):
         return np.linalg.norm(x - p[:3]) <= p[3] + d
     if k == sg.BOX:
         return np.all(np.abs(_quat_rot(p[6:10]).T @ (x - p[:3])) <= p[3:6] + d)
+    if k in (sg.TORUS, sg.CYLINDER):
+        ext = np.array([p[3] + p[4], p[4], p[3] + p[4]]) if k == sg.TORUS else np.array([p[3], p[4], p[3]])
+        return np.all(np.abs(_quat_rot(p[5:9]).T @ (x - p[:3])) <= ext + d)
     a, b = p[:3], p[3:6]
     s = np.clip((x - a) @ (b - a) / ((b - a) @ (b - a)), 0, 1)
     return np.linalg.norm(x - a - s * (b - a)) <= p[6] + d
@@ -372,8 +473,9 @@ def _voi_member(sc, i, d, x):
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_volume_of_interest_contains_range_of_interest(seed):
-    """{x : f_i(x) <= d_i} lies inside VOI_i (the bound offset by d_i)."""
-    sc = sg.config2(seed)
+    """{x : f_i(x) <= d_i} lies inside VOI_i (the bound offset by d_i), for
+    every primitive type."""
+    sc = sg.config2_extended(seed)
     o = oracle.OracleScene(sc)
     rng = np.random.default_rng(seed)
     prims = o.prim_ids()
