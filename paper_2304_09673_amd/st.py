@@ -7,6 +7,7 @@ if the library is missing, loading fails loudly.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 from pathlib import Path
 
 import numpy as np
@@ -85,6 +86,49 @@ class StSceneInfo(C.Structure):
 
 _lib = None
 
+# st_allocator backed by PyTorch's caching allocator: the scene's device
+# buffers come from the same pool as the caller's tensors (allocated on the
+# stream the library call runs on; freed blocks return to the pool).
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class StAllocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+_torch = None          # set by lib(): torch, imported before the library
+_live_scenes = weakref.WeakSet()
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return _torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:
+        return None   # the library reports ST_E_NOMEM
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        if ptr:
+            _torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass   # the allocator is gone (process exit)
+
+
+def _close_live_scenes():
+    """At exit, before torch's own exit handlers: scenes still alive return
+    their buffers to the caching allocator while it exists."""
+    for s in list(_live_scenes):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
+# module-level: the callbacks must outlive every scene that holds them
+_TORCH_ALLOCATOR = StAllocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+
 
 def lib():
     global _lib
@@ -96,7 +140,12 @@ def lib():
         # (same soname).  Loaded the other way round, the process would hold
         # two HIP runtimes, and torch's streams and buffers would be foreign
         # to the library's.
-        import torch  # noqa: F401
+        import atexit
+        import torch
+        global _torch
+        _torch = torch
+        # registered after torch's own handlers, so it runs before them
+        atexit.register(_close_live_scenes)
         L = C.CDLL(str(LIB_PATH))
         vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
         L.st_status_str.restype = C.c_char_p
@@ -104,7 +153,7 @@ def lib():
         L.st_last_error.restype = C.c_char_p
         L.st_last_error.argtypes = []
         L.st_default_tuning.argtypes = [C.POINTER(StTuning)]
-        L.st_flatten_blobtree.argtypes = [C.POINTER(StNode), i32, i32, vp, vp, C.POINTER(vp)]
+        L.st_flatten_blobtree.argtypes = [C.POINTER(StNode), i32, i32, C.POINTER(StAllocator), vp, C.POINTER(vp)]
         L.st_scene_destroy.restype = None
         L.st_scene_destroy.argtypes = [vp]
         L.st_scene_get_info.argtypes = [vp, C.POINTER(StSceneInfo)]
@@ -195,13 +244,19 @@ def _stream_ptr(stream):
 class Scene:
     """A flattened blobtree on the GPU (st_flatten_blobtree)."""
 
-    def __init__(self, scene=None, *, kind=None, left=None, right=None, params=None, root=None, stream=None):
+    def __init__(self, scene=None, *, kind=None, left=None, right=None, params=None, root=None, stream=None,
+                 torch_allocator: bool = True):
+        """torch_allocator: the scene's device buffers come from PyTorch's caching
+        allocator (False: hipMalloc / hipFree inside the library)."""
         if scene is not None:
             kind, left, right, params, root = scene.kind, scene.left, scene.right, scene.params, scene.root
         self._nodes = nodes_from_arrays(kind, left, right, params)
         self.n = len(self._nodes)
         h = C.c_void_p()
-        _check(lib().st_flatten_blobtree(self._nodes, self.n, int(root), None, _stream_ptr(stream), C.byref(h)))
+        L = lib()
+        alloc = C.byref(_TORCH_ALLOCATOR) if torch_allocator else None
+        _check(L.st_flatten_blobtree(self._nodes, self.n, int(root), alloc, _stream_ptr(stream), C.byref(h)))
+        _live_scenes.add(self)
         self._h = h
         self._cam = None
 
