@@ -382,28 +382,6 @@ constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4 * kOrderThreads;
 constexpr int kOrderBatch = 8;
 
-// cnt[bk] += 1 for every active lane of the wave, one atomic per distinct
-// bucket (most tiles share a few small counts, and per-lane atomics on the
-// same LDS word serialise); returns the lane's old value plus its rank among
-// the lanes of its bucket.  Called by every lane of the wave.
-__device__ __forceinline__ uint32_t wave_bucket_add(uint32_t* cnt, uint32_t bk, bool active) {
-    const uint32_t lane = threadIdx.x & 63u;
-    uint32_t mine = 0;
-    uint64_t todo = __ballot(active);
-    while (todo) {
-        const int leader = __builtin_ctzll(todo);
-        const uint32_t b = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(bk, leader));
-        const uint64_t m = __ballot(bk == b) & todo;
-        uint32_t base = 0;
-        if (lane == uint32_t(leader)) base = atomicAdd(cnt + b, uint32_t(__popcll(m)));
-        base = __builtin_amdgcn_readlane(base, leader);
-        if ((m >> lane) & 1ull)
-            mine = base + __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-        todo &= ~m;
-    }
-    return mine;
-}
-
 __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_t* __restrict__ tile_cnt,
                                                                     int n_tiles, uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[kOrderBuckets];
@@ -422,7 +400,8 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
 #pragma unroll
         for (int k = 0; k < kOrderBatch; k++) bk[k] = bucket(t0 + k * kOrderThreads + tid);
 #pragma unroll
-        for (int k = 0; k < kOrderBatch; k++) wave_bucket_add(cnt, bk[k], t0 + k * kOrderThreads + tid < n_tiles);
+        for (int k = 0; k < kOrderBatch; k++)
+            if (t0 + k * kOrderThreads + tid < n_tiles) atomicAdd(&cnt[bk[k]], 1u);
     }
     __syncthreads();
     // exclusive scan: four buckets per thread, then an inclusive scan of the
@@ -447,14 +426,13 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
 #pragma unroll
         for (int k = 0; k < kOrderBatch; k++) {
             const int t = t0 + k * kOrderThreads + tid;
-            const uint32_t pos = wave_bucket_add(cnt, bk[k], t < n_tiles);
-            if (t < n_tiles) order[pos] = uint32_t(t);
+            if (t < n_tiles) order[atomicAdd(&cnt[bk[k]], 1u)] = uint32_t(t);
         }
     }
 }
 
-// per primitive (one wave): one candidate for every tile of its rectangle
-__global__ void __launch_bounds__(64) cand_count_kernel(const int4* __restrict__ trect, int tiles_x,
+// per primitive (one workgroup): one candidate for every tile of its rectangle
+__global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict__ trect, int tiles_x,
                                                          uint32_t* __restrict__ tile_count) {
     const int4 rc = trect[blockIdx.x];
     const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
@@ -464,7 +442,7 @@ __global__ void __launch_bounds__(64) cand_count_kernel(const int4* __restrict__
 }
 
 // per primitive (one workgroup): its index into a slot of each tile segment
-__global__ void __launch_bounds__(64) cand_scatter_kernel(const int4* __restrict__ trect, int tiles_x,
+__global__ void __launch_bounds__(256) cand_scatter_kernel(const int4* __restrict__ trect, int tiles_x,
                                                            const uint32_t* __restrict__ tile_off,
                                                            uint32_t* __restrict__ cursor,
                                                            uint32_t* __restrict__ slot_prim) {
@@ -922,24 +900,19 @@ __device__ bool wave_alive(uint32_t x, bool in, uint32_t* srt, uint32_t* tab, co
     return in && m > 0 && hfind(tab, kWavePruneBits, x, tab[hslot(x, kWavePruneBits)]);
 }
 
-// Pre-test pruning of the tiles with 1..64 candidates (the workgroup kernel
-// below takes the longer lists): same result as cand_prune_kernel.
-__global__ void __launch_bounds__(256) cand_prune_wave_kernel(
-        const uint32_t* __restrict__ tile_off, int n_tiles, int tiles_x, int ts, const uint32_t* __restrict__ prims,
-        const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim, uint32_t* __restrict__ tile_n,
-        const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
-        uint32_t n_nodes, uint32_t* __restrict__ tstat) {
-    __shared__ uint32_t srt[4][kWavePruneMax], tab[4][2 * kWavePruneMax];
-    const int w = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63u);
-    const int tile = int(blockIdx.x) * 4 + w;
-    if (tile >= n_tiles) return;   // whole waves
-    const uint32_t e0 = tile_off[tile];
-    const int n = int(tile_off[tile + 1] - e0);
-    if (n == 0 || n > kWavePruneMax) return;
+// Pre-test pruning of a tile with 1..64 candidates by one wave (the first
+// of its workgroup): same result as the workgroup path of cand_prune_kernel.
+// srt (64 words) and tab (128 words) are LDS scratch.
+__device__ void cand_prune_wave(int tile, uint32_t e0, int n, int tiles_x, int ts, const uint32_t* __restrict__ prims,
+                                const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim,
+                                uint32_t* __restrict__ tile_n, const uint32_t* __restrict__ rmq,
+                                const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes,
+                                uint32_t* __restrict__ tstat, uint32_t* srt, uint32_t* tab) {
+    const int lane = int(threadIdx.x & 63u);
     const bool in = lane < n;
     const uint32_t p = in ? slot_prim[e0 + lane] : 0u;
     const uint32_t x = in ? prims[p] : 0u;
-    const bool keep = wave_alive(x, in, srt[w], tab[w], rmq, kslot, kill, n_nodes);
+    const bool keep = wave_alive(x, in, srt, tab, rmq, kslot, kill, n_nodes);
     const uint64_t km = __ballot(keep);
     if (keep) slot_prim[e0 + lanes_below_mask(km)] = p;   // every lane read its slot above
     const int kept = __popcll(km);
@@ -962,26 +935,22 @@ __global__ void __launch_bounds__(256) cand_prune_wave_kernel(
     }
 }
 
-// Post-test pruning of the tiles with 1..64 tested candidates: same result as
-// tile_prune_kernel (entries that hit and survive, compacted in order).
-__global__ void __launch_bounds__(256) tile_prune_wave_kernel(
-        const uint32_t* __restrict__ tile_off, int n_tiles, uint32_t* e_node, float* e_zin, float* e_zout,
-        uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot,
-        const uint32_t* __restrict__ kill, uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
-    __shared__ uint32_t srt[4][kWavePruneMax], tab[4][2 * kWavePruneMax];
-    const int w = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63u);
-    const int tile = int(blockIdx.x) * 4 + w;
-    if (tile >= n_tiles) return;
-    const uint32_t e0 = tile_off[tile];
-    const int n = int(tile_cnt[tile]);
-    if (n == 0 || n > kWavePruneMax) return;
+// Post-test pruning of a tile with 1..64 tested candidates by one wave (the
+// first of its workgroup): same result as prune_tile (entries that hit and
+// survive, compacted in order).  srt (64 words) and tab (128 words) are LDS
+// scratch.
+__device__ void tile_prune_wave(int tile, uint32_t e0, int n, uint32_t* e_node, float* e_zin, float* e_zout,
+                                uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ rmq,
+                                const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes,
+                                int keep_all, uint32_t* __restrict__ tstat, uint32_t* srt, uint32_t* tab) {
+    const int lane = int(threadIdx.x & 63u);
     const bool in = lane < n;
     const uint32_t x = in ? e_node[e0 + lane] : 0u;
     const float zi = in ? e_zin[e0 + lane] : 0.f, zo = in ? e_zout[e0 + lane] : 0.f;
     const bool hit = in && zi <= zo;
     bool keep = hit;
     if (!keep_all) {   // uniform: every lane of the wave takes part in wave_alive
-        const bool alive = wave_alive(x, hit, srt[w], tab[w], rmq, kslot, kill, n_nodes);
+        const bool alive = wave_alive(x, hit, srt, tab, rmq, kslot, kill, n_nodes);
         keep = hit && alive;
     }
     const uint64_t km = __ballot(keep);
@@ -1009,7 +978,12 @@ __global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
     const int tid = int(threadIdx.x);
     const uint32_t e0 = tile_off[tile];
     const int n = int(tile_off[tile + 1] - e0);
-    if (!keep_all && n >= 1 && n <= kWavePruneMax) return;   // cand_prune_wave_kernel's tile
+    if (!keep_all && n >= 1 && n <= kWavePruneMax) {   // a short list: one wave, no barrier
+        if (tid < 64)
+            cand_prune_wave(tile, e0, n, tiles_x, ts, prims, rect, voi, slot_prim, tile_n, rmq, kslot, kill, n_nodes,
+                            tstat, a, tab);
+        return;
+    }
     if (n == 0 || n > kPruneLdsCap || keep_all) {
         if (tid == 0) tile_n[tile] = uint32_t(n);
         if (n) add_tested(slot_prim, e0, n, tile, tiles_x, ts, rect, voi, tstat);
@@ -1058,7 +1032,13 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
     const uint32_t e0 = tile_off[tile];
     const int n = int(tile_cnt[tile]);   // tested candidates of the segment
     __syncthreads();                     // every thread has read it before thread 0 rewrites it
-    if (n == 0 || n <= kWavePruneMax) return;   // empty, or pruned by tile_prune_wave_kernel
+    if (n == 0) return;
+    if (n <= kWavePruneMax) {   // a short list: one wave, no barrier
+        if (threadIdx.x < 64)
+            tile_prune_wave(tile, e0, n, e_node, e_zin, e_zout, tile_cnt, rmq, kslot, kill, n_nodes, keep_all, tstat,
+                            a, tab);
+        return;
+    }
     if (n > kPruneLdsCap) {
         if (threadIdx.x == 0) long_list[atomicAdd(misc + 5, 1u)] = uint32_t(tile);
         return;
@@ -1345,7 +1325,7 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
                        s->d_oside, s->d_sub, t.keep_all_entries, rect, trect);
     // one wave per primitive: a rectangle covers about 60 tiles on the 1080p
     // frame, so wider workgroups would mostly idle
-    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(64), 0, stream, trect, s->tiles_x, tcnt);
+    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, trect, s->tiles_x, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_cand = replay ? s->n_cand : 0u;
     if (!replay) {
@@ -1371,14 +1351,10 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
         s->ab_cap = cap;
     }
     if (P && n_cand)
-        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(64), 0, stream, trect, s->tiles_x, s->d_tile_off,
+        hipLaunchKernelGGL(cand_scatter_kernel, dim3(P), dim3(256), 0, stream, trect, s->tiles_x, s->d_tile_off,
                            cur, s->d_e_node);
     // candidates dead for their tile's candidate set: dropped before the test
     // (d_tile_cnt: candidates left per tile)
-    if (!t.keep_all_entries)
-        hipLaunchKernelGGL(cand_prune_wave_kernel, dim3((T + 3) / 4), dim3(256), 0, stream, s->d_tile_off, T,
-                           s->tiles_x, ts, s->d_prims, rect, s->d_voi, s->d_e_node, s->d_tile_cnt, s->d_rmq,
-                           reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes), tstat);
     hipLaunchKernelGGL(cand_prune_kernel, dim3(T), dim3(kPruneThreads), 0, stream, s->d_tile_off, T, s->tiles_x, ts,
                        s->d_prims, rect, s->d_voi, s->d_e_node, s->d_tile_cnt, s->d_rmq,
                        reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
@@ -1425,9 +1401,6 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     }
     char* lbuf = (char*)s->d_long;
     // tile-level pruning (long lists: the kernel reads their count on the device)
-    hipLaunchKernelGGL(tile_prune_wave_kernel, dim3((T + 3) / 4), dim3(256), 0, stream, s->d_tile_off, T, s->d_e_node,
-                       s->d_e_zin, s->d_e_zout, s->d_tile_cnt, s->d_rmq, reinterpret_cast<const uint4*>(s->d_kslot),
-                       s->d_kill, uint32_t(s->n_nodes), t.keep_all_entries, tstat);
     hipLaunchKernelGGL(tile_prune_kernel, dim3(T), dim3(kPruneThreads), 0, stream, s->d_tile_off, T, s->d_e_node,
                        s->d_e_zin, s->d_e_zout, s->d_tile_cnt, longl, misc, s->d_rmq,
                        reinterpret_cast<const uint4*>(s->d_kslot), s->d_kill, uint32_t(s->n_nodes),
