@@ -567,7 +567,8 @@ __device__ void dump_samples(const TraceArgs& A, const uint32_t* view, int len, 
 // the block's record (one coalesced write, no atomics: thousands of blocks
 // adding into the same few words serialise in the L2 and were the largest
 // cost of a frame); the records are summed by a separate kernel when the
-// caller asks for statistics.  Without one, lane 0 adds them atomically.
+// caller asks for statistics.  Without one, lane 0 adds them atomically;
+// with neither (a trace without statistics) nothing is written.
 __device__ void block_counters(const TraceArgs& A, unsigned long long* cnt, uint32_t job,
                                const unsigned long long (&v)[kWaveStats]) {
     const int lane = lane_id();
@@ -576,7 +577,7 @@ __device__ void block_counters(const TraceArgs& A, unsigned long long* cnt, uint
 #pragma unroll
         for (int c = 0; c < kWaveStats; c++) mine = lane == c ? v[c] : mine;
         if (lane < kWaveStats) A.wrec[size_t(job) * kWaveStats + size_t(lane)] = mine;
-    } else if (lane == 0) {
+    } else if (cnt != nullptr && lane == 0) {
         for (int c = 0; c < S_COUNT; c++) {
             if (c == S_MAXACT) atomicMax(cnt + c, v[c]);
             else if (v[c]) atomicAdd(cnt + c, v[c]);

@@ -230,6 +230,12 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
             slots = reinterpret_cast<uint32_t*>(s->d_slots);
         }
     }
+    // a trace without statistics writes no counters (6 MB of records per
+    // 1080p frame otherwise)
+    if (!want_stats && !dump) {
+        A.wrec = nullptr;
+        A.stats = nullptr;
+    }
     // every size is checked: launch from here on (the counter reduction
     // overwrites every counter it reports, so the stats words need no clear)
     hipError_t e = hipSuccess;
