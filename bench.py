@@ -44,8 +44,9 @@ FLOPS_TEST = {"sphere": 25, "box": 38, "capsule": 96}
 # only while the kernel's sources hash to what was measured.
 TRAFFIC = {
     "trace": (ROOT / "profiles" / "trace_c3_traffic.md",
-              ["trace.hip", "st_trace.h", "st_field.h", "st_prune.h", "st_common.h", "st_mlp.h"]),
-    "tile_test": (ROOT / "profiles" / "tile_test_c3_traffic.md", ["binning.hip", "st_common.h", "st_internal.h"]),
+              ["trace.hip", "st_trace.h", "st_field.h", "st_internal.h", "st_prune.h", "st_common.h", "st_mlp.h"]),
+    "tile_test": (ROOT / "profiles" / "tile_test_c3_traffic.md",
+                  ["binning.hip", "st_internal.h", "st_prune.h", "st_voi.h", "st_common.h"]),
 }
 
 
@@ -94,19 +95,56 @@ def algorithmic_flops(stats) -> float:
             + ne[3] * FLOPS_OP_SHARP + stats.get("smooth_evals", 0) * SMOOTH_EXTRA)
 
 
-def cpu_baseline(sc, n_rays: int, seed: int = 1234):
+def _oracle_rate(config: int, seed: int, n_rays: int, sample_seed: int):
+    """Oracle Mrays/s on n_rays seeded random pixels of a workload's frame (this process's threads)."""
     import oracle
+    import scenegen as sg
     oracle.build(force=False)
+    sc = sg.by_config(config, seed=seed)
     osc = oracle.OracleScene(sc)
-    rng = np.random.default_rng(seed)
+    rng = np.random.default_rng(sample_seed)
     px = rng.integers(0, sc.camera.width, n_rays) + 0.5
     py = rng.integers(0, sc.camera.height, n_rays) + 0.5
     t0 = time.perf_counter()
     _, _, flag, ev = osc.trace(sc.camera, px, py)
     dt = time.perf_counter() - t0
-    return {"value": n_rays / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n_rays} seeded random pixels of the same 1920x1080 frame, full-tree FP64 first-root "
-                      f"tracing (no pruning, no A-buffer); {dt:.1f} s, {int(ev.sum())} full-tree evaluations"}
+    return {"mrays_s": n_rays / dt / 1e6, "seconds": dt, "evals": int(ev.sum()), "threads": oracle.num_threads()}
+
+
+def cpu_model() -> str:
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sc, config: int, seed: int, n_rays: int, n_rays_1core: int = 1024):
+    """The oracle on the host's cores and, in a child process, on one core."""
+    r = _oracle_rate(config, seed, n_rays, 1234)
+    one = None
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    import subprocess
+    code = (f"import sys, json; sys.path.insert(0, {str(ROOT)!r}); import bench; "
+            f"print(json.dumps(bench._oracle_rate({config}, {seed}, {n_rays_1core}, 4321)))")
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        if res.returncode == 0:
+            one = json.loads(res.stdout.strip().splitlines()[-1])
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        one = None
+    out = {"value": r["mrays_s"], "unit": "Mrays/s", "cores": r["threads"], "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"{n_rays} seeded random pixels of the same {sc.camera.width}x{sc.camera.height} frame, "
+                     f"full-tree FP64 first-root tracing (no pruning, no A-buffer); {r['seconds']:.1f} s, "
+                     f"{r['evals']} full-tree evaluations"}
+    if one is not None:
+        out["single_core"] = {"value": one["mrays_s"], "unit": "Mrays/s", "cores": one["threads"],
+                              "sample": f"{n_rays_1core} other seeded random pixels of the same frame; "
+                                        f"{one['seconds']:.1f} s"}
+    return out
 
 
 def bench_batch(args):
@@ -254,6 +292,112 @@ def learned_vs_plain(args):
             **out}
 
 
+def _wall_ms(fn, reps):
+    """Median wall time of fn() over reps calls, each ended by a device synchronization."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts))
+
+
+def dense_and_ablation(args):
+    """The second workload (142 primitives, mixed compact operators) at
+    1024x1024 with 16x16 tiles, where about a third of the pixels hit: the
+    synchronized frame with the trace kernel's roofline on a frame whose
+    field evaluations are dense, and the paper's Table 1 ablation on the same
+    frame: ParentPtr/Full and FastPtr/Full (A-buffer of 8x8 tiles with every
+    entry kept, per-pixel dexel buffer, every ray traced on its own with the
+    field evaluated by Algorithm 1 over parent or fast ancestor pointers).
+    Frame times are wall times of build + trace with a synchronization."""
+    import torch
+    import scenegen as sg
+    from paper_2304_09673_amd import st
+
+    sc = sg.config2(0)
+    cam = sc.camera
+    rays = cam.width * cam.height
+    depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda")
+    normal = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda")
+    progress("dense frame: synchronized")
+    s = st.Scene(sc)
+    tune = st.default_tuning(tile=16)
+    s.build_abuffer(cam, tune)
+    _, _, stats = s.trace(cam, depth, normal)
+    tr = []
+    for _ in range(args.c5_reps + 2):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        s.trace(cam, depth, normal, stats=False)
+        b.record()
+        torch.cuda.synchronize()
+        tr.append(a.elapsed_time(b))
+    trace_ms = float(np.median(tr))
+    frame_ms = _wall_ms(lambda: (s.build_abuffer(cam, tune), s.trace(cam, depth, normal, stats=False)),
+                        args.c5_reps + 2)
+    flops = algorithmic_flops(stats)
+    out = {"workload": f"{sc.name}: 142 primitives, random tree depth<=10, compact smooth union/intersection/"
+                       f"difference 60/20/20%, {cam.width}x{cam.height}, 16x16 tiles, plain sphere tracing",
+           "synchronized": {"frame_ms": round(frame_ms, 3), "mrays_s": round(rays / frame_ms / 1e3, 2),
+                            "trace_ms": round(trace_ms, 3), "hits": stats["hits"],
+                            "evals_per_ray": stats["field_evals"] / rays,
+                            "field_evals_per_s": stats["field_evals"] / (trace_ms * 1e-3)},
+           "trace_roofline": {"bound": "alu", "kernel": "trace (trace_fast_kernel + trace_wide_kernel)",
+                              "achieved": flops / (trace_ms * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12,
+                              "unit": "TFLOP/s", "frac": flops / (trace_ms * 1e-3) / PEAK_FP32,
+                              "frac_nonpacked": flops / (trace_ms * 1e-3) / PEAK_FP32_NONPACKED,
+                              "flops_per_launch": flops, "launch_ms": trace_ms, "traffic": None}}
+    s.close()
+    s = st.Scene(sc)
+    full = st.default_tuning(tile=8, keep_all_entries=1)
+    for name, variant in (("parent_ptr_full", st.ST_ABLATION_PARENT_PTR), ("fast_ptr_full", st.ST_ABLATION_FAST_PTR)):
+        progress(f"dense frame: ablation {name}")
+        s.build_abuffer(cam, full)
+        _, _, ast = s.trace_ablation(variant, cam, depth, normal)
+        ms = _wall_ms(lambda: (s.build_abuffer(cam, full), s.trace_ablation(variant, cam, depth, normal, stats=False)),
+                      args.c5_reps)
+        out[name] = {"frame_ms": round(ms, 3), "mrays_s": round(rays / ms / 1e3, 2),
+                     "dexel_entries": ast["abuffer_entries"], "evals_per_ray": ast["field_evals"] / rays,
+                     "operators_visited": ast["view_nodes"], "hits": ast["hits"],
+                     "slowdown_vs_synchronized": round(ms / frame_ms, 2)}
+    s.close()
+    return out
+
+
+def segment_vs_plain(sc, tune, reps):
+    """Plain and segment tracing of the same frame and A-buffer tuning
+    (trace-only device time, median of reps)."""
+    import torch
+    from paper_2304_09673_amd import st
+    cam = sc.camera
+    rays = cam.width * cam.height
+    out = {}
+    for name, mode in (("plain", st.ST_STEP_PLAIN), ("segment", st.ST_STEP_SEGMENT)):
+        s = st.Scene(sc)
+        t = st.default_tuning(tile=tune.tile, max_new=tune.max_new, sub_depth=tune.sub_depth, step_mode=mode)
+        s.build_abuffer(cam, t)
+        _, _, stats = s.trace()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            s.trace(stats=False)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        ms = float(np.median(ts))
+        out[name] = {"trace_ms": round(ms, 4), "trace_only_mrays_s": round(rays / ms / 1e3, 2),
+                     "steps_per_ray": stats["steps"] / rays, "evals_per_ray": stats["field_evals"] / rays}
+        s.close()
+    out["speedup"] = round(out["plain"]["trace_ms"] / out["segment"]["trace_ms"], 4)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,7 +414,11 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--n-scenes", type=int, default=64)
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-vs-plain comparison")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the 1024x1024 second-workload frame (dense roofline, ablation variants)")
     ap.add_argument("--c5-reps", type=int, default=3)
+    ap.add_argument("--frames-in-flight", type=int, default=2,
+                    help="frames rendered concurrently (one scene, output pair and stream each)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design (screen tiles sharded "
@@ -308,40 +456,69 @@ def main():
         # cap and fetch-ahead depth with device timing
         tune, _ = scene.autotune(cam, reps=3)
         tuned = "autotuned"
-    depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda")
-    normal = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda")
+    F = max(1, args.frames_in_flight)
+    # F frames in flight: one scene (its own A-buffer), output pair and
+    # stream per slot; frame k runs on slot k mod F, so frame k+1's build
+    # overlaps frame k's trace.  Streams keep the default priority.
+    scenes = [scene] + [st.Scene(sc) for _ in range(F - 1)]
+    streams = [stream] + [torch.cuda.Stream() for _ in range(F - 1)]
+    outs = [(torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda"),
+             torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda")) for _ in range(F)]
+    depth, normal = outs[0]
 
-    def step(stats=False, ev=None):
-        scene.build_abuffer(cam, tune)
+    def step(slot=0, stats=False, ev=None):
+        sc_, st_ = scenes[slot], streams[slot]
+        sc_.build_abuffer(cam, tune, stream=st_)
         if ev is not None:
-            ev[0].record(stream)
-        out = scene.trace(cam, depth, normal, stats=stats)
+            ev[0].record(st_)
+        out = sc_.trace(cam, *outs[slot], stats=stats, stream=st_)
         if ev is not None:
-            ev[1].record(stream)
+            ev[1].record(st_)
         return out[2]
 
     for _ in range(args.warmup):
-        step()
+        for i in range(F):
+            step(i)
     torch.cuda.synchronize()
     stats = step(stats=True)
     torch.cuda.synchronize()
 
+    # one frame at a time on one stream (per-frame latency, build and trace
+    # split); not the reported value when F > 1
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(0, ev=evs[k])
+    torch.cuda.synchronize()
+    serial_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    serial_trace_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    build_ms = serial_ms - serial_trace_ms
+
+    # the timed region: exactly `steps` frames, F in flight
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     # the library records a HIP event pair around every tile-test launch, on
     # the build stream
-    scene.kernel_timing(True)
+    for s_ in scenes:
+        s_.kernel_timing(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(ev=evs[k])
+        step(k % F, ev=evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    test_total_ms, test_launches = scene.kernel_timing(False)
+    test_total_ms, test_launches = 0.0, 0
+    for s_ in scenes:
+        a, b = s_.kernel_timing(False)
+        test_total_ms += a
+        test_launches += b
     test_ms_avg = test_total_ms / max(test_launches, 1)
     ms_per_step = wall / args.steps * 1e3
     trace_ms = [a.elapsed_time(b) for a, b in evs]
     trace_ms_avg = float(np.mean(trace_ms))
-    build_ms = ms_per_step - trace_ms_avg
+    # every slot renders the same image
+    for d_, n_ in outs[1:]:
+        assert torch.equal(d_, depth) and torch.equal(n_, normal), "frames in flight differ"
 
     rays = cam.width * cam.height
     value = rays / (ms_per_step * 1e-3) / 1e6
@@ -382,9 +559,14 @@ def main():
                                f"union/intersection/difference 60/20/20%, {cam.width}x{cam.height}, "
                                f"plain sphere tracing",
                    "rays": rays, "tuning": {"source": tuned, "tile": tune.tile, "max_new": tune.max_new,
-                                            "sub_depth": round(tune.sub_depth, 4), "eps": tune.eps}},
+                                            "sub_depth": round(tune.sub_depth, 4), "eps": tune.eps},
+                   "frames_in_flight": F},
         "field_evals_per_s": evals_per_s,
         "trace_ms": round(trace_ms_avg, 4),
+        "serial": {"note": "one frame at a time on one stream: build (replayed, no host synchronization) "
+                           "then trace; ms_per_frame is the frame's latency",
+                   "ms_per_frame": round(serial_ms, 4), "mrays_s": round(rays / (serial_ms * 1e-3) / 1e6, 3),
+                   "trace_ms": round(serial_trace_ms, 4), "build_ms": round(build_ms, 4)},
         "build_ms": round(build_ms, 4),
         "flatten_ms": round(flatten_ms, 3),
         "trace_only_mrays_s": round(rays / (trace_ms_avg * 1e-3) / 1e6, 3),
@@ -419,13 +601,19 @@ def main():
     line["binning"] = {"bound": "hbm", "algorithmic_bytes": bin_bytes, "ms_wall": round(build_ms, 4),
                        "achieved_GBps": bin_bytes / (build_ms * 1e-3) / 1e9,
                        "frac": bin_bytes / (build_ms * 1e-3) / 8e12,
-                       "note": "wall time of st_build_abuffer (includes its two host synchronizations)"}
+                       "note": "serial frame wall time minus the trace's device time: the build replayed "
+                               "with the sizes of the valid A-buffer (no host synchronization), launch gaps "
+                               "included"}
     progress(f"frame: {value:.1f} Mrays/s")
+    progress("segment tracing on the same frame")
+    line["segment_vs_plain"] = segment_vs_plain(sc, tune, 5)
+    if not args.no_dense:
+        line["dense_frame"] = dense_and_ablation(args)
     if not args.no_c5:
         line["learned_vs_plain"] = learned_vs_plain(args)
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_rays)
+        line["cpu_baseline"] = cpu_baseline(sc, args.config, args.seed, args.cpu_rays)
     print(json.dumps(line), flush=True)
 
 
