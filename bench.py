@@ -417,7 +417,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the 1024x1024 second-workload frame (dense roofline, ablation variants)")
     ap.add_argument("--c5-reps", type=int, default=3)
-    ap.add_argument("--frames-in-flight", type=int, default=2,
+    ap.add_argument("--frames-in-flight", type=int, default=3,
                     help="frames rendered concurrently (one scene, output pair and stream each)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
