@@ -405,6 +405,24 @@ st_status st_mlp_grad(const float *weights, const float *norm, const float *x, c
 st_status st_mlp_adam(float *w, float *m, float *v, const float *grad, int32_t n, int32_t step, float lr,
                       float beta1, float beta2, float eps, void *stream);
 
+/* Trains the step model on dumped samples (st_trace_dump) entirely on the
+ * device: the feature standardisation (mean and 1 / max(std, 1e-6) per
+ * feature, FP64 sums) into norm[16], initial weights from seed (He normal
+ * hidden layers, small output layer, omega near 1.5 at the start), one
+ * seeded order of the samples, then `epochs` passes of Adam (lr, betas 0.9 /
+ * 0.999, eps 1e-8) over the full batches of `batch` samples, on the loss and
+ * gradient of st_mlp_grad (the weight-gradient sums on the matrix cores).
+ *   x (device float[n][8]) raw features, target (device float[n]) omega*;
+ *   weights (device float[ST_MLP_PARAMS]) and norm (device float[16]) are
+ *   outputs; losses (host float[epochs], may be NULL) gets each epoch's mean
+ *   batch loss.  Blocks until done; allocates and frees its temporaries.
+ * Not in the paper (the learned step is this library's addition).
+ * Errors: ST_E_INVALID (NULL, n < 1 or > 2^31 - 1, epochs or batch < 1,
+ * lr or over_weight <= 0), ST_E_NOMEM, ST_E_DEVICE. */
+st_status st_train_step_model(const float *x, const float *target, int64_t n, int32_t epochs, int32_t batch,
+                              float lr, float over_weight, uint64_t seed, float *weights, float *norm,
+                              float *losses, void *stream);
+
 /* Install a step model in the scene (weights and norm: device; packed into a
  * table the scene owns).  Required before tracing with ST_STEP_LEARNED.
  * Errors: ST_E_INVALID, ST_E_NOMEM, ST_E_DEVICE. */

@@ -27,7 +27,7 @@ EXPORTS = (
     "st_debug_abuffer", "st_mlp_pack", "st_mlp_forward", "st_mlp_grad", "st_mlp_adam", "st_set_step_model",
     "st_trace_dump", "st_debug_mfma_probe", "st_batch_create", "st_batch_render", "st_batch_stats",
     "st_batch_destroy", "st_batch_autotune", "st_trace_batch", "st_update_primitives", "st_debug_kernel_timing",
-    "st_trace_noalloc", "st_debug_sparse_traversal", "st_trace_ablation",
+    "st_trace_noalloc", "st_debug_sparse_traversal", "st_trace_ablation", "st_train_step_model",
 )
 
 MLP_PARAMS = 1377
@@ -172,6 +172,7 @@ def lib():
         L.st_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
         L.st_mlp_grad.argtypes = [vp, vp, vp, vp, i32, C.c_float, vp, vp, vp]
         L.st_mlp_adam.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.st_train_step_model.argtypes = [vp, vp, i64, i32, i32, C.c_float, C.c_float, C.c_uint64, vp, vp, vp, vp]
         L.st_set_step_model.argtypes = [vp, vp, vp, vp]
         L.st_trace_dump.argtypes = [vp, C.POINTER(StCamera), vp, vp, vp, vp, i64, C.POINTER(i64), vp]
         L.st_debug_mfma_probe.argtypes = [vp, vp, vp, vp]
@@ -473,6 +474,22 @@ def mlp_adam(w, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, str
         _f32_cuda(t, n)
     _check(lib().st_mlp_adam(_ptr(w), _ptr(m), _ptr(v), _ptr(grad), n, int(step), float(lr), float(beta1),
                              float(beta2), float(eps), _stream_ptr(stream)))
+
+
+def train_step_model(x, target, epochs=8, batch=8192, lr=3e-3, over_weight=4.0, seed=0, stream=None):
+    """st_train_step_model on float32 CUDA tensors x [n, 8] and target [n];
+    returns (weights [1377], norm [16] CUDA tensors, losses per epoch)."""
+    import torch
+    n = target.numel()
+    _f32_cuda(x, 8 * n)
+    _f32_cuda(target, n)
+    w = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    norm = torch.empty(16, dtype=torch.float32, device="cuda")
+    losses = np.zeros(int(epochs), dtype=np.float32)
+    _check(lib().st_train_step_model(_ptr(x), _ptr(target), int(n), int(epochs), int(batch), float(lr),
+                                     float(over_weight), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(w), _ptr(norm),
+                                     losses.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
+    return w, norm, losses.astype(np.float64).tolist()
 
 
 def debug_mfma_probe(a, b, stream=None):

@@ -469,3 +469,18 @@ def test_golden_single_operator_views():
             names = {0: "A", 1: "B", 2: "op"}
             got = [names[int(v)] for v in view] or ["-"]
             assert got == expect, (cls, k, active, got, expect)
+
+
+def test_train_step_model_refuses_bad_arguments():
+    """Argument checks of st_train_step_model come before any device work."""
+    import ctypes as C
+    L = st.lib()
+    buf = (C.c_float * 16)()
+    p = C.cast(buf, C.c_void_p)
+    ok = dict(x=p, t=p, n=10, epochs=1, batch=4, lr=1e-3, over=4.0, w=p, norm=p)
+    for bad in (dict(x=None), dict(t=None), dict(w=None), dict(norm=None), dict(n=0), dict(n=1 << 31),
+                dict(epochs=0), dict(batch=0), dict(lr=0.0), dict(lr=float("nan")), dict(over=0.0)):
+        a = {**ok, **bad}
+        r = L.st_train_step_model(a["x"], a["t"], a["n"], a["epochs"], a["batch"], a["lr"], a["over"], 0,
+                                  a["w"], a["norm"], None, None)
+        assert r == st.ST_E_INVALID, bad

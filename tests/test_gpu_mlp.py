@@ -154,3 +154,26 @@ def test_training_reduces_loss():
     t = (1.0 + 3.0 / (1.0 + np.exp(-(1.5 * x[:, 0] - x[:, 3])))).astype(np.float32)
     w, norm, losses = stepmodel.fit(x, t, epochs=12, batch=4096, lr=1e-2, seed=1)
     assert losses[-1] < 0.2 * losses[0], losses
+
+
+def test_train_step_model_standardisation_and_loss():
+    """st_train_step_model: the standardisation equals the FP64 host one, the
+    trained model's loss (recomputed by st_mlp_grad) is below that of the
+    initial model, the reported epoch losses fall, and a batch larger than
+    the sample count trains on one batch."""
+    import torch
+    st = _st()
+    from paper_2304_09673_amd import stepmodel
+    rng = np.random.default_rng(5)
+    n = 20000
+    x = (rng.normal(0, 1, (n, 8)) * np.array([0.1, 1, 0.01, 3, 0.5, 2, 1.5, 2])
+         + np.array([0.05, 0.9, 0.01, 4, -0.3, 3, 3.0, 2])).astype(np.float32)
+    t = (1.0 + 3.0 / (1.0 + np.exp(-(1.5 * (x[:, 1] - 0.9) - (x[:, 3] - 4) / 3)))).astype(np.float32)
+    xd, td = torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda()
+    w, norm, losses = st.train_step_model(xd, td, epochs=6, batch=2048, lr=1e-2, seed=3)
+    np.testing.assert_allclose(norm.cpu().numpy(), stepmodel.standardisation(x), rtol=1e-5)
+    assert len(losses) == 6 and losses[-1] < 0.5 * losses[0], losses
+    _, l_end = st.mlp_grad(w, norm, xd, td)
+    assert float(l_end.cpu()) < losses[0]
+    w1, _, l1 = st.train_step_model(xd[:100], td[:100], epochs=2, batch=4096, lr=1e-2, seed=3)
+    assert len(l1) == 2 and np.isfinite(w1.cpu().numpy()).all()
