@@ -205,6 +205,83 @@ def bench_batch(args):
     b.close()
 
 
+def bench_batch_streams(args):
+    """The 64-scene batch without the persistent batch kernel (switched off):
+    every scene's A-buffer build (replayed) and trace per frame, the scenes
+    spread round-robin over `frames_in_flight` streams so that their
+    latency-bound kernels run side by side; the same frame on one stream is
+    reported beside it."""
+    import torch
+    import scenegen as sg
+    from paper_2304_09673_amd import st
+
+    scs = sg.config4(args.n_scenes)
+    F = max(1, args.frames_in_flight)
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(F - 1)]
+    tune = st.default_tuning(tile=args.tile, max_new=args.max_new, sub_depth=args.sub_depth)
+    scenes, outs = [], []
+    for sc in scs:
+        cam = sc.camera
+        scenes.append(st.Scene(sc))
+        outs.append((torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda"),
+                     torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda")))
+
+    def frame(nstreams, stats=False):
+        res = []
+        for i, (sc, s_) in enumerate(zip(scs, scenes)):
+            stv = streams[i % nstreams]
+            s_.build_abuffer(sc.camera, tune, stream=stv)
+            res.append(s_.trace(sc.camera, *outs[i], stats=stats, stream=stv)[2])
+        return res
+
+    progress(f"batch of {len(scs)} scenes: sizing builds")
+    stats = frame(1, stats=True)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        frame(F)
+    torch.cuda.synchronize()
+    ref = [o[0].clone() for o in outs]
+
+    def timed(nstreams):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            frame(nstreams)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps * 1e3
+
+    ms_serial = timed(1)
+    ms = timed(F)
+    for o, r in zip(outs, ref):
+        assert torch.equal(o[0], r), "batch frames differ"
+    rays = sum(sc.camera.width * sc.camera.height for sc in scs)
+    evals = sum(x["field_evals"] for x in stats)
+    flops = sum(algorithmic_flops(x) for x in stats)
+    line = {
+        "metric": "Mrays/s + field evals/s at 1080p, 4096 prims; learned vs plain step at equal depth err",
+        "value": round(rays / (ms * 1e-3) / 1e6, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch of {len(scs)} scenes (primitives log-uniform in [32, 8192], resolutions "
+                               f"from 256x256 to 1920x1080), every scene built and traced per frame, plain sphere "
+                               f"tracing; scenes round-robin over {F} streams (the persistent batch kernel is "
+                               f"switched off)",
+                   "rays": rays, "streams": F,
+                   "tuning": {"source": "fixed", "tile": tune.tile, "max_new": tune.max_new,
+                              "sub_depth": round(tune.sub_depth, 4)}},
+        "serial": {"ms_per_frame": round(ms_serial, 4), "mrays_s": round(rays / (ms_serial * 1e-3) / 1e6, 3)},
+        "field_evals_per_s": evals / (ms * 1e-3),
+        "frame_roofline": {"bound": "alu", "note": "algorithmic FLOPs of all traces of a frame over the frame's "
+                                                   "wall time (not one kernel's launch)",
+                           "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                           "frac": flops / (ms * 1e-3) / PEAK_FP32},
+    }
+    print(json.dumps(line), flush=True)
+    for s_ in scenes:
+        s_.close()
+
+
 def progress(msg: str):
     """Progress on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -433,8 +510,8 @@ def main():
         try:
             bench_batch(args)
         except Exception as exc:   # the batch entry points refuse while switched off
-            print(f"bench.py: batch workload unavailable: {exc}", file=sys.stderr)
-            sys.exit(2)
+            progress(f"persistent batch unavailable ({exc}); scenes on streams instead")
+            bench_batch_streams(args)
         return
 
     import torch
