@@ -140,7 +140,7 @@ struct EvalF {
     __device__ V none() const { return {__builtin_inff(), 0.f}; }
     __device__ V prim(uint32_t n) {
         const uint32_t k = blob_op(blob[n]);
-        kinds[node_class(k)]++;
+        count_class(*reinterpret_cast<uint32_t(*)[4]>(kinds), k);
         return {prim_eval<float>(k, (const cfloat*)(par[n].v), p), 1.f};
     }
     __device__ V single(uint32_t op, const V& a, bool from_left) const {

@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(256) batch_fast_kernel(const TraceArgs* __rest
                                                          const uint2* __restrict__ jobs, uint32_t n_jobs,
                                                          uint32_t* __restrict__ head) {
     __shared__ WaveLds<kMaFast> lds[4];
-    const int w = threadIdx.x >> 6;
+    const int w = int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));   // wave-uniform: the LDS slot address stays scalar
     // a wave takes at most n_jobs jobs, so the loop ends even if the queue
     // were corrupted
     for (uint32_t it = 0; it < n_jobs; it++) {

@@ -44,6 +44,15 @@ HD bool is_prim_kind(uint32_t k) { return k <= ST_CYLINDER; }
 // node class of the evaluation counters: sphere, primitive in a rotated box
 // frame (box, torus, cylinder), capsule, operator
 HD uint32_t node_class(uint32_t k) { return k == ST_SPHERE ? 0u : k == ST_CAPSULE ? 2u : k <= ST_CYLINDER ? 1u : 3u; }
+// counts[node_class(k)] += 1 with constant indices only (a run-time index
+// into a small per-lane array would place it in scratch memory)
+HD void count_class(uint32_t (&counts)[4], uint32_t k) {
+    const uint32_t c = node_class(k);
+    counts[0] += c == 0u ? 1u : 0u;
+    counts[1] += c == 1u ? 1u : 0u;
+    counts[2] += c == 2u ? 1u : 0u;
+    counts[3] += c == 3u ? 1u : 0u;
+}
 HD bool is_op_kind(uint32_t k) { return k >= ST_UNION && k <= ST_SDIFF; }
 HD bool is_compact_kind(uint32_t k) { return k >= ST_SUNION && k <= ST_SDIFF; }
 HD uint32_t ignore_of(uint32_t k) {

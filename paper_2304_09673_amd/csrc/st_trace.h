@@ -181,8 +181,10 @@ struct WaveLds {
     uint32_t lca_[MA];
     uint32_t vs_[2 * MA];
     uint32_t view_[2 * MA];
-    __device__ __forceinline__ uint32_t* act(int b) { return act_[b]; }
-    __device__ __forceinline__ float* ze(int b) { return ze_[b]; }
+    // buffer b as base + b * MA (an index into the 2-row array would make
+    // the compiler keep a table of the two row pointers in scratch memory)
+    __device__ __forceinline__ uint32_t* act(int b) { return &act_[0][0] + b * MA; }
+    __device__ __forceinline__ float* ze(int b) { return &ze_[0][0] + b * MA; }
     __device__ __forceinline__ uint32_t* lca() { return lca_; }
     __device__ __forceinline__ uint32_t* vs() { return vs_; }
     __device__ __forceinline__ uint32_t* view() { return view_; }
@@ -423,11 +425,15 @@ __device__ PruneResult build_view(const TraceArgs& A, Mem& S, int buf, int n) {
     const int bits = 31 - __builtin_clz(uint32_t(4 * S.cap()));
     int m;
     {
-        uint32_t* bx[2] = {S.act(buf ^ 1), reinterpret_cast<uint32_t*>(S.ze(buf ^ 1))};
+        // the two output buffers by a select, not a run-time index into a
+        // pointer array (which would live in scratch memory and turn every
+        // access through it into a generic-address access)
+        uint32_t* const bx0 = S.act(buf ^ 1);
+        uint32_t* const bx1 = reinterpret_cast<uint32_t*>(S.ze(buf ^ 1));
         bool lca_ok = false;
         for (int round = 0; round < 8; round++) {
             pair_lcas(A, act, n, S.lca(), tab, bits);
-            uint32_t* out = bx[round & 1];
+            uint32_t* out = (round & 1) ? bx1 : bx0;
             int kept = 0;
             for (int b = 0; b < n; b += 64) {
                 const int s = b + lane;
@@ -792,8 +798,7 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         // kinds in the view (for node counts)
         uint32_t kc[4] = {0, 0, 0, 0};
         for (int j = lane; j < len; j += 64) {
-            uint32_t kd = ventry_kind(S.view()[j]);
-            kc[node_class(kd)]++;
+            count_class(kc, ventry_kind(S.view()[j]));
         }
         for (int q = 0; q < 4; q++) kc[q] = uni(wave_sum(kc[q]));
 

@@ -16,7 +16,7 @@ namespace st {
 template <int MA, int KS, int SM>
 __global__ void __launch_bounds__(256, 3) trace_fast_kernel(TraceArgs A, uint32_t n_jobs) {
     __shared__ WaveLds<MA> lds[4];
-    const int w = threadIdx.x >> 6;
+    const int w = int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));   // wave-uniform: the LDS slot address stays scalar
     const uint32_t* tab = nullptr;
     if constexpr (SM == SM_LEARNED) {
         __shared__ uint32_t mlp_tab[kMlpTabWords];
