@@ -147,14 +147,14 @@ def _primitive(rng, b: _Builder, centre, s, kinds=PRIMITIVE_KINDS):
     return b.add(CAPSULE, p=(*a, *e, 0.5 * s))
 
 
-def _random_tree(rng, b: _Builder, leaves, max_depth, op_probs, k_range):
+def _random_tree(rng, b: _Builder, leaves, max_depth, op_probs, k_range, ops=(SUNION, SINTER, SDIFF)):
     """Random binary tree over ``leaves`` (kept in order) with depth <= max_depth.
 
     A subtree of n leaves at depth l splits its leaves uniformly over the left
-    sizes that still fit under the depth cap."""
+    sizes that still fit under the depth cap; each operator is drawn from
+    ``ops`` with probabilities ``op_probs``."""
     if len(leaves) > 2 ** max_depth:
         raise ValueError("too many leaves for the depth cap")
-    ops = (SUNION, SINTER, SDIFF)
 
     def build(lo, hi, depth):
         n = hi - lo
@@ -165,7 +165,7 @@ def _random_tree(rng, b: _Builder, leaves, max_depth, op_probs, k_range):
         nl = int(rng.integers(nl_min, nl_max + 1))
         l = build(lo, lo + nl, depth + 1)
         r = build(lo + nl, hi, depth + 1)
-        op = ops[int(rng.choice(3, p=op_probs))]
+        op = ops[int(rng.choice(len(ops), p=op_probs))]
         k = float(rng.uniform(*k_range))
         return b.add(op, l, r, (k, 0.0))
 
@@ -189,7 +189,8 @@ def config1(seed: int = 0, width: int = 256, height: int = 256) -> Scene:
 
 
 def _mixed_scene(name, seed, n_prims, size_range, max_depth, width, height, tile,
-                 centres=None, config=None, kinds=PRIMITIVE_KINDS):
+                 centres=None, config=None, kinds=PRIMITIVE_KINDS, ops=(SUNION, SINTER, SDIFF),
+                 op_probs=(0.6, 0.2, 0.2)):
     rng = _rng(seed)
     b = _Builder()
     if centres is None:
@@ -198,7 +199,7 @@ def _mixed_scene(name, seed, n_prims, size_range, max_depth, width, height, tile
     for i in range(n_prims):
         s = float(rng.uniform(*size_range))
         leaves.append(_primitive(rng, b, centres[i], s, kinds=kinds))
-    root = _random_tree(rng, b, leaves, max_depth, (0.6, 0.2, 0.2), (0.02, 0.15))
+    root = _random_tree(rng, b, leaves, max_depth, op_probs, (0.02, 0.15), ops=ops)
     return b.finish(name, root, Camera(width=width, height=height),
                     {"config": config, "seed": seed, "tile": tile, "max_depth": max_depth})
 
@@ -219,6 +220,16 @@ def config2_extended(seed: int = 0, width: int = 256, height: int = 256, n_prims
     half height s U[0.4,1], uniformly random orientations."""
     return _mixed_scene(f"c2x_{n_prims}prims", seed, n_prims, (0.05, 0.4), max_depth,
                         width, height, 16, config=2, kinds=EXTENDED_KINDS)
+
+
+def config2_sharp(seed: int = 0, width: int = 256, height: int = 256, n_prims: int = 142,
+                  max_depth: int = 10) -> Scene:
+    """The second workload's primitives and tree shape with sharp operators
+    beside the compact ones: union, intersection, difference sharp
+    35/10/10%, compact 25/10/10% (creases where a sharp operator meets)."""
+    return _mixed_scene(f"c2s_{n_prims}prims", seed, n_prims, (0.05, 0.4), max_depth, width, height, 16,
+                        config=2, ops=(UNION, INTER, DIFF, SUNION, SINTER, SDIFF),
+                        op_probs=(0.35, 0.1, 0.1, 0.25, 0.1, 0.1))
 
 
 def gaussian_mixture_centres(rng, n, n_clusters=32, sigma=0.15):
