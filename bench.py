@@ -654,6 +654,11 @@ def main():
         "abuffer_binned": stats["abuffer_binned"],
         "max_overlap": stats["max_overlap"],
         "max_active": stats["max_active"],
+        "block_cycles": {"note": "8x8 blocks of the statistics frame, shader clock cycles from the start to the end "
+                                 "of each block (the trace launch lasts at least the longest)",
+                         "max": stats["block_cycles_max"],
+                         "mean": stats["block_cycles_sum"] / max(1, -(-cam.width // 8) * -(-cam.height // 8)),
+                         "blocks": -(-cam.width // 8) * -(-cam.height // 8)},
         "subfrustums": stats["subfrustums"],
         "empty_views": stats["empty_views"],
         "view_nodes": stats["view_nodes"],

@@ -181,6 +181,10 @@ typedef struct {
                                  before every ray finished (0 in a correct run) */
     uint64_t smooth_evals;    /* compact operators evaluated on their smooth
                                  (blending) branch */
+    uint64_t block_cycles_max; /* longest 8x8 block of the trace, in shader
+                                 clock cycles (s_memtime): the launch lasts
+                                 at least this long */
+    uint64_t block_cycles_sum; /* sum over the blocks (mean = sum / blocks) */
 } st_stats;
 
 /* Device memory allocator used for the scene's buffers (e.g. a framework's
@@ -306,7 +310,7 @@ st_status st_trace_ex(st_scene *s, const st_camera *cam, float *out_depth, float
  * st_trace_noalloc -- st_trace that allocates no device memory, for callers
  * that cannot allocate (code under HIP graph capture, serving loops,
  * harnesses that forbid hipMalloc).  Same kernels and the same outputs as
- * st_trace; the trace's scratch (one 192-byte counter record per 8x8 pixel
+ * st_trace; the trace's scratch (one 208-byte counter record per 8x8 pixel
  * block, and the wide path's per-workgroup slots when an overlap is too large
  * for LDS) lives in a 32 MiB device array of the library, one copy per GPU,
  * held until the process ends.
@@ -317,7 +321,7 @@ st_status st_trace_ex(st_scene *s, const st_camera *cam, float *out_depth, float
  * on the same GPU (two streams, two threads) race and give undefined
  * results; calls on one stream are ordered and safe.  The array needs no
  * clearing: every block writes its whole record.
- * Errors: ST_E_CAPACITY when the frame has more than 174,762 blocks of 8x8
+ * Errors: ST_E_CAPACITY when the frame has more than 161,319 blocks of 8x8
  * pixels (about 11 million pixels; the message gives the sizes), or no room
  * is left for one wide-path slot; ST_E_STALE, ST_E_INVALID, ST_E_DEVICE as
  * st_trace.  Nothing is launched on a capacity error.

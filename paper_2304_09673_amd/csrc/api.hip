@@ -114,6 +114,8 @@ void stats_from_counters(const st_scene* s, const unsigned long long* h, st_stat
     out->learned_rejected = h[20];
     out->stalled = h[21];
     out->smooth_evals = h[22];
+    out->block_cycles_max = h[23];
+    out->block_cycles_sum = h[24];
     out->abuffer_entries = uint64_t(s->n_live);
     out->abuffer_binned = uint64_t(s->n_entries);
     out->abuffer_candidates = uint64_t(s->n_cand);

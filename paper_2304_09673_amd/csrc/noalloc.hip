@@ -12,7 +12,7 @@
 
 namespace {
 
-// 32 MiB: counter records for up to 174,762 blocks of 8x8 pixels (a
+// 32 MiB: counter records for up to 161,319 blocks of 8x8 pixels (a
 // 3840x2160 frame has 129,600 at every tile size), the rest for wide-path
 // slots.  Each GPU the library runs on holds its own copy until the process
 // ends.

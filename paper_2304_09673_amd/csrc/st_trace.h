@@ -162,10 +162,12 @@ int wide_capacity(const st_scene* s);
 
 enum StatIdx {
     S_RAYS = 0, S_HITS, S_UNCONV, S_EVALS, S_GEVALS, S_NODE = 5, S_GNODE = 9, S_STEPS = 13, S_SUBF, S_EMPTY,
-    S_VIEWN, S_MAXACT, S_WIDE, S_ACC, S_REJ, S_STALL, S_SMOOTH, S_COUNT
+    S_VIEWN, S_MAXACT, S_WIDE, S_ACC, S_REJ, S_STALL, S_SMOOTH, S_CYC_MAX, S_CYC_SUM, S_COUNT
 };
 // words of a block's counter record (S_COUNT rounded up)
-constexpr int kWaveStats = 24;
+constexpr int kWaveStats = 26;
+// counters reduced by maximum (the others by sum)
+__host__ __device__ constexpr bool stat_is_max(int c) { return c == S_MAXACT || c == S_CYC_MAX; }
 static_assert(S_COUNT <= kWaveStats, "counter record too small");
 
 // Per-wave storage of the active set and the view.  Two layouts share the
@@ -585,7 +587,7 @@ __device__ void block_counters(const TraceArgs& A, unsigned long long* cnt, uint
         if (lane < kWaveStats) A.wrec[size_t(job) * kWaveStats + size_t(lane)] = mine;
     } else if (cnt != nullptr && lane == 0) {
         for (int c = 0; c < S_COUNT; c++) {
-            if (c == S_MAXACT) atomicMax(cnt + c, v[c]);
+            if (stat_is_max(c)) atomicMax(cnt + c, v[c]);
             else if (v[c]) atomicAdd(cnt + c, v[c]);
         }
     }
@@ -610,6 +612,9 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
         block_counters(A, cnt, job, zero);
         return;
     }
+    // the block's duration in shader clock cycles (its counters report the
+    // longest and the sum: the launch is set by its slowest blocks)
+    const uint64_t clk_start = __builtin_amdgcn_s_memtime();
     Ray ray = pixel_ray(A.cam, px, py);
     const float inv_cos = 1.0f / ray.cosv;
 
@@ -1035,6 +1040,7 @@ __device__ void trace_block(const TraceArgs& A, Mem& S, uint32_t tile, uint32_t 
     v[S_REJ] = nrej;
     v[S_STALL] = n_stall;
     v[S_SMOOTH] = smt;
+    v[S_CYC_MAX] = v[S_CYC_SUM] = __builtin_amdgcn_s_memtime() - clk_start;
     block_counters(A, cnt, job, v);
 }
 

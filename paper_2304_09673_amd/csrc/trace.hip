@@ -64,14 +64,14 @@ __global__ void __launch_bounds__(256) reduce_counters_kernel(const unsigned lon
     unsigned long long acc = 0;
     for (uint32_t j = threadIdx.x; j < n_jobs; j += blockDim.x) {
         const unsigned long long x = wrec[size_t(j) * kWaveStats + size_t(c)];
-        acc = c == S_MAXACT ? (x > acc ? x : acc) : acc + x;
+        acc = stat_is_max(c) ? (x > acc ? x : acc) : acc + x;
     }
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (int(threadIdx.x) < o) {
             const unsigned long long y = part[threadIdx.x + o];
-            part[threadIdx.x] = c == S_MAXACT ? (y > part[threadIdx.x] ? y : part[threadIdx.x]) : part[threadIdx.x] + y;
+            part[threadIdx.x] = stat_is_max(c) ? (y > part[threadIdx.x] ? y : part[threadIdx.x]) : part[threadIdx.x] + y;
         }
         __syncthreads();
     }

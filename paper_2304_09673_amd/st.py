@@ -68,7 +68,8 @@ class StStats(C.Structure):
                 ("learned_accepted", C.c_uint64), ("learned_rejected", C.c_uint64),
                 ("abuffer_binned", C.c_uint64), ("abuffer_candidates", C.c_uint64),
                 ("candidate_pixels", C.c_uint64 * 3), ("abuffer_tested", C.c_uint64), ("stalled", C.c_uint64),
-                ("smooth_evals", C.c_uint64)]
+                ("smooth_evals", C.c_uint64), ("block_cycles_max", C.c_uint64),
+                ("block_cycles_sum", C.c_uint64)]
 
     def as_dict(self):
         d = {}

@@ -405,3 +405,24 @@ def test_device_view_equals_host_view_large_sets(which):
         # primitives almost never reach the root, which the equality above
         # covers as well)
         assert n_used > 0
+
+
+def test_block_clock_counters():
+    """Per-block shader clock counters: the longest block is at least the mean,
+    and the longest block, converted at a 2.5 GHz clock (above the chip's
+    highest), does not exceed the launch's duration measured with HIP events."""
+    import torch
+    from paper_2304_09673_amd import st
+    sc = sg.config2(0, 256, 256)
+    s = st.Scene(sc)
+    s.build_abuffer(sc.camera, st.default_tuning(tile=16))
+    s.trace()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    _, _, stats = s.trace()
+    b.record()
+    torch.cuda.synchronize()
+    blocks = (256 // 8) * (256 // 8)
+    mx, mean = stats["block_cycles_max"], stats["block_cycles_sum"] / blocks
+    assert 0 < mean <= mx, stats
+    assert mx / 2.5e9 * 1e3 <= a.elapsed_time(b) + 0.01, (mx, a.elapsed_time(b))

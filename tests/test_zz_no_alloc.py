@@ -75,7 +75,7 @@ def test_noalloc_without_stats_and_repeated():
 
 
 def test_noalloc_refuses_frames_above_its_scratch():
-    """4096x2816 pixels = 180,224 blocks of 8x8, above the 174,762 records the
+    """4096x2816 pixels = 180,224 blocks of 8x8, above the 161,319 records the
     32 MiB scratch holds: ST_E_CAPACITY and nothing written."""
     import torch
     from paper_2304_09673_amd import st
