@@ -215,24 +215,26 @@ __device__ __forceinline__ int4 rect_tiles(int4 pr, int ts) {
 // and for every set that the pruning passes see.  (The cut is by whole
 // tiles: the per-ray test still covers the primitive's whole rectangle in
 // each tile it keeps.)
-__global__ void __launch_bounds__(256) rect_kernel(const Voi* __restrict__ voi, int P, DevCam cam, int ts,
-                                                   const uint32_t* __restrict__ oside, const float* __restrict__ sub,
-                                                   int keep_all, int4* __restrict__ rect, int4* __restrict__ trect) {
-    // eight lanes per primitive: lane 0 its own rectangle, lane k (1..7) the
-    // k-th killing ancestor's other side; the tile ranges are intersected
-    // across the eight lanes
-    const int gid = int(blockIdx.x * blockDim.x + threadIdx.x);
-    const int p = gid >> 3, j = gid & 7;
-    const bool in = p < P;
+__global__ void __launch_bounds__(64) rect_count_kernel(const Voi* __restrict__ voi, DevCam cam, int ts,
+                                                         const uint32_t* __restrict__ oside,
+                                                         const float* __restrict__ sub, int keep_all, int tiles_x,
+                                                         int4* __restrict__ rect, int4* __restrict__ trect,
+                                                         uint32_t* __restrict__ tile_count) {
+    // one wave per primitive p (a rectangle covers a few dozen tiles).  Eight
+    // lanes: lane 0 the primitive's own rectangle, lane k (1..7) the k-th
+    // killing ancestor's other side; the tile ranges are intersected across
+    // the eight lanes and broadcast
+    const int p = int(blockIdx.x), j = int(threadIdx.x & 7u);
+    const bool lead = threadIdx.x < 8u;
     constexpr int kAll = 0x7FFFFFFF;
     int4 tr = make_int4(0, 0, kAll, kAll);
-    if (in && j == 0) {
+    if (lead && j == 0) {
         int i0, i1, j0, j1;
         const bool any = voi_pixels(voi[p], cam, i0, i1, j0, j1);
         const int4 pr = any ? make_int4(i0, j0, i1, j1) : make_int4(0, 0, -1, -1);
-        rect[p] = pr;
+        if (threadIdx.x == 0) rect[p] = pr;
         tr = rect_tiles(pr, ts);
-    } else if (in && !keep_all) {
+    } else if (lead && !keep_all) {
         const uint32_t other = oside[8 * size_t(p) + size_t(j - 1)];
         if (other != kNoKill) {
             int a0, a1, b0, b1;
@@ -246,7 +248,17 @@ __global__ void __launch_bounds__(256) rect_kernel(const Voi* __restrict__ voi, 
         tr.z = min(tr.z, __shfl_xor(tr.z, o));
         tr.w = min(tr.w, __shfl_xor(tr.w, o));
     }
-    if (in && j == 0) trect[p] = tr.x <= tr.z && tr.y <= tr.w ? tr : make_int4(0, 0, -1, -1);
+    tr.x = __builtin_amdgcn_readfirstlane(tr.x);
+    tr.y = __builtin_amdgcn_readfirstlane(tr.y);
+    tr.z = __builtin_amdgcn_readfirstlane(tr.z);
+    tr.w = __builtin_amdgcn_readfirstlane(tr.w);
+    if (!(tr.x <= tr.z && tr.y <= tr.w)) tr = make_int4(0, 0, -1, -1);
+    if (threadIdx.x == 0) trect[p] = tr;
+    // one candidate for every tile of the range
+    const int w = tr.z - tr.x + 1, h = tr.w - tr.y + 1;
+    if (w <= 0 || h <= 0) return;
+    for (int k = int(threadIdx.x); k < w * h; k += int(blockDim.x))
+        atomicAdd(tile_count + (tr.y + k / w) * tiles_x + tr.x + k % w, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -371,13 +383,21 @@ void exclusive_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* scratch,
 // workgroup per primitive (its volume of interest is workgroup-uniform and
 // read once), one wave per candidate tile in turn, each lane testing
 // ts*ts/64 rays, then a wave min/max of the entry and exit depths
+// number of lanes below this one whose bit is set in mask
+__device__ __forceinline__ uint32_t lanes_below_mask(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
 // Dispatch order of tiles: decreasing count of the candidates left for the
 // per-ray test (the trace reuses the order).  The work of a tile grows with its
 // count and a launch is set by its slowest workgroups, so the heavy tiles
 // start first and the light ones fill the machine behind them.  One
 // workgroup, counting sort over kOrderBuckets count buckets (counts beyond
 // the last bucket share it); the order within a bucket is whatever the LDS
-// atomics give, which changes only the schedule, not any result.
+// atomics give, which changes only the schedule, not any result.  Most tiles
+// of a sparse frame have no candidate left: the lanes of a wave that fall in
+// that bucket take their places with one atomic per wave (ballot and rank),
+// since thousands of lane atomics on one LDS word serialize.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4 * kOrderThreads;
 constexpr int kOrderBatch = 8;
@@ -386,10 +406,12 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
                                                                     int n_tiles, uint32_t* __restrict__ order) {
     __shared__ uint32_t cnt[kOrderBuckets];
     __shared__ uint32_t part[kOrderThreads];
+    constexpr uint32_t kEmpty = uint32_t(kOrderBuckets - 1);   // bucket of count 0
     const int tid = int(threadIdx.x);
+    const bool leader = (tid & 63) == 0;
     auto bucket = [&](int t) {   // longest first
         const uint32_t len = t < n_tiles ? tile_cnt[t] : 0u;
-        return uint32_t(kOrderBuckets - 1) - min(len, uint32_t(kOrderBuckets - 1));
+        return kEmpty - min(len, kEmpty);
     };
     for (int b = tid; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
     __syncthreads();
@@ -400,8 +422,12 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
 #pragma unroll
         for (int k = 0; k < kOrderBatch; k++) bk[k] = bucket(t0 + k * kOrderThreads + tid);
 #pragma unroll
-        for (int k = 0; k < kOrderBatch; k++)
-            if (t0 + k * kOrderThreads + tid < n_tiles) atomicAdd(&cnt[bk[k]], 1u);
+        for (int k = 0; k < kOrderBatch; k++) {
+            const bool in = t0 + k * kOrderThreads + tid < n_tiles;
+            const uint64_t em = __ballot(in && bk[k] == kEmpty);
+            if (in && bk[k] != kEmpty) atomicAdd(&cnt[bk[k]], 1u);
+            if (leader && em) atomicAdd(&cnt[kEmpty], uint32_t(__popcll(em)));
+        }
     }
     __syncthreads();
     // exclusive scan: four buckets per thread, then an inclusive scan of the
@@ -426,19 +452,15 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint32_
 #pragma unroll
         for (int k = 0; k < kOrderBatch; k++) {
             const int t = t0 + k * kOrderThreads + tid;
-            if (t < n_tiles) order[atomicAdd(&cnt[bk[k]], 1u)] = uint32_t(t);
+            const bool in = t < n_tiles, empty = in && bk[k] == kEmpty;
+            const uint64_t em = __ballot(empty);
+            uint32_t base = 0;
+            if (leader && em) base = atomicAdd(&cnt[kEmpty], uint32_t(__popcll(em)));
+            base = __builtin_amdgcn_readlane(base, 0);
+            if (empty) order[base + lanes_below_mask(em)] = uint32_t(t);
+            else if (in) order[atomicAdd(&cnt[bk[k]], 1u)] = uint32_t(t);
         }
     }
-}
-
-// per primitive (one workgroup): one candidate for every tile of its rectangle
-__global__ void __launch_bounds__(256) cand_count_kernel(const int4* __restrict__ trect, int tiles_x,
-                                                         uint32_t* __restrict__ tile_count) {
-    const int4 rc = trect[blockIdx.x];
-    const int w = rc.z - rc.x + 1, h = rc.w - rc.y + 1;
-    if (w <= 0 || h <= 0) return;
-    for (int k = int(threadIdx.x); k < w * h; k += int(blockDim.x))
-        atomicAdd(tile_count + (rc.y + k / w) * tiles_x + rc.x + k % w, 1u);
 }
 
 // per primitive (one workgroup): its index into a slot of each tile segment
@@ -671,10 +693,6 @@ constexpr int kPruneThreads = 256;
 constexpr int kTileStat = 8;
 constexpr int kPruneLdsCap = 1024;
 
-__device__ __forceinline__ uint32_t lanes_below_mask(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-}
-
 // exclusive rank of this thread among the workgroup's threads with keep set,
 // in thread order; *total gets their count
 __device__ int block_rank(bool keep, int* total) {
@@ -900,9 +918,9 @@ __device__ bool wave_alive(uint32_t x, bool in, uint32_t* srt, uint32_t* tab, co
     return in && m > 0 && hfind(tab, kWavePruneBits, x, tab[hslot(x, kWavePruneBits)]);
 }
 
-// Pre-test pruning of a tile with 1..64 candidates by one wave (the first
-// of its workgroup): same result as the workgroup path of cand_prune_kernel.
-// srt (64 words) and tab (128 words) are LDS scratch.
+// Pre-test pruning of a tile with 1..64 candidates by one wave: same result
+// as the workgroup path (cand_prune_wg).  srt (64 words) and tab (128 words)
+// are the wave's LDS scratch.
 __device__ void cand_prune_wave(int tile, uint32_t e0, int n, int tiles_x, int ts, const uint32_t* __restrict__ prims,
                                 const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim,
                                 uint32_t* __restrict__ tile_n, const uint32_t* __restrict__ rmq,
@@ -935,10 +953,9 @@ __device__ void cand_prune_wave(int tile, uint32_t e0, int n, int tiles_x, int t
     }
 }
 
-// Post-test pruning of a tile with 1..64 tested candidates by one wave (the
-// first of its workgroup): same result as prune_tile (entries that hit and
-// survive, compacted in order).  srt (64 words) and tab (128 words) are LDS
-// scratch.
+// Post-test pruning of a tile with 1..64 tested candidates by one wave: same
+// result as prune_tile (entries that hit and survive, compacted in order).
+// srt (64 words) and tab (128 words) are the wave's LDS scratch.
 __device__ void tile_prune_wave(int tile, uint32_t e0, int n, uint32_t* e_node, float* e_zin, float* e_zout,
                                 uint32_t* __restrict__ tile_cnt, const uint32_t* __restrict__ rmq,
                                 const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes,
@@ -967,26 +984,26 @@ __device__ void tile_prune_wave(int tile, uint32_t e0, int n, uint32_t* e_node, 
     }
 }
 
-__global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
-        const uint32_t* __restrict__ tile_off, int n_tiles, int tiles_x, int ts, const uint32_t* __restrict__ prims,
-        const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim, uint32_t* __restrict__ tile_n,
-        const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
-        uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
-    __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
-    const int tile = int(blockIdx.x);
-    if (tile >= n_tiles) return;
+// Work split of the two pruning kernels (one workgroup per tile in the
+// grid): wave w of workgroup b takes tile 4b + w when its list is empty or
+// short (nearly every tile; one wave, no barrier), and workgroup b takes tile
+// b when its list is longer (the whole workgroup).  Four short tiles per
+// workgroup keep four waves busy where a workgroup per short tile would hold
+// its LDS for one, and the long lists, which sit next to each other around
+// the clusters of a scene, still run side by side in their own workgroups.
+constexpr int kPruneTiles = kPruneThreads / 64;
+
+// Pre-test pruning of a tile with more than kWavePruneMax candidates (or
+// keep_all) by the whole workgroup; a, b, tab are its LDS scratch.
+__device__ void cand_prune_wg(int tile, uint32_t e0, int n, int tiles_x, int ts, const uint32_t* __restrict__ prims,
+                              const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim,
+                              uint32_t* __restrict__ tile_n, const uint32_t* __restrict__ rmq,
+                              const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill, uint32_t n_nodes,
+                              int keep_all, uint32_t* __restrict__ tstat, uint32_t* a, uint32_t* b, uint32_t* tab) {
     const int tid = int(threadIdx.x);
-    const uint32_t e0 = tile_off[tile];
-    const int n = int(tile_off[tile + 1] - e0);
-    if (!keep_all && n >= 1 && n <= kWavePruneMax) {   // a short list: one wave, no barrier
-        if (tid < 64)
-            cand_prune_wave(tile, e0, n, tiles_x, ts, prims, rect, voi, slot_prim, tile_n, rmq, kslot, kill, n_nodes,
-                            tstat, a, tab);
-        return;
-    }
-    if (n == 0 || n > kPruneLdsCap || keep_all) {
+    if (n > kPruneLdsCap || keep_all) {
         if (tid == 0) tile_n[tile] = uint32_t(n);
-        if (n) add_tested(slot_prim, e0, n, tile, tiles_x, ts, rect, voi, tstat);
+        add_tested(slot_prim, e0, n, tile, tiles_x, ts, rect, voi, tstat);
         return;
     }
     int np2 = 1;
@@ -1021,31 +1038,68 @@ __global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
     if (kept) add_tested(slot_prim, e0, kept, tile, tiles_x, ts, rect, voi, tstat);
 }
 
+__global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
+        const uint32_t* __restrict__ tile_off, int n_tiles, int tiles_x, int ts, const uint32_t* __restrict__ prims,
+        const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim, uint32_t* __restrict__ tile_n,
+        const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
+        uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
+    __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
+    const int w = int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));   // wave-uniform
+    // the wave's tile, if empty or short (its scratch: 64 words of a, 128 of tab)
+    const int mine = int(blockIdx.x) * kPruneTiles + w;
+    if (mine < n_tiles) {
+        const uint32_t e0 = tile_off[mine];
+        const int n = int(tile_off[mine + 1] - e0);
+        if (n == 0) {
+            if ((threadIdx.x & 63u) == 0) tile_n[mine] = 0u;
+        } else if (!keep_all && n <= kWavePruneMax) {
+            cand_prune_wave(mine, e0, n, tiles_x, ts, prims, rect, voi, slot_prim, tile_n, rmq, kslot, kill, n_nodes,
+                            tstat, a + 64 * w, tab + 128 * w);
+        }
+    }
+    // the workgroup's tile, if its list is longer (uniform: every thread reads
+    // the same offsets, which this kernel does not write)
+    const int tile = int(blockIdx.x);
+    if (tile >= n_tiles) return;
+    const uint32_t e0 = tile_off[tile];
+    const int n = int(tile_off[tile + 1] - e0);
+    if (n == 0 || (!keep_all && n <= kWavePruneMax)) return;
+    __syncthreads();   // the waves are done with their scratch
+    cand_prune_wg(tile, e0, n, tiles_x, ts, prims, rect, voi, slot_prim, tile_n, rmq, kslot, kill, n_nodes, keep_all,
+                  tstat, a, b, tab);
+}
+
+// tstat[kTileStat * t] holds tile t's candidate count after the pre-test
+// pruning (the count the per-ray test takes): this kernel decides from it,
+// since it rewrites tile_cnt while other workgroups still decide
 __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
         const uint32_t* __restrict__ tile_off, int n_tiles, uint32_t* e_node, float* e_zin, float* e_zout,
         uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
         const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
         uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
     __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
+    const int w = int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));   // wave-uniform
+    // the wave's tile, if its list is short (its scratch: 64 words of a, 128 of tab)
+    const int mine = int(blockIdx.x) * kPruneTiles + w;
+    if (mine < n_tiles) {
+        const int n = int(tstat[kTileStat * size_t(mine)]);
+        if (n > 0 && n <= kWavePruneMax)
+            tile_prune_wave(mine, tile_off[mine], n, e_node, e_zin, e_zout, tile_cnt, rmq, kslot, kill, n_nodes,
+                            keep_all, tstat, a + 64 * w, tab + 128 * w);
+    }
+    // the workgroup's tile, if its list is longer (uniform)
     const int tile = int(blockIdx.x);
     if (tile >= n_tiles) return;
-    const uint32_t e0 = tile_off[tile];
-    const int n = int(tile_cnt[tile]);   // tested candidates of the segment
-    __syncthreads();                     // every thread has read it before thread 0 rewrites it
-    if (n == 0) return;
-    if (n <= kWavePruneMax) {   // a short list: one wave, no barrier
-        if (threadIdx.x < 64)
-            tile_prune_wave(tile, e0, n, e_node, e_zin, e_zout, tile_cnt, rmq, kslot, kill, n_nodes, keep_all, tstat,
-                            a, tab);
-        return;
-    }
-    if (n > kPruneLdsCap) {
+    const int n = int(tstat[kTileStat * size_t(tile)]);
+    if (n <= kWavePruneMax) return;
+    if (n > kPruneLdsCap) {   // for the long-list kernel
         if (threadIdx.x == 0) long_list[atomicAdd(misc + 5, 1u)] = uint32_t(tile);
         return;
     }
+    __syncthreads();   // the waves are done with their scratch
     int hits;
-    const int kept = prune_tile(e0, n, e_node, e_zin, e_zout, a, b, tab, prune_bits(n), rmq, kslot, kill, n_nodes,
-                                keep_all != 0, &hits);
+    const int kept = prune_tile(tile_off[tile], n, e_node, e_zin, e_zout, a, b, tab, prune_bits(n), rmq, kslot, kill,
+                                n_nodes, keep_all != 0, &hits);
     if (threadIdx.x == 0) {
         tile_cnt[tile] = uint32_t(kept);
         tstat[kTileStat * size_t(tile) + 4] = uint32_t(hits);
@@ -1321,11 +1375,9 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
     hipLaunchKernelGGL(clear_build_kernel, dim3((uint32_t(kTileStat) * uint32_t(T) + 64u) / 256u + 1u), dim3(256), 0,
                        stream, tcnt, cur, uint32_t(T), misc, s->d_wide, tstat);
     unsigned long long* pix = reinterpret_cast<unsigned long long*>(misc + 16);   // 3 counters, 8-byte aligned
-    if (P) hipLaunchKernelGGL(rect_kernel, dim3((8 * P + 255) / 256), dim3(256), 0, stream, s->d_voi, P, s->dcam, ts,
-                       s->d_oside, s->d_sub, t.keep_all_entries, rect, trect);
-    // one wave per primitive: a rectangle covers about 60 tiles on the 1080p
-    // frame, so wider workgroups would mostly idle
-    if (P) hipLaunchKernelGGL(cand_count_kernel, dim3(P), dim3(256), 0, stream, trect, s->tiles_x, tcnt);
+    // pixel rectangle, tile range and candidate count of every primitive
+    if (P) hipLaunchKernelGGL(rect_count_kernel, dim3(P), dim3(64), 0, stream, s->d_voi, s->dcam, ts, s->d_oside,
+                              s->d_sub, t.keep_all_entries, s->tiles_x, rect, trect, tcnt);
     exclusive_scan(tcnt, s->d_tile_off, T, sums, misc + 9, s->d_tile_off + T, stream);
     uint32_t n_cand = replay ? s->n_cand : 0u;
     if (!replay) {
