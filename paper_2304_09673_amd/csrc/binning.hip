@@ -512,21 +512,28 @@ __device__ __forceinline__ float dpp_max(float v) {
 // waves per tile: sixteen take a 16x16 or 32x32 tile's candidates in turn,
 // so that the longest lists end early; an 8x8 tile (one ray per lane) has few
 // candidates to share
+// Waves per tile of the test, in workgroups of four waves: a tile's waves
+// share nothing (no LDS, no barrier), and a workgroup of four finds room on a
+// compute unit beside other kernels' workgroups (other frames' traces) where
+// one of sixteen would wait for a quarter of a compute unit to drain.
 constexpr uint32_t test_waves(int ts) { return ts == 8 ? 4u : 16u; }
+constexpr uint32_t kTestWgWaves = 4;
+constexpr uint32_t test_wgs(int ts) { return test_waves(ts) / kTestWgWaves; }   // workgroups per tile
 
 template <int TS>
-__global__ void __launch_bounds__(64 * test_waves(TS)) tile_test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
+__global__ void __launch_bounds__(64 * kTestWgWaves) tile_test_kernel(const Voi* __restrict__ voi, const int4* __restrict__ rect,
                                                         const uint32_t* __restrict__ tile_off,
                                                         const uint32_t* __restrict__ tile_n,
                                                         const uint32_t* __restrict__ order, int tiles_x, DevCam cam,
                                                         uint32_t* __restrict__ e_node, float* __restrict__ e_zin,
                                                         float* __restrict__ e_zout) {
     constexpr int RPL = TS * TS / 64;   // rays per lane
-    const int tile = int(order[blockIdx.x]);
+    const int tile = int(order[blockIdx.x / test_wgs(TS)]);
     const uint32_t e0 = tile_off[tile], n = tile_n[tile];
     if (n == 0) return;
     const int lane = int(threadIdx.x & 63u);
-    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the wave's index among the tile's test_waves(TS) waves
+    const uint32_t w = (blockIdx.x % test_wgs(TS)) * kTestWgWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     float dir[RPL][3], cosv[RPL];
     bool ok[RPL];
@@ -1431,13 +1438,13 @@ st_status build_abuffer_device(st_scene* s, const st_tuning& t, hipStream_t stre
             ST_CHECK(hipEventRecord(ev[0], stream), "timing record");
         }
         if (ts == 8)
-            hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T), dim3(64 * test_waves(8)), 0, stream, s->d_voi, rect, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<8>, dim3(T * test_wgs(8)), dim3(64 * kTestWgWaves), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         else if (ts == 16)
-            hipLaunchKernelGGL(tile_test_kernel<16>, dim3(T), dim3(64 * test_waves(16)), 0, stream, s->d_voi, rect, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<16>, dim3(T * test_wgs(16)), dim3(64 * kTestWgWaves), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         else
-            hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T), dim3(64 * test_waves(32)), 0, stream, s->d_voi, rect, s->d_tile_off,
+            hipLaunchKernelGGL(tile_test_kernel<32>, dim3(T * test_wgs(32)), dim3(64 * kTestWgWaves), 0, stream, s->d_voi, rect, s->d_tile_off,
                                s->d_tile_cnt, s->d_tile_order, s->tiles_x, s->dcam, s->d_e_node, s->d_e_zin, s->d_e_zout);
         if (ev) ST_CHECK(hipEventRecord(ev[1], stream), "timing record");
     }
