@@ -13,10 +13,19 @@ namespace st {
 // At least 3 waves per SIMD: the deep-tree and learned-step instances would
 // otherwise take more than 170 registers and run 1 or 2 waves per SIMD; the
 // few spills this costs are cheaper than the lost latency hiding.
+// Waves per workgroup: one (the waves of a workgroup would share nothing,
+// and a one-wave workgroup finds room beside other kernels' workgroups, e.g.
+// other frames' builds, where a four-wave one with four LDS views waits),
+// except for the learned step, whose four waves share the step model's table
+// in LDS.
+constexpr int fast_waves(int sm) { return sm == SM_LEARNED ? 4 : 1; }
+
 template <int MA, int KS, int SM>
-__global__ void __launch_bounds__(256, 3) trace_fast_kernel(TraceArgs A, uint32_t n_jobs) {
-    __shared__ WaveLds<MA> lds[4];
-    const int w = int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));   // wave-uniform: the LDS slot address stays scalar
+__global__ void __launch_bounds__(64 * fast_waves(SM), 3) trace_fast_kernel(TraceArgs A, uint32_t n_jobs) {
+    constexpr int kW = fast_waves(SM);
+    __shared__ WaveLds<MA> lds[kW];
+    // wave-uniform: the LDS slot address stays scalar
+    const int w = kW == 1 ? 0 : int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     const uint32_t* tab = nullptr;
     if constexpr (SM == SM_LEARNED) {
         __shared__ uint32_t mlp_tab[kMlpTabWords];
@@ -27,7 +36,7 @@ __global__ void __launch_bounds__(256, 3) trace_fast_kernel(TraceArgs A, uint32_
     // Workgroups are dispatched in index order, round-robin over the 8 XCDs:
     // job k is a block of the k-th tile of the longest-first order, so the
     // heaviest tiles start first and spread evenly over the XCDs.
-    uint32_t job = blockIdx.x * 4u + uint32_t(w);
+    uint32_t job = blockIdx.x * uint32_t(kW) + uint32_t(w);
     if (job >= n_jobs) return;
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     uint32_t tile = A.tile_order[job / spt], sub = job % spt;
@@ -86,9 +95,11 @@ hipError_t launch_reduce_counters(const unsigned long long* wrec, uint32_t n_job
 }
 
 template <int KS, int SM>
-static hipError_t launch_trace(const TraceArgs& A, uint32_t nwg, uint32_t n_jobs, uint32_t wide_grid,
+static hipError_t launch_trace(const TraceArgs& A, uint32_t n_jobs, uint32_t wide_grid,
                                uint32_t* slots, int ma, hipStream_t stream) {
-    hipLaunchKernelGGL((trace_fast_kernel<kMaFast, KS, SM>), dim3(nwg), dim3(256), 0, stream, A, n_jobs);
+    constexpr uint32_t kW = uint32_t(fast_waves(SM));
+    hipLaunchKernelGGL((trace_fast_kernel<kMaFast, KS, SM>), dim3((n_jobs + kW - 1) / kW), dim3(64 * kW), 0, stream,
+                       A, n_jobs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || wide_grid == 0) return e;
     const size_t shm = slot_words(ma) * 4u;
@@ -174,7 +185,6 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
     }
     uint32_t spt = uint32_t(A.sub_x * A.sub_x);
     uint32_t n_jobs = uint32_t(s->n_tiles) * spt;
-    uint32_t nwg = (n_jobs + 3) / 4;
     // one counter record per block, every one written by its block (so a
     // caller's scratch needs no clearing)
     const size_t rec_bytes = size_t(n_jobs) * kWaveStats * 8u;
@@ -241,23 +251,23 @@ st_status trace_device(st_scene* s, const st_tuning& t, float* depth, float* nor
     hipError_t e = hipSuccess;
     switch (sm) {
     case SM_PLAIN:
-        e = shallow ? launch_trace<16, SM_PLAIN>(A, nwg, n_jobs, grid, slots, ma, stream)
-                    : launch_trace<32, SM_PLAIN>(A, nwg, n_jobs, grid, slots, ma, stream);
+        e = shallow ? launch_trace<16, SM_PLAIN>(A, n_jobs, grid, slots, ma, stream)
+                    : launch_trace<32, SM_PLAIN>(A, n_jobs, grid, slots, ma, stream);
         break;
     case SM_OVER:
-        e = shallow ? launch_trace<16, SM_OVER>(A, nwg, n_jobs, grid, slots, ma, stream)
-                    : launch_trace<32, SM_OVER>(A, nwg, n_jobs, grid, slots, ma, stream);
+        e = shallow ? launch_trace<16, SM_OVER>(A, n_jobs, grid, slots, ma, stream)
+                    : launch_trace<32, SM_OVER>(A, n_jobs, grid, slots, ma, stream);
         break;
     case SM_LEARNED:
-        e = shallow ? launch_trace<16, SM_LEARNED>(A, nwg, n_jobs, grid, slots, ma, stream)
-                    : launch_trace<32, SM_LEARNED>(A, nwg, n_jobs, grid, slots, ma, stream);
+        e = shallow ? launch_trace<16, SM_LEARNED>(A, n_jobs, grid, slots, ma, stream)
+                    : launch_trace<32, SM_LEARNED>(A, n_jobs, grid, slots, ma, stream);
         break;
     case SM_SEGMENT:
-        e = shallow ? launch_trace<16, SM_SEGMENT>(A, nwg, n_jobs, grid, slots, ma, stream)
-                    : launch_trace<32, SM_SEGMENT>(A, nwg, n_jobs, grid, slots, ma, stream);
+        e = shallow ? launch_trace<16, SM_SEGMENT>(A, n_jobs, grid, slots, ma, stream)
+                    : launch_trace<32, SM_SEGMENT>(A, n_jobs, grid, slots, ma, stream);
         break;
     default:
-        e = launch_trace<32, SM_DUMP>(A, nwg, n_jobs, grid, slots, ma, stream);
+        e = launch_trace<32, SM_DUMP>(A, n_jobs, grid, slots, ma, stream);
         break;
     }
     if (e != hipSuccess) return device_error(e, "trace kernels");
