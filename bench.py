@@ -494,8 +494,9 @@ def main():
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the 1024x1024 second-workload frame (dense roofline, ablation variants)")
     ap.add_argument("--c5-reps", type=int, default=3)
-    ap.add_argument("--frames-in-flight", type=int, default=3,
-                    help="frames rendered concurrently (one scene, output pair and stream each)")
+    ap.add_argument("--frames-in-flight", type=int, default=4,
+                    help="frames rendered concurrently (one scene, output pair and stream each; the "
+                         "default, 4, is one per hardware queue HIP gives a process)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design (screen tiles sharded "
