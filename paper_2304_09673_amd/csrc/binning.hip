@@ -699,6 +699,7 @@ constexpr int kPruneThreads = 256;
 // kind (3), tested candidates that hit, padding
 constexpr int kTileStat = 8;
 constexpr int kPruneLdsCap = 1024;
+constexpr int kPruneBatch = kPruneLdsCap / kPruneThreads;   // keys per thread of rank_sort_wg
 
 // exclusive rank of this thread among the workgroup's threads with keep set,
 // in thread order; *total gets their count
@@ -716,6 +717,42 @@ __device__ int block_rank(bool keep, int* total) {
     __syncthreads();
     *total = all;
     return before + int(lanes_below_mask(mk));
+}
+
+// Sorts the keys of in[0..n) (in 16-byte aligned) other than 0xFFFFFFFF (distinct node indices)
+// into out[0..count) by rank counting: each thread ranks its kPruneBatch
+// keys against all n in one pass, and every lane reads the same in[j] at the
+// same time (an LDS broadcast).  n <= kPruneThreads * kPruneBatch.  A list of
+// a few hundred takes one pass of n steps where a bitonic network of
+// workgroup barriers took 45 or more barrier stages.
+__device__ void rank_sort_wg(const uint32_t* in, int n, uint32_t* out) {
+    const int tid = int(threadIdx.x);
+    uint32_t x[kPruneBatch], r[kPruneBatch];
+#pragma unroll
+    for (int k = 0; k < kPruneBatch; k++) {
+        const int i = tid + k * kPruneThreads;
+        x[k] = i < n ? in[i] : 0xFFFFFFFFu;
+        r[k] = 0;
+    }
+    // four keys per LDS read (in is 16-byte aligned), four reads in flight
+    int j = 0;
+#pragma unroll 4
+    for (; j + 4 <= n; j += 4) {
+        const uint4 y = *reinterpret_cast<const uint4*>(in + j);
+#pragma unroll
+        for (int k = 0; k < kPruneBatch; k++)
+            r[k] += (y.x < x[k] ? 1u : 0u) + (y.y < x[k] ? 1u : 0u) + (y.z < x[k] ? 1u : 0u) + (y.w < x[k] ? 1u : 0u);
+    }
+    for (; j < n; j++) {
+        const uint32_t y = in[j];
+#pragma unroll
+        for (int k = 0; k < kPruneBatch; k++) r[k] += y < x[k] ? 1u : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPruneBatch; k++)
+        if (x[k] != 0xFFFFFFFFu) out[r[k]] = x[k];
+    __threadfence_block();
+    __syncthreads();
 }
 
 // Removes from the sorted node list cur[0..m) the primitives that are dead for
@@ -785,9 +822,18 @@ __device__ int prune_tile(uint32_t e0, int n, uint32_t* e_node, float* e_zin, fl
     *hits = m;
     __threadfence_block();
     __syncthreads();
-    if (!keep_all) bitonic_wg(a, (uint32_t*)nullptr, np2);
     uint32_t* cur = a;
-    if (!keep_all) m = dead_rounds(cur, b, m, tab, bits, rmq, kslot, kill, n_nodes);
+    if (!keep_all) {
+        uint32_t* nxt = b;
+        if (n <= kPruneThreads * kPruneBatch) {   // the sorted hits go to b (m <= n words)
+            rank_sort_wg(a, n, b);
+            cur = b;
+            nxt = a;
+        } else {
+            bitonic_wg(a, (uint32_t*)nullptr, np2);
+        }
+        m = dead_rounds(cur, nxt, m, tab, bits, rmq, kslot, kill, n_nodes);
+    }
     // the survivors, as a hash set; then the entries, compacted in place in
     // their order (each chunk is read whole before any of it is written)
     if (!keep_all) {
@@ -1013,15 +1059,25 @@ __device__ void cand_prune_wg(int tile, uint32_t e0, int n, int tiles_x, int ts,
         add_tested(slot_prim, e0, n, tile, tiles_x, ts, rect, voi, tstat);
         return;
     }
-    int np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    for (int i = tid; i < np2; i += kPruneThreads) a[i] = i < n ? prims[slot_prim[e0 + i]] : 0xFFFFFFFFu;
+    {   // the thread's candidates: every slot load issued, then every node load
+        uint32_t p[kPruneBatch];
+#pragma unroll
+        for (int k = 0; k < kPruneBatch; k++) {
+            const int i = tid + k * kPruneThreads;
+            p[k] = i < n ? slot_prim[e0 + i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kPruneBatch; k++) {
+            const int i = tid + k * kPruneThreads;
+            if (i < n) a[i] = prims[p[k]];
+        }
+    }
     __threadfence_block();
     __syncthreads();
-    bitonic_wg(a, (uint32_t*)nullptr, np2);
+    rank_sort_wg(a, n, b);   // n <= kPruneLdsCap
     const int bits = prune_bits(n);
-    uint32_t* cur = a;
-    const int m = dead_rounds(cur, b, n, tab, bits, rmq, kslot, kill, n_nodes);
+    uint32_t* cur = b;
+    const int m = dead_rounds(cur, a, n, tab, bits, rmq, kslot, kill, n_nodes);
     for (int i = tid; i < (1 << bits); i += kPruneThreads) tab[i] = kNoKill;
     __threadfence_block();
     __syncthreads();
@@ -1050,7 +1106,7 @@ __global__ void __launch_bounds__(kPruneThreads) cand_prune_kernel(
         const int4* __restrict__ rect, const Voi* __restrict__ voi, uint32_t* slot_prim, uint32_t* __restrict__ tile_n,
         const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
         uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
-    __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
+    __shared__ __align__(16) uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
     const int w = int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));   // wave-uniform
     // the wave's tile, if empty or short (its scratch: 64 words of a, 128 of tab)
     const int mine = int(blockIdx.x) * kPruneTiles + w;
@@ -1084,7 +1140,7 @@ __global__ void __launch_bounds__(kPruneThreads) tile_prune_kernel(
         uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ long_list, uint32_t* __restrict__ misc,
         const uint32_t* __restrict__ rmq, const uint4* __restrict__ kslot, const uint32_t* __restrict__ kill,
         uint32_t n_nodes, int keep_all, uint32_t* __restrict__ tstat) {
-    __shared__ uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
+    __shared__ __align__(16) uint32_t a[kPruneLdsCap], b[kPruneLdsCap], tab[2 * kPruneLdsCap];
     const int w = int(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));   // wave-uniform
     // the wave's tile, if its list is short (its scratch: 64 words of a, 128 of tab)
     const int mine = int(blockIdx.x) * kPruneTiles + w;
