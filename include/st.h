@@ -59,6 +59,10 @@ enum {
     ST_CYLINDER = 4, /* capped cylinder: p[0..2] centre, p[3] radius > 0,
                         p[4] half height > 0, p[5..8] rotation quaternion;
                         its axis is the local y axis */
+    ST_CONE = 5,     /* capped cone: p[0..2] centre, p[3] bottom radius >= 0
+                        (the disk at local y = -p[4]), p[4] half height > 0,
+                        p[5..8] rotation quaternion, p[9] top radius >= 0 (at
+                        y = +p[4]); p[3] + p[9] > 0; axis the local y axis */
     ST_UNION = 16,   /* sharp union, no parameters */
     ST_INTER = 17,   /* sharp intersection */
     ST_DIFF = 18,    /* sharp difference left \ right */

@@ -28,7 +28,7 @@
 #endif
 
 enum {
-    K_SPHERE = 0, K_BOX = 1, K_CAPSULE = 2, K_TORUS = 3, K_CYLINDER = 4,
+    K_SPHERE = 0, K_BOX = 1, K_CAPSULE = 2, K_TORUS = 3, K_CYLINDER = 4, K_CONE = 5,
     K_UNION = 16, K_INTER = 17, K_DIFF = 18,
     K_SUNION = 19, K_SINTER = 20, K_SDIFF = 21
 };
@@ -46,10 +46,10 @@ typedef struct {
     double ext_lo[3], ext_hi[3];  /* AABB of all primitives (scene extent) */
 } or_scene;
 
-static int is_prim(int k) { return k >= K_SPHERE && k <= K_CYLINDER; }
+static int is_prim(int k) { return k >= K_SPHERE && k <= K_CONE; }
 /* primitives with a rotated local frame: the box (quaternion at p[6..9]),
  * the torus and the cylinder (quaternion at p[5..8]) */
-static int quat_offset(int k) { return k == K_BOX ? 6 : (k == K_TORUS || k == K_CYLINDER) ? 5 : -1; }
+static int quat_offset(int k) { return k == K_BOX ? 6 : (k == K_TORUS || k == K_CYLINDER || k == K_CONE) ? 5 : -1; }
 static int is_op(int k) { return k >= K_UNION && k <= K_SDIFF; }
 static int is_compact(int k) { return k >= K_SUNION && k <= K_SDIFF; }
 
@@ -145,6 +145,36 @@ static dual prim_dual(const or_scene *s, int i, const dual p[3]) {
         dual outside = dsqrt(dadd(dmul(ox, ox), dmul(oy, oy)));
         return dadd(outside, dmin(dmax(wx, wy), dconst(0)));
     }
+    case K_CONE: {
+        /* Capped cone: axis local y, bottom disk radius a[3] at y = -a[4], top
+         * disk radius a[9] at y = +a[4].  In the meridian half-plane (rho, y),
+         * rho = sqrt(lx^2 + lz^2), the solid is the trapezoid bounded by the
+         * two cap segments and the side segment S from (a[3], -a[4]) to
+         * (a[9], a[4]).  Distance to the surface: the smaller of the distance
+         * to the cap segment on the point's side of y = 0 and the distance to
+         * S (closest point at the clamped projection parameter); negative
+         * inside, which is |y| < a[4] and the point left of S. */
+        const double *R = s->rot + 9 * i;
+        dual d[3]; for (int j = 0; j < 3; j++) d[j] = dsub(p[j], dconst(a[j]));
+        dual l[3];
+        for (int j = 0; j < 3; j++)
+            l[j] = dadd(dadd(dscale(d[0], R[0 * 3 + j]), dscale(d[1], R[1 * 3 + j])), dscale(d[2], R[2 * 3 + j]));
+        const double rb = a[3], h = a[4], rt = a[9];
+        dual rho = dsqrt(dadd(dmul(l[0], l[0]), dmul(l[2], l[2])));
+        const double rcap = l[1].v < 0 ? rb : rt;
+        dual cax = dsub(rho, dmin(rho, dconst(rcap)));
+        dual cay = dsub(dabs(l[1]), dconst(h));
+        const double ex = rt - rb, ey = 2 * h, ee = ex * ex + ey * ey;
+        dual px = dsub(rho, dconst(rb)), py = dadd(l[1], dconst(h));     /* point relative to the bottom end of S */
+        dual tt = dscale(dadd(dscale(px, ex), dscale(py, ey)), 1.0 / ee);
+        tt = dmin(dmax(tt, dconst(0)), dconst(1));
+        dual cbx = dsub(px, dscale(tt, ex)), cby = dsub(py, dscale(tt, ey));
+        dual dcap = dadd(dmul(cax, cax), dmul(cay, cay)), dside = dadd(dmul(cbx, cbx), dmul(cby, cby));
+        dual dist = dsqrt(dmin(dcap, dside));
+        /* left of S: the cross product of S's direction and the point is positive */
+        const int inside = cay.v < 0 && (ex * py.v - ey * px.v) > 0;
+        return inside ? dneg(dist) : dist;
+    }
     }
     return dconst(INFINITY);
 }
@@ -153,6 +183,7 @@ static dual prim_dual(const or_scene *s, int i, const dual p[3]) {
 static void ring_extents(const or_scene *s, int i, double e[3]) {
     const double *a = s->par + 16 * i;
     if (s->kind[i] == K_TORUS) { e[0] = e[2] = a[3] + a[4]; e[1] = a[4]; }
+    else if (s->kind[i] == K_CONE) { e[0] = e[2] = fmax(a[3], a[9]); e[1] = a[4]; }
     else { e[0] = e[2] = a[3]; e[1] = a[4]; }
 }
 
@@ -270,7 +301,8 @@ static void prim_aabb(const or_scene *s, int i, double d, double lo[3], double h
         }
         break;
     case K_TORUS:
-    case K_CYLINDER: {
+    case K_CYLINDER:
+    case K_CONE: {
         const double *R = s->rot + 9 * i;
         double ext[3];
         ring_extents(s, i, ext);
@@ -629,7 +661,8 @@ static int ray_voi(const or_scene *s, int i, const double o[3], const double d[3
         return ray_sphere(o, d, a, a[3] + dd, t0, t1);
     case K_BOX:
     case K_TORUS:
-    case K_CYLINDER: {
+    case K_CYLINDER:
+    case K_CONE: {
         /* the volume of interest of these three is the oriented box of the
          * primitive's local box grown by d */
         const double *R = s->rot + 9 * i;
@@ -742,7 +775,8 @@ int or_in_voi(const or_scene *s, int i, const double x[3]) {
     }
     case K_BOX:
     case K_TORUS:
-    case K_CYLINDER: {
+    case K_CYLINDER:
+    case K_CONE: {
         const double *R = s->rot + 9 * i;
         double ext[3] = {a[3], a[4], a[5]};
         if (s->kind[i] != K_BOX) ring_extents(s, i, ext);

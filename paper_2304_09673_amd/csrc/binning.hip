@@ -49,14 +49,17 @@ __global__ void voi_kernel(const uint32_t* __restrict__ prims, int P, const Node
         float R = q[3] + d;
         v.v[0] = q[0]; v.v[1] = q[1]; v.v[2] = q[2]; v.v[3] = R;
         v.v[4] = q[0]; v.v[5] = q[1]; v.v[6] = q[2]; v.v[7] = R;
-    } else if (kind == ST_BOX || kind == ST_TORUS || kind == ST_CYLINDER) {
+    } else if (kind == ST_BOX || kind == ST_TORUS || kind == ST_CYLINDER || kind == ST_CONE) {
         // oriented box of the local box grown by d (torus: ring radius R,
-        // tube r; cylinder: radius, half height along axis 1)
+        // tube r; cylinder: radius, half height along axis 1; cone: the
+        // larger end radius, half height)
         float e0, e1, e2;
         if (kind == ST_BOX) {
             e0 = q[7] + d; e1 = q[11] + d; e2 = q[15] + d;
         } else if (kind == ST_TORUS) {
             e0 = q[3] + q[7] + d; e1 = q[7] + d; e2 = e0;
+        } else if (kind == ST_CONE) {
+            e0 = fmaxf(q[3], q[11]) + d; e1 = q[7] + d; e2 = e0;
         } else {
             e0 = q[3] + d; e1 = q[7] + d; e2 = e0;
         }

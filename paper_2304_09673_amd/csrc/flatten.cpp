@@ -50,8 +50,17 @@ st_status validate_primitive(const st_node& nd, int i) {
         set_error("primitive " + std::to_string(i) + " has children");
         return ST_E_TREE;
     }
-    int cnt = k == ST_SPHERE ? 4 : k == ST_BOX ? 10 : k == ST_CAPSULE ? 7 : 9;
+    int cnt = k == ST_SPHERE ? 4 : k == ST_BOX ? 10 : k == ST_CAPSULE ? 7 : k == ST_CONE ? 10 : 9;
     if (!finite_params(nd, cnt)) { set_error("non-finite primitive parameter"); return ST_E_INVALID; }
+    if (k == ST_CONE) {
+        if (!(nd.p[3] >= 0 && nd.p[9] >= 0 && nd.p[3] + nd.p[9] > 0 && nd.p[4] > 0)) {
+            set_error("cone radius < 0, both radii 0 or half height <= 0");
+            return ST_E_INVALID;
+        }
+        double qn = 0;
+        for (int j = 5; j < 9; j++) qn += double(nd.p[j]) * nd.p[j];
+        if (!(qn > 1e-20)) { set_error("zero quaternion"); return ST_E_INVALID; }
+    }
     if (k == ST_TORUS || k == ST_CYLINDER) {
         if (!(nd.p[3] > 0 && nd.p[4] > 0)) {
             set_error(k == ST_TORUS ? "torus radius <= 0" : "cylinder radius or half height <= 0");
@@ -106,7 +115,8 @@ void primitive_params(const st_node& nd, double d, NodePar& par, PrimBox& box) {
         break;
     }
     case ST_TORUS:
-    case ST_CYLINDER: {
+    case ST_CYLINDER:
+    case ST_CONE: {
         // local frame of the quaternion; axis 1 is the axis of revolution
         double ax[3][3];
         quat_axes(nd.p + 5, ax);
@@ -115,8 +125,15 @@ void primitive_params(const st_node& nd, double d, NodePar& par, PrimBox& box) {
             for (int c = 0; c < 3; c++) q[4 + 4 * a + c] = float(ax[a][c]);
         q[3] = nd.p[3];
         q[7] = nd.p[4];
-        const double ext[3] = {nd.kind == ST_TORUS ? double(nd.p[3]) + nd.p[4] : double(nd.p[3]), double(nd.p[4]),
-                               nd.kind == ST_TORUS ? double(nd.p[3]) + nd.p[4] : double(nd.p[3])};
+        double r_ext = nd.p[3];   // radial extent
+        if (nd.kind == ST_TORUS) r_ext = double(nd.p[3]) + nd.p[4];
+        if (nd.kind == ST_CONE) {   // top radius, and the inverse length of the side in (rho, y)
+            q[11] = nd.p[9];
+            const double ex = double(nd.p[9]) - nd.p[3], ey = 2.0 * nd.p[4];
+            q[15] = float(1.0 / std::sqrt(ex * ex + ey * ey));
+            r_ext = std::max<double>(nd.p[3], nd.p[9]);
+        }
+        const double ext[3] = {r_ext, double(nd.p[4]), r_ext};
         for (int j = 0; j < 3; j++) {
             double e = 0, ev = 0;
             for (int a = 0; a < 3; a++) {

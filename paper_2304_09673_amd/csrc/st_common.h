@@ -40,10 +40,10 @@ constexpr uint32_t kIgnoreNever = 0u;   // union-like
 constexpr uint32_t kIgnoreLeftAbsent = 2u;   // difference-like
 constexpr uint32_t kIgnoreAny = 3u;     // intersection-like
 
-HD bool is_prim_kind(uint32_t k) { return k <= ST_CYLINDER; }
+HD bool is_prim_kind(uint32_t k) { return k <= ST_CONE; }
 // node class of the evaluation counters: sphere, primitive in a rotated box
-// frame (box, torus, cylinder), capsule, operator
-HD uint32_t node_class(uint32_t k) { return k == ST_SPHERE ? 0u : k == ST_CAPSULE ? 2u : k <= ST_CYLINDER ? 1u : 3u; }
+// frame (box, torus, cylinder, cone), capsule, operator
+HD uint32_t node_class(uint32_t k) { return k == ST_SPHERE ? 0u : k == ST_CAPSULE ? 2u : k <= ST_CONE ? 1u : 3u; }
 // counts[node_class(k)] += 1 with constant indices only (a run-time index
 // into a small per-lane array would place it in scratch memory)
 HD void count_class(uint32_t (&counts)[4], uint32_t k) {

@@ -191,12 +191,53 @@ __device__ __forceinline__ T prim_cylinder(const cfloat* q, const P3<T>& p) {
     return sqrt_(ox * ox + oy * oy) + fmin_(fmax_(wx, wy), cst(0.f, wx));
 }
 
+// Capped cone, axis local y: radius q[3] at y = -q[7], q[11] at y = +q[7];
+// q[15] = 1 / |(q[11] - q[3], 2 q[7])|.  In the meridian half-plane (rho, y)
+// the solid is a trapezoid.  Inside it the distance is that to the nearer
+// face line (the section through the axis is convex); outside, the smaller
+// of the distances to the cap segment on the point's side and to the side
+// segment, the latter as the distance to the side's line when the foot
+// falls inside the segment, and the former as the distance to the cap's
+// plane above the disk (linear forms whose gradients stay exact at the
+// surface, where a square root of a near-zero or zero square would not).
+template <class T>
+__device__ __forceinline__ T prim_cone(const cfloat* q, const P3<T>& p) {
+    T dx = p.x - q[0], dy = p.y - q[1], dz = p.z - q[2];
+    T lx = dx * q[4] + dy * q[5] + dz * q[6];
+    T ly = dx * q[8] + dy * q[9] + dz * q[10];
+    T lz = dx * q[12] + dy * q[13] + dz * q[14];
+    const float rb = q[3], h = q[7], rt = q[11], il = q[15];
+    const float ex = rt - rb, ey = 2.f * h;
+    T rho = sqrt_(lx * lx + lz * lz);
+    T px = rho - rb, py = ly + h;        // relative to the side's bottom end
+    T sd = (px * ey - py * ex) * il;     // signed distance to the side's line, > 0 outside
+    T cy = fabs_(ly) - h;                // signed distance to the nearer cap's plane
+    if (val(sd) < 0.f && val(cy) < 0.f) return fmax_(sd, cy);
+    const float rcap = val(ly) < 0.f ? rb : rt;
+    // the cap segment: its plane when the point is above the disk (a hit
+    // point can lie exactly on that plane, where the square root of 0 would
+    // give a zero gradient), else its rim
+    T cx = relu_(rho - rcap);
+    T dcap = val(cx) > 0.f ? sqrt_(cx * cx + cy * cy) : fabs_(cy);
+    T t = (px * ex + py * ey) * (il * il);   // foot on the side, 0 at the bottom end, 1 at the top
+    T dside;
+    if (val(t) > 0.f && val(t) < 1.f) {
+        dside = fabs_(sd);
+    } else {
+        const float te = val(t) <= 0.f ? 0.f : 1.f;
+        T bx = px - te * ex, by = py - te * ey;
+        dside = sqrt_(bx * bx + by * by);
+    }
+    return fmin_(dcap, dside);
+}
+
 template <class T>
 __device__ __forceinline__ T prim_eval(uint32_t kind, const cfloat* q, const P3<T>& p) {
     if (kind == ST_SPHERE) return prim_sphere(q, p);
     if (kind == ST_BOX) return prim_box(q, p);
     if (kind == ST_CAPSULE) return prim_capsule(q, p);
     if (kind == ST_TORUS) return prim_torus(q, p);
+    if (kind == ST_CONE) return prim_cone(q, p);
     return prim_cylinder(q, p);
 }
 

@@ -232,7 +232,7 @@ __device__ __forceinline__ T eval_view(const uint32_t* view, int len_in, const N
             // operands pending above it, at indices 1..D; with KS >= D (KS is
             // at least the tree depth) only index KS wraps, onto that dead
             // slot 0.  An unconditional push is one indexed register move.
-            if (kind <= ST_CYLINDER) {
+            if (kind <= ST_CONE) {
                 stk[sp & (KS - 1)] = acc;
                 sp++;
                 acc = prim_eval<T>(kind, q, p);
@@ -272,7 +272,7 @@ __device__ __forceinline__ float eval_view_seg(const uint32_t* view, int len_in,
             uint32_t kind = ventry_kind(e);
             const cfloat* q = (const cfloat*)(par[min(ventry_node(e), n_nodes - 1u)].v);
             // push as in eval_view (slot 0 is the dead bottom value)
-            if (kind <= ST_CYLINDER) {
+            if (kind <= ST_CONE) {
                 stk[sp & (KS - 1)] = acc;
                 stl[sp & (KS - 1)] = lam;
                 sp++;

@@ -20,6 +20,8 @@ Scene arrays (one row per blobtree node, any node order, ``root`` given):
               the ring lies in the local x-z plane around the local y axis
   - CYLINDER: c(3), radius, half height, unit quaternion; capped, its axis is
               the local y axis
+  - CONE    : c(3), bottom radius, half height, unit quaternion, top radius;
+              capped, its axis is the local y axis, the bottom disk at -h
   - UNION / INTER / DIFF (sharp CSG): no parameters
   - SUNION / SINTER / SDIFF (compact smooth CSG): k, d_o (d_o <= 0 asks the
     consumer to derive d_o from k)
@@ -34,14 +36,14 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SPHERE, BOX, CAPSULE, TORUS, CYLINDER = 0, 1, 2, 3, 4
+SPHERE, BOX, CAPSULE, TORUS, CYLINDER, CONE = 0, 1, 2, 3, 4, 5
 UNION, INTER, DIFF = 16, 17, 18
 SUNION, SINTER, SDIFF = 19, 20, 21
 
 # the primitive types of the configured workloads
 PRIMITIVE_KINDS = (SPHERE, BOX, CAPSULE)
 # every primitive type the library takes
-EXTENDED_KINDS = (SPHERE, BOX, CAPSULE, TORUS, CYLINDER)
+EXTENDED_KINDS = (SPHERE, BOX, CAPSULE, TORUS, CYLINDER, CONE)
 OPERATOR_KINDS = (UNION, INTER, DIFF, SUNION, SINTER, SDIFF)
 
 
@@ -142,6 +144,12 @@ def _primitive(rng, b: _Builder, centre, s, kinds=PRIMITIVE_KINDS):
         h = s * rng.uniform(0.4, 1.0)
         q = _unit_quaternion(rng)
         return b.add(CYLINDER, p=(*c, rad, h, *q))
+    if t == CONE:
+        rb = s * rng.uniform(0.3, 1.0)
+        rt = s * rng.uniform(0.0, 0.8)   # 0 to 0.8 s: pointed to nearly cylindrical
+        h = s * rng.uniform(0.4, 1.0)
+        q = _unit_quaternion(rng)
+        return b.add(CONE, p=(*c, rb, h, *q, rt))
     u = _unit_vector(rng)
     a, e = c - 0.5 * s * u, c + 0.5 * s * u
     return b.add(CAPSULE, p=(*a, *e, 0.5 * s))

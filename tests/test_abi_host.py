@@ -484,3 +484,22 @@ def test_train_step_model_refuses_bad_arguments():
         r = L.st_train_step_model(a["x"], a["t"], a["n"], a["epochs"], a["batch"], a["lr"], a["over"], 0,
                                   a["w"], a["norm"], None, None)
         assert r == st.ST_E_INVALID, bad
+
+
+@pytest.mark.parametrize("col,value", [(3, -0.1), (9, -0.1), ("both", 0.0), (4, 0.0), (9, float("nan")), ("quat", 0.0)])
+def test_flatten_rejects_bad_cone_parameters(col, value):
+    """Cone radii must be >= 0 and not both 0, the half height > 0, every
+    parameter finite, the quaternion non-zero; a valid one flattens."""
+    sc = sg.tree_from_shape((0, 0), [sg.SUNION], kinds=(sg.CONE,))
+    st.prune_tree(sc.kind, sc.left, sc.right, sc.params, sc.root, [])
+    p = sc.params.copy()
+    leaf = sc.left[sc.root]
+    if col == "quat":
+        p[leaf, 5:9] = 0.0
+    elif col == "both":
+        p[leaf, 3] = p[leaf, 9] = 0.0
+    else:
+        p[leaf, col] = value
+    with pytest.raises(st.StError) as e:
+        st.prune_tree(sc.kind, sc.left, sc.right, p, sc.root, [])
+    assert e.value.code == st.ST_E_INVALID

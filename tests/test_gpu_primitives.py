@@ -36,7 +36,7 @@ def test_extended_field_matches_oracle(seed):
     assert (np.linalg.norm(g - go, axis=1) < 1e-3).mean() > 0.99
 
 
-@pytest.mark.parametrize("kind", [sg.TORUS, sg.CYLINDER])
+@pytest.mark.parametrize("kind", [sg.TORUS, sg.CYLINDER, sg.CONE])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_single_primitive_image(kind, seed):
     sc = sg.single_primitive(kind, seed=seed, width=128, height=128)
@@ -61,18 +61,18 @@ def _surface_kinds(sc, d, n_samples=300):
         x = eye + float(d[jj[q], ii[q]]) * oracle.pixel_ray(sc.camera, ii[q] + 0.5, jj[q] + 0.5)
         vals = [abs(osc.prim(i, x)) for i in prims]
         kinds.append(int(sc.kind[prims[int(np.argmin(vals))]]))
-    return np.bincount(kinds, minlength=5)
+    return np.bincount(kinds, minlength=6)
 
 
-# a seed of the five-type generator whose view shows a surface (seed 0's tree
+# a seed of the six-type generator whose view shows a surface (seed 0's tree
 # has none in view: its image is empty for the oracle too)
 SEED_IMAGE = 1
 
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
 def test_extended_scene_full_image(tile):
-    """Five primitive types, mixed compact operators, 256x256, every tile size;
-    tori and cylinders form part of the visible surface."""
+    """Six primitive types, mixed compact operators, 256x256, every tile size;
+    tori, cylinders and cones form part of the visible surface."""
     from paper_2304_09673_amd import st
     sc = sg.config2_extended(SEED_IMAGE)
     _, d, n, stats = gpu_render(sc, st.default_tuning(tile=tile))
@@ -83,8 +83,8 @@ def test_extended_scene_full_image(tile):
     assert stats["stalled"] == 0 and stats["unconverged"] == 0
     if tile == 16:
         kinds = _surface_kinds(sc, d)
-        print("surface kinds (sphere, box, capsule, torus, cylinder):", kinds.tolist(), flush=True)
-        assert kinds[sg.TORUS] > 0 and kinds[sg.CYLINDER] > 0
+        print("surface kinds (sphere, box, capsule, torus, cylinder, cone):", kinds.tolist(), flush=True)
+        assert kinds[sg.TORUS] > 0 and kinds[sg.CYLINDER] > 0 and kinds[sg.CONE] > 0
 
 
 def test_extended_scene_segment_and_ablation():

@@ -325,14 +325,25 @@ def test_primitive_is_a_distance(kind):
 
 
 def _surface_samples(kind, p, n=200):
-    """Points on the surface of a torus or capped cylinder from its
-    parametrisation (local frame, axis of revolution y), in world space."""
+    """Points on the surface of a torus, capped cylinder or capped cone from
+    its parametrisation (local frame, axis of revolution y), in world space."""
     th = np.linspace(0, 2 * np.pi, 4 * n, endpoint=False)
     if kind == sg.TORUS:
         ph = np.linspace(0, 2 * np.pi, n, endpoint=False)
         T, P = np.meshgrid(th, ph)
         ring = p[3] + p[4] * np.cos(P)
         loc = np.stack([ring * np.cos(T), p[4] * np.sin(P), ring * np.sin(T)], -1).reshape(-1, 3)
+    elif kind == sg.CONE:
+        # side: radius linear in y from p[3] at -p[4] to p[9] at +p[4]; caps: disks
+        ys = np.linspace(-p[4], p[4], n)
+        T, Y = np.meshgrid(th, ys)
+        R = p[3] + (p[9] - p[3]) * (Y + p[4]) / (2 * p[4])
+        side = np.stack([R * np.cos(T), Y, R * np.sin(T)], -1).reshape(-1, 3)
+        caps = []
+        for y, r in ((-p[4], p[3]), (p[4], p[9])):
+            T2, RR = np.meshgrid(th, np.linspace(0, r, n // 2))
+            caps.append(np.stack([RR * np.cos(T2), np.full_like(RR, y), RR * np.sin(T2)], -1).reshape(-1, 3))
+        loc = np.concatenate([side] + caps)
     else:
         ys = np.linspace(-p[4], p[4], n)
         T, Y = np.meshgrid(th, ys)
@@ -345,7 +356,7 @@ def _surface_samples(kind, p, n=200):
     return loc @ _quat_rot(p[5:9]).T + p[:3]
 
 
-@pytest.mark.parametrize("kind", [sg.TORUS, sg.CYLINDER])
+@pytest.mark.parametrize("kind", [sg.TORUS, sg.CYLINDER, sg.CONE])
 def test_torus_and_cylinder_values_are_distances_to_their_surface(kind):
     """|f(x)| equals the distance from x to a dense sampling of the surface
     (parametrisation, no distance formula), within the sampling spacing, and
@@ -362,6 +373,8 @@ def test_torus_and_cylinder_values_are_distances_to_their_surface(kind):
     rad = np.hypot(loc[:, 0], loc[:, 2])
     if kind == sg.TORUS:
         inside = (rad - p[3]) ** 2 + loc[:, 1] ** 2 < p[4] ** 2
+    elif kind == sg.CONE:
+        inside = (rad < p[3] + (p[9] - p[3]) * (loc[:, 1] + p[4]) / (2 * p[4])) & (np.abs(loc[:, 1]) < p[4])
     else:
         inside = (rad < p[3]) & (np.abs(loc[:, 1]) < p[4])
     for x, v, ins in zip(pts, f, inside):
@@ -463,8 +476,9 @@ def _voi_member(sc, i, d, x):
         return np.linalg.norm(x - p[:3]) <= p[3] + d
     if k == sg.BOX:
         return np.all(np.abs(_quat_rot(p[6:10]).T @ (x - p[:3])) <= p[3:6] + d)
-    if k in (sg.TORUS, sg.CYLINDER):
-        ext = np.array([p[3] + p[4], p[4], p[3] + p[4]]) if k == sg.TORUS else np.array([p[3], p[4], p[3]])
+    if k in (sg.TORUS, sg.CYLINDER, sg.CONE):
+        r = p[3] + p[4] if k == sg.TORUS else max(p[3], p[9]) if k == sg.CONE else p[3]
+        ext = np.array([r, p[4], r])
         return np.all(np.abs(_quat_rot(p[5:9]).T @ (x - p[:3])) <= ext + d)
     a, b = p[:3], p[3:6]
     s = np.clip((x - a) @ (b - a) / ((b - a) @ (b - a)), 0, 1)
@@ -762,3 +776,68 @@ def test_scene_extent_of_a_lone_rotated_box():
     p[0, :10] = (0, 0, 0, 0.5, 0.1, 0.1, c8, 0, 0, s8)
     o = oracle.OracleScene(kind=kind, left=np.array([-1], np.int32), right=np.array([-1], np.int32), params=p, root=0)
     assert o.extent == pytest.approx(0.6 * math.sqrt(2), abs=2e-6)
+
+
+def _one_cone(rb, rt, h, c=(0.1, -0.2, 0.05), q=(0.9, 0.3, -0.2, 0.25)):
+    """A scene of one capped cone with the given radii and half height."""
+    b = sg._Builder()
+    qq = np.asarray(q, dtype=np.float64)
+    qq = qq / np.linalg.norm(qq)
+    root = b.add(sg.CONE, p=(*c, rb, h, *qq, rt))
+    return b.finish("one_cone", root, sg.Camera(width=32, height=32), {"config": 0, "seed": 0, "tile": 8})
+
+
+def test_cone_with_equal_radii_is_the_cylinder():
+    """A cone whose two radii are equal is the capped cylinder of that radius
+    (the cylinder's own pins fix that one)."""
+    cone = _one_cone(0.4, 0.4, 0.3)
+    b = sg._Builder()
+    pc = cone.params[cone.root].astype(np.float64)
+    root = b.add(sg.CYLINDER, p=(*pc[:3], pc[3], pc[4], *pc[5:9]))
+    cyl = b.finish("one_cyl", root, sg.Camera(width=32, height=32), {"config": 0, "seed": 0, "tile": 8})
+    rng = np.random.default_rng(3)
+    pts = pc[:3] + rng.uniform(-0.9, 0.9, size=(500, 3))
+    fa = oracle.OracleScene(cone).eval(pts)
+    fb = oracle.OracleScene(cyl).eval(pts)
+    assert np.allclose(fa, fb, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("rb,rt", [(0.5, 0.0), (0.0, 0.4), (0.5, 0.2)])
+def test_cone_closed_forms_on_its_axis(rb, rt):
+    """On the axis: beyond a cap the distance is the height above that cap's
+    plane; inside, minus the smaller of the distance to the nearer cap plane
+    and the perpendicular distance to the side line (for a point on the axis
+    its foot falls on the side segment here)."""
+    sc = _one_cone(rb, rt, 0.3)
+    p = sc.params[sc.root].astype(np.float64)
+    rb, h, rt = p[3], p[4], p[9]   # as stored (float32)
+    R = _quat_rot(p[5:9])
+    axis = R[:, 1]
+    L = np.hypot(rt - rb, 2 * h)
+    for y in (-0.9, -0.5, -0.31, 0.31, 0.5, 0.9, -0.2, -0.05, 0.0, 0.1, 0.25):
+        x = p[:3] + y * axis
+        f = oracle.OracleScene(sc).eval(x[None, :])[0]
+        if abs(y) > h:
+            want = abs(y) - h
+        else:
+            side = abs((0 - rb) * 2 * h - (y + h) * (rt - rb)) / L
+            want = -min(h - abs(y), side)
+        assert abs(f - want) < 1e-12, (y, f, want)
+
+
+def test_cone_gradient_has_unit_norm():
+    """The value is a Euclidean distance: its forward-mode gradient has norm 1
+    away from the medial axis (where it jumps) and equals central differences
+    of the value."""
+    sc = _one_cone(0.45, 0.15, 0.35)
+    o = oracle.OracleScene(sc)
+    p = sc.params[sc.root].astype(np.float64)
+    rng = np.random.default_rng(5)
+    pts = p[:3] + rng.uniform(-0.8, 0.8, size=(200, 3))
+    f, g = o.eval(pts, grad=True)
+    e = 1e-6
+    cd = np.stack([(o.eval(pts + e * u) - o.eval(pts - e * u)) / (2 * e) for u in np.eye(3)], -1)
+    smooth = np.abs(np.linalg.norm(cd, axis=1) - 1) < 1e-4   # off the medial axis
+    assert smooth.sum() >= 190
+    assert np.allclose(np.linalg.norm(g[smooth], axis=1), 1, atol=1e-9)
+    assert np.allclose(g[smooth], cd[smooth], atol=1e-5)
