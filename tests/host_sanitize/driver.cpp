@@ -31,7 +31,7 @@ float unif(float a, float b) { return a + (b - a) * float(rnd() & 0xFFFFFF) / fl
 st_node primitive() {
     st_node nd{};
     nd.left = nd.right = -1;
-    nd.kind = rnd() % 5;
+    nd.kind = rnd() % 6;
     for (int j = 0; j < 3; j++) nd.p[j] = unif(-1.f, 1.f);
     switch (nd.kind) {
     case ST_SPHERE: nd.p[3] = unif(0.05f, 0.4f); break;
@@ -44,11 +44,12 @@ st_node primitive() {
         for (int j = 3; j < 6; j++) nd.p[j] = nd.p[j - 3] + unif(-0.3f, 0.3f);
         nd.p[6] = unif(0.05f, 0.2f);
         break;
-    default:   // torus, cylinder
+    default:   // torus, cylinder, cone (p[9]: the cone's top radius, 0 allowed)
         nd.p[3] = unif(0.05f, 0.3f);
         nd.p[4] = unif(0.02f, 0.2f);
         for (int j = 5; j < 9; j++) nd.p[j] = unif(-1.f, 1.f);
         nd.p[5] += 2.f;
+        if (nd.kind == ST_CONE) nd.p[9] = unif(0.f, 0.3f);
     }
     return nd;
 }
@@ -151,7 +152,7 @@ int main(int argc, char** argv) {
         case 4:   // zero radius / blend radius
             if (b[size_t(victim)].kind == ST_SPHERE) b[size_t(victim)].p[3] = 0.f;
             else if (b[size_t(victim)].kind >= ST_SUNION) b[size_t(victim)].p[0] = 0.f;
-            else if (b[size_t(victim)].kind >= ST_TORUS && b[size_t(victim)].kind <= ST_CYLINDER) b[size_t(victim)].p[4] = -1.f;
+            else if (b[size_t(victim)].kind >= ST_TORUS && b[size_t(victim)].kind <= ST_CONE) b[size_t(victim)].p[4] = -1.f;
             else want = ST_OK;
             if (want != ST_OK) want = ST_E_INVALID;
             break;
