@@ -113,13 +113,14 @@ def test_extended_scene_segment_and_ablation():
 
 
 def test_torus_and_cylinder_edits_equal_reflatten():
-    """st_update_primitives on tori and cylinders (moved, resized, turned):
+    """st_update_primitives on tori, cylinders and cones (moved, resized, turned):
     the image equals that of a scene flattened from the edited tree."""
     import torch
     from paper_2304_09673_amd import st
     sc = sg.config2_extended(6, 160, 160)
     rng = np.random.default_rng(3)
-    ids = np.nonzero(np.isin(sc.kind, [sg.TORUS, sg.CYLINDER]))[0][:24]
+    ids = np.nonzero(np.isin(sc.kind, [sg.TORUS, sg.CYLINDER, sg.CONE]))[0][:24]
+    assert (sc.kind[ids] == sg.CONE).any()
     params = sc.params.copy()
     for i in ids:
         params[i, 0:3] += rng.normal(0, 0.1, 3).astype(np.float32)
